@@ -1,0 +1,124 @@
+"""Plant plausible mistakes in the CPU oracle and check that a pin catches
+each one (the pins would be worthless if a wrong oracle still passed them).
+Every mistake is planted on the CPU, in the oracle module only."""
+import numpy as np
+import pytest
+
+import pins
+from oracle import felbm_oracle as fo
+
+_rhs, _lapC, _lapmu, _forces = fo.rhs, fo.laplacian_C, fo.laplacian_mu, fo.element_forces
+_wall, _collide, _wall_op, _equil = fo.wall_flux, fo.collide, fo.wall_operator, fo.equilibria
+
+
+def rhs_printed_sign(mat, dt, psi_hat, Phi):
+    # the sign printed in eq:galerkin_lbm: -(dt M10 - dt^2 K) Phi
+    out = _rhs(mat, dt, psi_hat, np.zeros_like(Phi))
+    for a in range(fo.Q):
+        out[:, a] += -dt * (mat.M10 @ Phi[:, a]) + dt * dt * (mat.Ka[a] @ Phi[:, a])
+    return out
+
+
+def rhs_no_D(mat, dt, psi_hat, Phi):
+    return np.stack([-dt * (mat.Ca[a] @ psi_hat[:, a]) + dt * (mat.M10 @ Phi[:, a]) + dt * dt * (mat.Ka[a] @ Phi[:, a])
+                     for a in range(fo.Q)], 1)
+
+
+def rhs_K_sign(mat, dt, psi_hat, Phi):
+    return np.stack([-dt * (mat.Ca[a] @ psi_hat[:, a]) - dt * dt * (mat.Da[a] @ psi_hat[:, a])
+                     + dt * (mat.M10 @ Phi[:, a]) - dt * dt * (mat.Ka[a] @ Phi[:, a]) for a in range(fo.Q)], 1)
+
+
+def rhs_C_transposed(mat, dt, psi_hat, Phi):
+    return np.stack([-dt * (mat.Ca[a].T @ psi_hat[:, a]) - dt * dt * (mat.Da[a] @ psi_hat[:, a])
+                     + dt * (mat.M10 @ Phi[:, a]) + dt * dt * (mat.Ka[a] @ Phi[:, a]) for a in range(fo.Q)], 1)
+
+
+def lapC_no_average(geo, C, gradC, bc):
+    # inner element gradient only on every outer edge (no averaging with the neighbour)
+    g2 = gradC.copy()
+    saved = geo.edge_nbr.copy()
+    geo.edge_nbr[:] = np.where(saved >= 0, np.arange(geo.NT)[:, None], saved)
+    try:
+        return _lapC(geo, C, g2, bc)
+    finally:
+        geo.edge_nbr[:] = saved
+
+
+def wall_flux_flipped(C_a, C_b, r_a, r_b, length):
+    return -_wall(C_a, C_b, r_a, r_b, length)
+
+
+def lapC_no_incident_wall_edges(geo, C, gradC, bc):
+    saved, saved_len = geo.wall_edges, geo.wall_len
+    geo.wall_edges, geo.wall_len = saved[:0], saved_len[:0]
+    try:
+        return _lapC(geo, C, gradC, bc)
+    finally:
+        geo.wall_edges, geo.wall_len = saved, saved_len
+
+
+def forces_e_not_e_minus_u(geo, prm, C, rho, u, mu, gradC, gradp, gradrho, lapmu):
+    # Phi_h with e . X instead of (e - u) . X
+    Pg, Ph = _forces(geo, prm, C, rho, u, mu, gradC, gradp, gradrho, lapmu)
+    ub = u[geo.tri].mean(1)
+    Cb, rhob, mub = C[geo.tri].mean(1), rho[geo.tri].mean(1), mu[geo.tri].mean(1)
+    X = gradC - (Cb / (rhob * fo.CS2))[:, None] * (gradp - mub[:, None] * gradC)
+    return Pg, Ph + (ub * X).sum(1)[:, None] * fo.gamma(ub)
+
+
+def forces_no_mobility(geo, prm, C, rho, u, mu, gradC, gradp, gradrho, lapmu):
+    return _forces(geo, prm, C, rho, u, mu, gradC, gradp, gradrho, 0 * lapmu)
+
+
+def lapmu_wall_uses_own_gradient(geo, gradmu):
+    saved_w = geo.edge_is_wall.copy(); saved_n = geo.edge_nbr.copy()
+    geo.edge_is_wall[:] = False
+    geo.edge_nbr[:] = np.where(saved_n >= 0, saved_n, np.arange(geo.NT)[:, None])
+    try:
+        return _lapmu(geo, gradmu)
+    finally:
+        geo.edge_is_wall[:] = saved_w; geo.edge_nbr[:] = saved_n
+
+
+def collide_one_over_tau(psi, psi_eq, tau):
+    return psi - (psi - psi_eq) / tau[:, None]
+
+
+def no_wall_operator(geo, psi):
+    return psi.copy()
+
+
+def equilibria_wrong_weight(C, p, rho, u):
+    g, h = _equil(C, p, rho, u)
+    return g, h * (1.0 + 0.01 * (np.arange(fo.Q) == 5))
+
+
+MUTATIONS = [
+    ("printed M10 sign", "rhs", rhs_printed_sign, lambda: pins.static_balance_drift() > 1e-8),
+    ("dropped D term", "rhs", rhs_no_D, lambda: pins.advection_error() > 0.05),
+    ("K sign", "rhs", rhs_K_sign, lambda: pins.force_source_error() > 1e-5),
+    ("C transposed", "rhs", rhs_C_transposed, lambda: pins.advection_error() > 0.05),
+    ("no gradient averaging", "laplacian_C", lapC_no_average, lambda: pins.laplacian_quadratic_error() > 1e-4),
+    ("wetting flux sign", "wall_flux", wall_flux_flipped, lambda: pins.wall_linear_laplacian_error() > 1e-4),
+    ("wetting flux sign (wedge)", "wall_flux", wall_flux_flipped, lambda: pins.wall_flux_wedge_error(60.0) > 0.5),
+    ("missing incident wall edges", "laplacian_C", lapC_no_incident_wall_edges,
+     lambda: pins.wall_linear_laplacian_error() > 1e-4),
+    ("(e - u) -> e in F_h", "element_forces", forces_e_not_e_minus_u, lambda: pins.force_moments_error() > 1e-8),
+    ("dropped mobility term", "element_forces", forces_no_mobility, lambda: pins.force_moments_error() > 1e-8),
+    ("nonzero wall flux of grad mu", "laplacian_mu", lapmu_wall_uses_own_gradient, lambda: pins.mass_drift() > 1e-10),
+    ("collision rate 1/tau", "collide", collide_one_over_tau,
+     lambda: not (0.98 < pins.shear_wave_viscosity_ratio(n_steps=300) < 1.08)),
+    ("no wall operator", "wall_operator", no_wall_operator, lambda: pins.wall_velocity_after_step() > 1e-6),
+    ("wrong equilibrium weight", "equilibria", equilibria_wrong_weight, lambda: pins.lattice_identities_error() > 1e-6),
+]
+
+
+@pytest.mark.parametrize("name,attr,fn,caught", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pin_catches_planted_mistake(monkeypatch, name, attr, fn, caught):
+    monkeypatch.setattr(fo, attr, fn)
+    assert caught(), f"no pin caught the planted mistake: {name}"
+
+
+def test_unmutated_oracle_passes_the_same_predicates():
+    assert not any(m[3]() for m in MUTATIONS)

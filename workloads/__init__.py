@@ -1,0 +1,5 @@
+"""Seeded synthetic inputs (meshes, initial fields, wetting fields) shared by
+the CPU oracle, the tests and the benchmark.  Geometry and input recipes only:
+no lattice Boltzmann or finite element arithmetic lives here."""
+from .mesh import Mesh, graded_rows, split_grid_mesh, uniform_rows, unwrap_tri_xy  # noqa: F401
+from .configs import Physics, Workload, config, droplet_field, fourier_field, make_physics, wetting_from_angles  # noqa: F401

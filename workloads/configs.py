@@ -1,0 +1,131 @@
+"""The five synthetic droplet-on-wall workloads: mesh, physical constants,
+initial composition field and per-node wetting potential.
+
+Everything here is input data.  Physical constants are given in the form the
+paper states them (surface tension sigma, interface width xi, mobility M,
+densities, kinematic viscosities, time step); the derived free-energy
+constants (kappa, beta, phi_c, relaxation times) are computed by each
+consumer on its own.
+
+Readings for constants the paper leaves open (all documented with the build):
+  * time step: dt = 0.1 on unit-spacing meshes, 0.025 on wall-graded meshes;
+  * liquid viscosity nu_l = dt / 3 (liquid relaxation time 1), and the
+    viscosity ratio is nu_v / nu_l;
+  * mobility M = 0.02 everywhere; the top wall is neutral (theta = 90 deg);
+  * the wetting potential of a wall node is Omega_c = -cos(theta) (Young).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .mesh import Mesh, graded_rows, split_grid_mesh, uniform_rows
+
+
+@dataclass
+class Physics:
+    sigma: float
+    xi: float
+    mobility: float
+    rho_l: float
+    rho_v: float
+    nu_l: float
+    nu_v: float
+    dt: float
+
+
+@dataclass
+class Workload:
+    name: str
+    mesh: Mesh
+    phys: Physics
+    C0: np.ndarray                     # (N,) initial composition
+    omega_c: np.ndarray                # (N,) wetting potential, read at wall nodes only
+    steps: int
+    droplets: list = field(default_factory=list)   # [(xc, yc, R)]
+    extra: dict = field(default_factory=dict)
+
+
+def make_physics(sigma, m_rho, m_nu, dt, xi=4.0, mobility=0.02, rho_l=1.0) -> Physics:
+    nu_l = dt / 3.0
+    return Physics(sigma=sigma, xi=xi, mobility=mobility, rho_l=rho_l, rho_v=rho_l / m_rho,
+                   nu_l=nu_l, nu_v=nu_l * m_nu, dt=dt)
+
+
+def droplet_field(mesh: Mesh, droplets, xi: float) -> np.ndarray:
+    """C = 1/2 + 1/2 tanh(2 (R - |x - x_c|) / xi) around each centre (minimum
+    image in x for periodic meshes); several droplets combine by maximum."""
+    C = np.zeros(mesh.n_nodes)
+    for (xc, yc, R) in droplets:
+        dx = mesh.xy[:, 0] - xc
+        if mesh.period_x > 0:
+            dx -= mesh.period_x * np.round(dx / mesh.period_x)
+        d = np.sqrt(dx * dx + (mesh.xy[:, 1] - yc) ** 2)
+        C = np.maximum(C, 0.5 + 0.5 * np.tanh(2.0 * (R - d) / xi))
+    return C
+
+
+def wetting_from_angles(mesh: Mesh, theta_bottom_deg, theta_top_deg=90.0) -> np.ndarray:
+    """Per-node Omega_c = -cos(theta).  theta_bottom_deg is a scalar or a
+    callable of the node x coordinate; only wall nodes get a nonzero value."""
+    om = np.zeros(mesh.n_nodes)
+    for side, th in ((0, theta_bottom_deg), (1, theta_top_deg)):
+        nodes = mesh.wall_nodes(side)
+        t = th(mesh.xy[nodes, 0]) if callable(th) else np.full(nodes.size, float(th))
+        om[nodes] = -np.cos(np.deg2rad(t))
+    return om
+
+
+def fourier_field(x: np.ndarray, period: float, seed, n_modes: int = 4) -> np.ndarray:
+    """Normalised sum of n_modes random-phase cosines of the given period
+    (mode k has amplitude 1/k); max |f| over x equals 1."""
+    ph = np.random.default_rng(list(np.atleast_1d(seed)) + [3]).uniform(0, 2 * np.pi, n_modes)
+    f = sum(np.cos(2 * np.pi * (k + 1) * x / period + ph[k]) / (k + 1) for k in range(n_modes))
+    return f / np.max(np.abs(f))
+
+
+def config(cfg: int) -> Workload:
+    """Build workload 1..5."""
+    if cfg == 1:
+        mesh = split_grid_mesh(64.0, uniform_rows(32.0, 33), 64, seed=[1])
+        phys = make_physics(sigma=0.01, m_rho=10.0, m_nu=1.0, dt=0.1)
+        drops = [(32.0, 0.0, 12.0)]
+        om = wetting_from_angles(mesh, 90.0)
+        return Workload("droplet-64x32-fp64", mesh, phys, droplet_field(mesh, drops, phys.xi), om, 200, drops)
+    if cfg == 2:
+        mesh = split_grid_mesh(512.0, uniform_rows(256.0, 257), 512, seed=[2])
+        phys = make_physics(sigma=0.005, m_rho=100.0, m_nu=10.0, dt=0.1)
+        drops = [(256.0, 0.0, 64.0)]
+        om = wetting_from_angles(mesh, 60.0)
+        return Workload("droplet-512x256-theta60", mesh, phys, droplet_field(mesh, drops, phys.xi), om, 10000, drops)
+    if cfg == 3:
+        mesh = split_grid_mesh(2048.0, graded_rows(1024.0, 1.1), 2048, seed=[3], rough_amp=4.0,
+                               rough_period=64.0, rough_decay=64.0)
+        phys = make_physics(sigma=0.005, m_rho=1000.0, m_nu=40.0, dt=0.025)
+        L = 2048.0
+        drops = [(L / 6, 0.0, 80.0), (L / 2, 0.0, 80.0), (5 * L / 6, 0.0, 80.0)]
+        th = lambda x: np.where(x < L / 3, 45.0, np.where(x < 2 * L / 3, 90.0, 135.0))
+        om = wetting_from_angles(mesh, th)
+        return Workload("3-droplets-2048x1024-graded-rough", mesh, phys, droplet_field(mesh, drops, phys.xi), om,
+                        2000, drops)
+    if cfg == 4:
+        mesh = split_grid_mesh(256.0, uniform_rows(128.0, 129), 256, seed=[4])
+        phys = make_physics(sigma=0.01, m_rho=10.0, m_nu=1.0, dt=0.1)
+        drops = [(128.0, 0.0, 32.0)]
+        th = lambda x: 90.0 + 40.0 * fourier_field(x, 256.0, [4])
+        om = wetting_from_angles(mesh, th)
+        return Workload("adjoint-256x128", mesh, phys, droplet_field(mesh, drops, phys.xi), om, 500, drops,
+                        extra={"ckpt_every": 50})
+    if cfg == 5:
+        mesh = split_grid_mesh(1024.0, graded_rows(512.0, 1.3), 1024, seed=[5])
+        phys = make_physics(sigma=0.01, m_rho=10.0, m_nu=1.0, dt=0.025)
+        drops = [(512.0, 0.0, 64.0)]
+        th = lambda x: 90.0 + 40.0 * fourier_field(x, 1024.0, [5])
+        om = wetting_from_angles(mesh, th)
+        r = np.random.default_rng([5, 4])
+        shift, scale = r.uniform(-32.0, 32.0), r.uniform(0.9, 1.1)
+        target = droplet_field(mesh, [(512.0 + shift, 0.0, 64.0 * scale)], phys.xi)
+        return Workload("adjoint-1024x512-graded", mesh, phys, droplet_field(mesh, drops, phys.xi), om, 2000, drops,
+                        extra={"ckpt_every": 100, "C_target": target})
+    raise ValueError(f"no workload {cfg}")
