@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Throughput of the FE-LBM time step on one MI355X.
+
+Workload (default): three droplets (R = 80, theta = 45/90/135 deg) on a
+sinusoidally rough wall, 2048 x 1024 domain, wall-graded jittered split-quad
+mesh (2,140,160 nodes, 4,276,224 triangles), density ratio 1000, viscosity
+ratio 40.  A step is one pass of the whole hot path (moments, collision,
+Laplacians, element forces, Galerkin right-hand side, mass-matrix solve, wall
+operator, FP64 reductions) over all nodes; inputs are resident in HBM when the
+timed region starts.
+
+Printed: one JSON line with MNUPS (mesh nodes x steps / s / 1e6, each node
+update advancing all 9 directions of both g and h) for the FP32 precision form
+(FP64 islands for the chemical-potential chain and reductions), the FP64 run of
+the same workload beside it, the roofline entry of the dominant kernel (the
+mass-matrix solve sweep) and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD-published
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for f in ("kernels.hpp", "felbm.hip"):
+        with open(os.path.join(ROOT, "paper_1708_04678_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def make_ctx(felbm, w, precision, sweeps, stream):
+    p = w.phys
+    ctx = felbm.Context(sigma=p.sigma, xi=p.xi, mobility=p.mobility, rho_l=p.rho_l, rho_v=p.rho_v, nu_l=p.nu_l,
+                        nu_v=p.nu_v, dt=p.dt, precision=precision, solver_sweeps=sweeps)
+    ctx.bind_stream(stream)
+    ctx.upload_mesh(w.mesh.xy, w.mesh.tri, w.mesh.wall_edges, w.mesh.period_x)
+    ctx.set_wetting(w.omega_c)
+    xc, yc, R = w.droplets[0]
+    ctx.set_band(xc, yc, R, w.phys.xi)
+    ctx.init(w.C0)
+    return ctx, ctx.diagnostics()
+
+
+def timed_run(torch, ctx, warmup, steps):
+    ctx.step(warmup)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    ctx.step_async(steps)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    ctx.step(0)
+    return ms
+
+
+def kernel_pass(ctx, steps):
+    ctx.kernel_timing(True)
+    ctx.step(steps)
+    stats = {s["name"]: s for s in ctx.kernel_stats()}
+    ctx.kernel_timing(False)
+    return stats
+
+
+def cpu_baseline(cfg, rows):
+    """The FP64 CPU oracle, as it stands, on the bottom `rows` node rows of the
+    same mesh (one step after one warm-up step)."""
+    from oracle import Oracle
+    from workloads import config
+    full_rows = config(cfg).mesh.nrows
+    w = config(cfg, row_limit=rows)
+    o = Oracle(w.mesh, w.phys, w.omega_c)
+    g, h = o.init_state(w.C0)
+    g, h = o.step(g, h)
+    c0, t0 = time.process_time(), time.perf_counter()
+    g, h = o.step(g, h)
+    wall = time.perf_counter() - t0
+    cpu = time.process_time() - c0
+    return {"value": w.mesh.n_nodes / wall / 1e6, "unit": "MNUPS", "cores": max(1, round(cpu / wall)),
+            "kind": "oracle", "seconds": round(wall, 2),
+            "sample": f"1 step (after 1 warm-up step) of the FP64 numpy/scipy oracle on the bottom {rows} of the "
+                      f"{full_rows} node rows of the same mesh ({w.mesh.n_nodes} nodes, same droplets and walls)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--sweeps32", type=int, default=16, help="solver sweeps per step in FP32")
+    ap.add_argument("--sweeps64", type=int, default=32, help="solver sweeps per step in FP64")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=349)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding of this path is "
+              "described in DESIGN.md and not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1708_04678_amd as felbm
+    from workloads import config
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream().cuda_stream
+    log(f"workload {args.config}")
+    w = config(args.config)
+    N, E = w.mesh.n_nodes, w.mesh.n_tris
+
+    log("fp32 context")
+    c32, d0 = make_ctx(felbm, w, "fp32", args.sweeps32, stream)
+    ms32 = timed_run(torch, c32, args.warmup, args.steps)
+    log(f"fp32 {ms32 / args.steps:.3f} ms/step")
+    stats = kernel_pass(c32, args.steps)
+    d32 = c32.diagnostics()
+    info = c32.mesh_info()
+
+    dom = stats["sweep_mid"]
+    avg_ms = dom["total_ms"] / max(dom["launches"], 1)
+    achieved = dom["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "sweep_mid_traffic.json")
+    if os.path.exists(tfile):
+        with open(tfile) as fh:
+            t = json.load(fh)
+        if t.get("kernel_source_sha") == kernel_source_sha() and t.get("workload") == w.name:
+            traffic = t.get("hbm_bytes_per_launch")
+    roofline = {"bound": "hbm", "kernel": "sweep_mid", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "avg_launch_us": round(avg_ms * 1e3, 2), "algorithmic_bytes_per_launch": dom["bytes_per_launch"]}
+    kernels = {k: {"launches": v["launches"], "avg_us": round(v["total_ms"] / max(v["launches"], 1) * 1e3, 2),
+                   "share": round(v["total_ms"] / max(sum(x["total_ms"] for x in stats.values()), 1e-9), 4)}
+               for k, v in stats.items() if v["launches"]}
+
+    out = {
+        "metric": "MNUPS (mesh-node x 9-pop updates/s) FP32 vs FP64 at equal spurious-current error",
+        "value": round(N * args.steps / (ms32 * 1e-3) / 1e6, 2),
+        "unit": "MNUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms32 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "nodes": N, "triangles": E, "mass_offdiag_nnz": info["mass_offdiag_nnz"],
+                   "precision": "fp32 populations/arithmetic, fp64 chemical-potential chain and reductions",
+                   "solver_sweeps": args.sweeps32, "population_updates_per_s": round(18 * N * args.steps / (ms32 * 1e-3)),
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "kernels": kernels,
+    }
+
+    if not args.no_fp64:
+        log("fp64 context")
+        c64, _ = make_ctx(felbm, w, "fp64", args.sweeps64, stream)
+        ms64 = timed_run(torch, c64, args.warmup, args.steps)
+        log(f"fp64 {ms64 / args.steps:.3f} ms/step")
+        c64.step(args.steps)  # same step count as the fp32 context (its kernel pass)
+        d64 = c64.diagnostics()
+        out["fp64"] = {"value": round(N * args.steps / (ms64 * 1e-3) / 1e6, 2), "ms_per_step": round(ms64 / args.steps, 4),
+                       "solver_sweeps": args.sweeps64}
+        out["fp32_vs_fp64"] = {
+            "speedup": round(ms64 / ms32, 3),
+            "step": d32["step"],
+            "max_u_fp32": d32["max_u"], "max_u_fp64": d64["max_u"],
+            "max_u_rel_diff": abs(d32["max_u"] - d64["max_u"]) / max(d64["max_u"], 1e-300),
+            "band_ke_rel_diff": abs(d32["band_ke"] - d64["band_ke"]) / max(d64["band_ke"], 1e-300),
+            "mass_rel_diff": abs(d32["mass"] - d64["mass"]) / d64["mass"],
+        }
+        c64.close()
+    out["mass_drift_fp32"] = abs(d32["mass"] - d0["mass"]) / d0["mass"]
+    c32.close()
+
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline (oracle, bottom {args.cpu_rows} rows)")
+        out["cpu_baseline"] = cpu_baseline(args.config, args.cpu_rows)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

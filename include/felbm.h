@@ -1,0 +1,225 @@
+/*
+ * felbm.h — C ABI of the MI355X (gfx950) finite element lattice Boltzmann
+ * step for two-phase flow with wetting walls (Matin, Misztal,
+ * Hernandez-Garcia, Mathiesen, "Finite Element Lattice Boltzmann Simulations
+ * of Contact Line Dynamics", arXiv:1708.04678).
+ *
+ * One time step (Sec. II.C-D) on a P1 triangle mesh with D2Q9 populations
+ * g (pressure/momentum) and h (composition), 18 values per node:
+ *   moments C, p, u (eq:velocity, eq:pressure) -> element gradients ->
+ *   nodal patch Laplacian of C with the wetting flux (eqn:lapl_int_mp,
+ *   eq. bc2) -> chemical potential (eqn:mp_mu) -> element Laplacian of mu
+ *   -> P0 element forces (eq:G, eq:H, eq:intF) -> BGK collision
+ *   (eqn::collide) -> Galerkin streaming right-hand side (eqn::stream,
+ *   eq:galerkin_lbm) -> consistent-mass solve with the lumped-mass
+ *   preconditioner -> wall operator.
+ *
+ * Conventions for every function below:
+ *   - return value: FELBM_OK (0) or a negative FELBM_E* code; nothing throws
+ *     across the ABI; felbm_last_error() gives a message owned by the
+ *     context, valid until the next call on that context.
+ *   - host arrays are owned by the caller and copied; device memory is owned
+ *     by the library.  Arrays are in the caller's node / triangle order.
+ *   - floating point host arrays are double; integer arrays int32.
+ *   - all validation happens on the host before any device work.
+ *   - one context per host thread; calls on one context are not thread safe.
+ *   - results are deterministic: no atomics, fixed reduction orders.
+ */
+#ifndef FELBM_H
+#define FELBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  FELBM_OK = 0,
+  FELBM_EINVAL = -1,     /* null pointer, bad size or bad parameter            */
+  FELBM_EMESH = -2,      /* index out of range, non-positive unwrapped area,
+                            non-manifold edge, boundary edge that is neither a
+                            wall nor periodic, wall edge not on the boundary   */
+  FELBM_ESTATE = -3,     /* call out of order (e.g. step before init)          */
+  FELBM_ENONFINITE = -4, /* a NaN / Inf appeared in the state                  */
+  FELBM_ESOLVER = -5,    /* solver configuration rejected                      */
+  FELBM_EDEVICE = -6,    /* HIP runtime error                                  */
+  FELBM_ENOMEM = -7      /* device allocation failed                           */
+};
+
+enum { FELBM_FP64 = 0, FELBM_FP32 = 1 };
+
+/* Physical and numerical parameters (Sec. II and II.A).
+ *   sigma, xi      surface tension and interface width; the free energy
+ *                  constants follow from xi = sqrt(8 kappa/beta) and
+ *                  sigma = sqrt(2 kappa beta)/6 (Sec. II, after eqn:mp_mu)
+ *   mobility       M of eqn:mp_che
+ *   rho_l, rho_v   phase densities, rho = C rho_l + (1 - C) rho_v
+ *   nu_l, nu_v     kinematic viscosities; tau = nu / (c_s^2 dt) per phase and
+ *                  1/tau = C/tau_l + (1 - C)/tau_v (Sec. II.A)
+ *   dt             time step
+ *   precision      FELBM_FP64: everything in double.  FELBM_FP32: populations,
+ *                  velocity/pressure fields, forces, streaming and solve in
+ *                  float; the chain C -> lap C -> mu -> grad mu -> lap mu and
+ *                  all global reductions in double.
+ *   solver_sweeps  K >= 0: the mass-matrix system M11 x = b is solved by K
+ *                  preconditioned Richardson sweeps from x0 = b/m whose step
+ *                  lengths are the reciprocal Chebyshev roots for the spectrum
+ *                  bounds below, i.e. the degree-K Chebyshev iterate with the
+ *                  lumped-mass preconditioner (error <= 2/T_K((b+a)/(b-a))).
+ *                  K = 0 is the lumped-mass solve.  Every sweep preserves
+ *                  sum_i m_i x_i = sum_i b_i, hence mass.
+ *   lambda_min/max bounds of the spectrum of diag(m)^-1 M11; 0/0 selects the
+ *                  bounds [1/4, 1] that hold for every P1 triangle mesh.     */
+typedef struct {
+  double sigma, xi, mobility;
+  double rho_l, rho_v, nu_l, nu_v, dt;
+  int32_t precision;
+  int32_t solver_sweeps;
+  double lambda_min, lambda_max;
+} felbm_params;
+
+/* Global FP64 reductions of the current state (Sec. III).
+ *   mass     sum_i m_i C_i with m the lumped mass vector (int C dx)
+ *   mean_ke  <T> = 0.5 sum_i rho_i |u_i|^2 / N (caption of the mobility figure)
+ *   max_u    max_i |u_i|
+ *   band_ke  mean of rho |u|^2 over nodes in the band set by felbm_set_band
+ *            (the <rho u.u> of the parasitic-current table); 0 if unset
+ *   band_nodes number of nodes in that band
+ *   nonfinite 1 if any population is NaN/Inf                              */
+typedef struct {
+  int64_t step;
+  double mass, mean_ke, max_u, band_ke;
+  int64_t band_nodes;
+  int32_t nonfinite;
+  int32_t pad_;
+} felbm_diag;
+
+/* Fields for felbm_read.  Nodal fields have N values, element fields E. */
+enum {
+  FELBM_FIELD_C = 0,     /* composition sum_a h_a                       (N) */
+  FELBM_FIELD_RHO = 1,   /* density                                      (N) */
+  FELBM_FIELD_P = 2,     /* pressure sum_a g_a                           (N) */
+  FELBM_FIELD_UX = 3,    /* velocity (1/(c_s^2 rho)) sum_a e_a g_a       (N) */
+  FELBM_FIELD_UY = 4,
+  FELBM_FIELD_MU = 5,    /* chemical potential                           (N) */
+  FELBM_FIELD_LAPC = 6,  /* nodal patch Laplacian of C                   (N) */
+  FELBM_FIELD_LAPMU = 7  /* element Laplacian of mu                      (E) */
+};
+
+typedef struct felbm_ctx felbm_ctx;
+
+/* Create a context on the current HIP device.  params is copied.
+ * Errors: EINVAL (null, non-positive dt/xi/densities/viscosities, negative
+ * sigma or mobility, bad precision, solver_sweeps < 0 or > 256,
+ * 0 < lambda_min < lambda_max violated), EDEVICE, ENOMEM. */
+int felbm_create(const felbm_params* params, felbm_ctx** out);
+
+/* Message for the last failed call on ctx (or on creation when ctx is NULL). */
+const char* felbm_last_error(const felbm_ctx* ctx);
+
+/* Upload an unstructured P1 triangle mesh (Sec. II.C: nodal unknowns,
+ * piecewise-linear shape functions).
+ *   xy         [n_nodes][2] node coordinates
+ *   tri        [n_tris][3] vertex indices, counter-clockwise after the x
+ *              unwrap (minimum image when period_x > 0)
+ *   wall_edge  [n_wall_edges][2] node pairs of solid-wall boundary edges;
+ *              every boundary edge must be listed, and only those
+ *   period_x   > 0: x is periodic with this period (nodes on the seam are
+ *              shared by the elements on both sides); 0: not periodic
+ * Builds element geometry in FP64, element adjacency, the node->element
+ * gather lists and the consistent mass matrix on the host, then copies them
+ * to the device.  May be called once per context.
+ * Errors: EINVAL, EMESH, ESTATE (second call), ENOMEM, EDEVICE. */
+int felbm_upload_mesh(felbm_ctx* ctx, int64_t n_nodes, const double* xy, int64_t n_tris,
+                      const int32_t* tri, int64_t n_wall_edges, const int32_t* wall_edge,
+                      double period_x);
+
+/* Per-node wetting potential Omega_c (Young: cos theta = -Omega_c, Sec. II.B),
+ * [n_nodes], read at wall nodes only; the wall flux uses
+ * phi_c / kappa = Omega_c sqrt(2 kappa beta) / kappa in eq. bc2.
+ * Defaults to 0 (neutral wall).  Errors: EINVAL (null, non-finite, or
+ * nonzero with kappa = 0), ESTATE (no mesh). */
+int felbm_set_wetting(felbm_ctx* ctx, const double* omega_c);
+
+/* Initialise the populations to the equilibria (eqn::g_eq, eqn::f_eq) of
+ * C [n_nodes], u [n_nodes][2] (NULL = 0) and p [n_nodes] (NULL = 0), then
+ * apply the wall operator.  Resets the step counter.
+ * Errors: EINVAL (null C, non-finite value), ESTATE (no mesh). */
+int felbm_init(felbm_ctx* ctx, const double* C, const double* u, const double* p);
+
+/* Advance n_steps >= 0 time steps on the bound stream and wait for them.
+ * Errors: ESTATE (not initialised), ENONFINITE (the per-step FP64 check saw
+ * a NaN/Inf; felbm_last_error names the first such step), EDEVICE. */
+int felbm_step(felbm_ctx* ctx, int64_t n_steps);
+
+/* Same as felbm_step without waiting and without the non-finite check:
+ * work is queued on the bound stream.  For timing loops. */
+int felbm_step_async(felbm_ctx* ctx, int64_t n_steps);
+
+/* Copy a field derived from the current state to out (caller-owned double,
+ * N or E values as listed above).  Errors: EINVAL, ESTATE. */
+int felbm_read(felbm_ctx* ctx, int32_t field, double* out);
+
+/* Copy the current populations to out [18][n_nodes] (g_0..g_8, h_0..h_8) as
+ * double.  Errors: EINVAL, ESTATE. */
+int felbm_read_populations(felbm_ctx* ctx, double* out);
+
+/* Advance one step and copy its intermediates (each may be NULL), all
+ * [18][n_nodes] double: post-collision populations psi_hat (eqn::collide),
+ * the lumped-scaled right-hand side b/m of eq:galerkin_lbm, and the solve's
+ * increment delta with M11 delta = b (before the wall operator). */
+int felbm_step_debug(felbm_ctx* ctx, double* psi_hat, double* rhs_over_m, double* delta);
+
+/* Reduction band for band_ke: nodes with R - w <= |x - (xc, yc)| <= R + w
+ * (minimum image in periodic x).  R <= 0 disables it. */
+int felbm_set_band(felbm_ctx* ctx, double xc, double yc, double R, double w);
+
+/* FP64 reductions of the current state.  Errors: EINVAL, ESTATE. */
+int felbm_diagnostics(felbm_ctx* ctx, felbm_diag* out);
+
+/* Per-step history of the FP64 reductions computed inside the step (mass,
+ * mean KE, max |u| of the state entering each step), most recent last.
+ * Copies min(max_entries, available) records; *n_out receives the count. */
+int felbm_history(felbm_ctx* ctx, felbm_diag* out, int64_t max_entries, int64_t* n_out);
+
+/* Checkpoint of the state: felbm_state_bytes gives the buffer size; save
+ * copies the populations (compute precision, internal layout) and the step
+ * counter to buf; load restores them.  Errors: EINVAL (null or short
+ * buffer, header mismatch), ESTATE. */
+int64_t felbm_state_bytes(const felbm_ctx* ctx);
+int felbm_save_state(felbm_ctx* ctx, void* buf, int64_t bytes);
+int felbm_load_state(felbm_ctx* ctx, const void* buf, int64_t bytes);
+
+/* Run all subsequent device work on this HIP stream (hipStream_t, NULL =
+ * the library's own stream).  The stream is not owned by the library. */
+int felbm_bind_stream(felbm_ctx* ctx, void* hip_stream);
+
+/* Per-kernel timing with HIP events recorded around every launch of the
+ * step's kernels (for measurement; adds event records to the stream). */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double total_ms;
+  double bytes_per_launch;   /* algorithmic bytes moved by one launch */
+} felbm_kstat;
+int felbm_kernel_timing(felbm_ctx* ctx, int32_t enable);
+int felbm_kernel_stats(felbm_ctx* ctx, felbm_kstat* out, int32_t max_entries, int32_t* n_out);
+
+/* Sizes of the uploaded mesh and of the consistent mass matrix. */
+int felbm_mesh_info(const felbm_ctx* ctx, int64_t* n_nodes, int64_t* n_tris, int64_t* n_wall_edges,
+                    int64_t* mass_matrix_offdiag_nnz);
+
+/* Validate a mesh with the same host checks as felbm_upload_mesh, without a
+ * context or a device.  msg (may be NULL) receives a message of at most
+ * msg_len bytes including the terminator.  Returns FELBM_OK, EINVAL or EMESH. */
+int felbm_validate_mesh(int64_t n_nodes, const double* xy, int64_t n_tris, const int32_t* tri,
+                        int64_t n_wall_edges, const int32_t* wall_edge, double period_x, char* msg,
+                        int32_t msg_len);
+
+void felbm_destroy(felbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FELBM_H */

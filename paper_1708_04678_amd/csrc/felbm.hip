@@ -1,0 +1,813 @@
+// C ABI of the gfx950 FE-LBM step (declared in include/felbm.h): context and
+// device memory management, mesh upload, the per-step launch sequence and
+// the read-back / checkpoint / timing entry points.
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "felbm.h"
+#include "kernels.hpp"
+#include "mesh_prep.hpp"
+
+using namespace felbm;
+
+namespace {
+
+enum KernelId {
+  K_MOMENTS = 0, K_REDUCE, K_GRAD, K_LAPC, K_GRADMU, K_LAPMU, K_RHS, K_SWEEP_FIRST, K_SWEEP_MID, K_SWEEP_LAST,
+  K_COUNT
+};
+const char* const kKernelNames[K_COUNT] = {"moments_collide", "reduce_final", "elem_grad", "lapC_mu", "elem_gradmu",
+                                           "elem_lapmu", "rhs_gather", "sweep_first", "sweep_mid", "sweep_last"};
+
+struct KStat {
+  int64_t launches = 0;
+  double total_ms = 0.0;
+  double bytes = 0.0;
+};
+
+struct PendingTiming {
+  int kid;
+  hipEvent_t start, stop;
+};
+
+constexpr uint32_t kStateMagic = 0x4645424du;  // "FEBM"
+
+struct StateHeader {
+  uint32_t magic;
+  int32_t precision;
+  int64_t n_nodes;
+  int64_t step;
+  int64_t payload_bytes;
+};
+
+inline int grid_for(int64_t n) {
+  int64_t b = (n + BLOCK - 1) / BLOCK;
+  b = (b + 7) / 8 * 8;  // multiple of 8 for the XCD remap
+  return (int)std::max<int64_t>(b, 8);
+}
+
+}  // namespace
+
+struct felbm_ctx {
+  felbm_params prm{};
+  StepParams sp{};
+  std::string err;
+  int device = 0;
+  hipStream_t own_stream = nullptr, stream = nullptr;
+  bool has_mesh = false, has_state = false;
+  int64_t N = 0, Np = 0, E = 0, W = 0, offdiag_nnz = 0, sell_entries = 0;
+  size_t rs = 8;
+  int64_t step = 0;
+  Band band{};
+  std::vector<double> cheb_w;  // Richardson step lengths (reciprocal Chebyshev roots), in sweep order
+  // mesh (device)
+  int32_t *tri = nullptr, *enbr = nullptr, *n2e_ptr = nullptr, *n2e = nullptr, *wall_nbr = nullptr;
+  int32_t *sell_ptr = nullptr, *sell_col = nullptr;
+  double *geo = nullptr, *wall_len = nullptr, *bc = nullptr, *mass = nullptr, *xy = nullptr;
+  void *geor = nullptr, *sell_val = nullptr;
+  uint8_t* is_wall = nullptr;
+  // state and work buffers (device)
+  void *pop = nullptr, *f = nullptr, *xa = nullptr, *xb = nullptr;
+  double *Cn = nullptr, *mu = nullptr, *lapC = nullptr, *gC = nullptr, *gmu = nullptr, *lapmu = nullptr;
+  void *pn = nullptr, *uxn = nullptr, *uyn = nullptr, *gp = nullptr;
+  double* partials = nullptr;
+  DiagRecord* hist = nullptr;  // ring of per-step reductions
+  DiagRecord* diag_now = nullptr;
+  int32_t* first_bad = nullptr;
+  int64_t hist_cap = 16384;
+  std::vector<double> host_omega;
+  // timing
+  bool timing = false;
+  KStat kstat[K_COUNT];
+  std::vector<PendingTiming> pending;
+  std::vector<hipEvent_t> event_pool;
+  std::vector<void*> allocations;
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+int fail(felbm_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIP_OK(c, call)                                                                          \
+  do {                                                                                           \
+    hipError_t e_ = (call);                                                                      \
+    if (e_ != hipSuccess)                                                                        \
+      return fail((c), FELBM_EDEVICE, std::string(#call) + " failed: " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T>
+int dalloc(felbm_ctx* c, T** p, size_t count) {
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+  if (e != hipSuccess) return fail(c, FELBM_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+  c->allocations.push_back(q);
+  *p = reinterpret_cast<T*>(q);
+  return FELBM_OK;
+}
+
+int dalloc_bytes(felbm_ctx* c, void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 1));
+  if (e != hipSuccess) return fail(c, FELBM_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  c->allocations.push_back(*p);
+  return FELBM_OK;
+}
+
+template <typename T>
+int upload(felbm_ctx* c, T* dst, const std::vector<T>& src) {
+  HIP_OK(c, hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  return FELBM_OK;
+}
+
+hipEvent_t take_event(felbm_ctx* c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Launch a kernel on the context stream; with timing on, bracket it with
+// events recorded by the command processor at kernel start and end.
+template <typename F, typename... Args>
+int launch(felbm_ctx* c, int kid, F kernel, int grid, Args... args) {
+  if (c->timing) {
+    hipEvent_t s = take_event(c), t = take_event(c);
+    if (!s || !t) return fail(c, FELBM_EDEVICE, "hipEventCreate failed");
+    hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(BLOCK), 0, c->stream, s, t, 0, args...);
+    c->pending.push_back({kid, s, t});
+  } else {
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(BLOCK), 0, c->stream, args...);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, FELBM_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  return FELBM_OK;
+}
+
+int harvest_timing(felbm_ctx* c) {
+  for (auto& p : c->pending) {
+    float ms = 0.f;
+    HIP_OK(c, hipEventSynchronize(p.stop));
+    HIP_OK(c, hipEventElapsedTime(&ms, p.start, p.stop));
+    c->kstat[p.kid].launches += 1;
+    c->kstat[p.kid].total_ms += ms;
+    c->event_pool.push_back(p.start);
+    c->event_pool.push_back(p.stop);
+  }
+  c->pending.clear();
+  return FELBM_OK;
+}
+
+#define TRY(x)                   \
+  do {                           \
+    int r_ = (x);                \
+    if (r_ != FELBM_OK) return r_; \
+  } while (0)
+
+// Algorithmic bytes per launch of each kernel (perfect reuse of gathered data)
+void set_kernel_bytes(felbm_ctx* c) {
+  const double N = (double)c->N, E = (double)c->E, s = (double)c->rs, nnz = (double)c->offdiag_nnz;
+  const double pops = 18.0 * N * s;
+  const double mat = nnz * (4.0 + s) + (double)(c->Np / 64 + 1) * 4.0;
+  c->kstat[K_MOMENTS].bytes = 2 * pops + N * (8 + 3 * s) + N * 8 * 3;        // pop r/w, fields, mass + xy
+  c->kstat[K_REDUCE].bytes = 0;
+  c->kstat[K_GRAD].bytes = E * (12 + 56 + 16 + 2 * s) + N * (8 + s);
+  c->kstat[K_LAPC].bytes = N * (4 + 8 + 8 + 8 + 8 + 8 + 8 * 2 + 4 * 2) + 3 * E * 4 + E * (4 * 3 + 56 + 16);
+  c->kstat[K_GRADMU].bytes = E * (12 + 48 + 16) + N * 8;
+  c->kstat[K_LAPMU].bytes = E * (12 + 48 + 16 + 8);
+  c->kstat[K_RHS].bytes = 2 * pops + N * (4 + 8 + 8 + 2 * s + 8) + 3 * E * 4 + E * (12 + 7 * s + 16 + 2 * s + 8);
+  c->kstat[K_SWEEP_FIRST].bytes = 2 * pops + mat;
+  c->kstat[K_SWEEP_MID].bytes = 3 * pops + mat;
+  c->kstat[K_SWEEP_LAST].bytes = 4 * pops + mat + N;
+}
+
+template <typename real>
+int enqueue_fields(felbm_ctx* c, bool collide, bool record, DiagRecord* rec_target) {
+  const int gN = grid_for(c->N), gE = grid_for(c->E);
+  const int N = (int)c->N, Np = (int)c->Np, E = (int)c->E;
+  real* pop = (real*)c->pop;
+  if (collide)
+    TRY(launch(c, K_MOMENTS, k_moments<real, true>, gN, pop, N, Np, c->sp, c->Cn, (real*)c->pn, (real*)c->uxn,
+               (real*)c->uyn, (const double*)c->mass, (const double*)c->xy, c->band, c->partials));
+  else
+    TRY(launch(c, K_MOMENTS, k_moments<real, false>, gN, pop, N, Np, c->sp, c->Cn, (real*)c->pn, (real*)c->uxn,
+               (real*)c->uyn, (const double*)c->mass, (const double*)c->xy, c->band, c->partials));
+  if (record)
+    TRY(launch(c, K_REDUCE, k_reduce_final, 1, (const double*)c->partials, gN, N, (int64_t)c->step, rec_target,
+               c->first_bad));
+  TRY(launch(c, K_GRAD, k_elem_grad<real>, gE, E, (const int*)c->tri, (const double*)c->geo, (const double*)c->Cn,
+             (const real*)c->pn, c->gC, (real*)c->gp));
+  TRY(launch(c, K_LAPC, k_lapC_mu, gN, N, E, (const int*)c->n2e_ptr, (const int*)c->n2e, (const int*)c->tri,
+             (const int*)c->enbr, (const double*)c->geo, (const double*)c->gC, (const double*)c->Cn,
+             (const double*)c->bc, (const int*)c->wall_nbr, (const double*)c->wall_len, c->sp, c->lapC, c->mu));
+  TRY(launch(c, K_GRADMU, k_elem_gradmu, gE, E, (const int*)c->tri, (const double*)c->geo, (const double*)c->mu,
+             c->gmu));
+  TRY(launch(c, K_LAPMU, k_elem_lapmu, gE, E, (const int*)c->enbr, (const double*)c->geo, (const double*)c->gmu,
+             c->lapmu));
+  return FELBM_OK;
+}
+
+template <typename real>
+int enqueue_step(felbm_ctx* c) {
+  const int gN = grid_for(c->N);
+  const int N = (int)c->N, Np = (int)c->Np, E = (int)c->E;
+  TRY(enqueue_fields<real>(c, true, true, c->hist + (c->step % c->hist_cap)));
+  real* pop = (real*)c->pop;
+  real* f = (real*)c->f;
+  TRY(launch(c, K_RHS, k_rhs<real>, gN, N, Np, E, (const int*)c->n2e_ptr, (const int*)c->n2e, (const int*)c->tri,
+             (const real*)c->geor, (const double*)c->gC, (const real*)c->gp, (const double*)c->lapmu,
+             (const double*)c->Cn, (const real*)c->uxn, (const real*)c->uyn, (const double*)c->mu, (const real*)pop,
+             (const double*)c->mass, c->sp, f));
+  const int K = c->prm.solver_sweeps;
+  const int* sp = c->sell_ptr;
+  const int* sc = c->sell_col;
+  const real* sv = (const real*)c->sell_val;
+  real *xa = (real*)c->xa, *xb = (real*)c->xb;
+  const uint8_t* wall = c->is_wall;
+  if (K == 0) {
+    TRY(launch(c, K_SWEEP_LAST, k_sweep<real, 4>, gN, N, Np, sp, sc, sv, (const real*)f, (const real*)nullptr,
+               (real*)nullptr, pop, wall, (real)0));
+  } else if (K == 1) {
+    TRY(launch(c, K_SWEEP_LAST, k_sweep<real, 3>, gN, N, Np, sp, sc, sv, (const real*)f, (const real*)nullptr,
+               (real*)nullptr, pop, wall, (real)c->cheb_w[0]));
+  } else {
+    TRY(launch(c, K_SWEEP_FIRST, k_sweep<real, 0>, gN, N, Np, sp, sc, sv, (const real*)f, (const real*)nullptr, xa,
+               pop, wall, (real)c->cheb_w[0]));
+    real *xin = xa, *xout = xb;
+    for (int j = 1; j < K - 1; ++j) {
+      TRY(launch(c, K_SWEEP_MID, k_sweep<real, 1>, gN, N, Np, sp, sc, sv, (const real*)f, (const real*)xin, xout, pop,
+                 wall, (real)c->cheb_w[j]));
+      std::swap(xin, xout);
+    }
+    TRY(launch(c, K_SWEEP_LAST, k_sweep<real, 2>, gN, N, Np, sp, sc, sv, (const real*)f, (const real*)xin,
+               (real*)nullptr, pop, wall, (real)c->cheb_w[K - 1]));
+  }
+  c->step += 1;
+  return FELBM_OK;
+}
+
+int enqueue_steps(felbm_ctx* c, int64_t n) {
+  for (int64_t s = 0; s < n; ++s) {
+    if (c->prm.precision == FELBM_FP64)
+      TRY(enqueue_step<double>(c));
+    else
+      TRY(enqueue_step<float>(c));
+  }
+  return FELBM_OK;
+}
+
+int enqueue_fields_any(felbm_ctx* c, bool collide, bool record, DiagRecord* target) {
+  return c->prm.precision == FELBM_FP64 ? enqueue_fields<double>(c, collide, record, target)
+                                        : enqueue_fields<float>(c, collide, record, target);
+}
+
+int to_double(felbm_ctx* c, const void* src, double* dst_dev, int64_t n) {
+  const int g = (int)((n + BLOCK - 1) / BLOCK);
+  if (c->prm.precision == FELBM_FP64)
+    HIP_OK(c, hipMemcpyAsync(dst_dev, src, n * 8, hipMemcpyDeviceToDevice, c->stream));
+  else
+    hipLaunchKernelGGL(k_to_double<float>, dim3(g), dim3(BLOCK), 0, c->stream, (int)n, (const float*)src, dst_dev);
+  HIP_OK(c, hipGetLastError());
+  return FELBM_OK;
+}
+
+// Copy a [18][Np] device population array to a host [18][N] double array.
+int copy_pops_out(felbm_ctx* c, const void* dev, double* out) {
+  double* tmp = nullptr;
+  HIP_OK(c, hipMallocAsync((void**)&tmp, 18 * c->Np * sizeof(double), c->stream));
+  int r = to_double(c, dev, tmp, 18 * c->Np);
+  if (r == FELBM_OK) {
+    hipError_t e = hipMemcpy2DAsync(out, c->N * sizeof(double), tmp, c->Np * sizeof(double), c->N * sizeof(double), 18,
+                                    hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) r = fail(c, FELBM_EDEVICE, std::string("population copy failed: ") + hipGetErrorString(e));
+  }
+  hipFreeAsync(tmp, c->stream);
+  hipStreamSynchronize(c->stream);
+  return r;
+}
+
+std::vector<double> chebyshev_steps(int K, double lo, double hi) {
+  // roots of T_K mapped to [lo, hi], taken alternately from the top and the
+  // bottom of the spectrum so that partial products stay bounded
+  std::vector<double> lam(K), out;
+  for (int i = 0; i < K; ++i) lam[i] = 0.5 * (hi + lo) + 0.5 * (hi - lo) * std::cos((2.0 * i + 1.0) * M_PI / (2.0 * K));
+  int i = 0, j = K - 1;
+  while (i <= j) {
+    out.push_back(1.0 / lam[i]);
+    if (i != j) out.push_back(1.0 / lam[j]);
+    ++i;
+    --j;
+  }
+  return out;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* felbm_last_error(const felbm_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+int felbm_create(const felbm_params* p, felbm_ctx** out) {
+  g_create_error.clear();
+  if (!p || !out) {
+    g_create_error = "create: null argument";
+    return FELBM_EINVAL;
+  }
+  *out = nullptr;
+  auto bad = [](double v) { return !std::isfinite(v); };
+  if (bad(p->sigma) || bad(p->xi) || bad(p->mobility) || bad(p->rho_l) || bad(p->rho_v) || bad(p->nu_l) ||
+      bad(p->nu_v) || bad(p->dt) || p->xi <= 0 || p->sigma < 0 || p->mobility < 0 || p->rho_l <= 0 || p->rho_v <= 0 ||
+      p->nu_l <= 0 || p->nu_v <= 0 || p->dt <= 0) {
+    g_create_error = "create: parameters must be finite with xi, densities, viscosities, dt > 0 and sigma, mobility >= 0";
+    return FELBM_EINVAL;
+  }
+  if (p->precision != FELBM_FP64 && p->precision != FELBM_FP32) {
+    g_create_error = "create: precision must be FELBM_FP64 or FELBM_FP32";
+    return FELBM_EINVAL;
+  }
+  if (p->solver_sweeps < 0 || p->solver_sweeps > 256) {
+    g_create_error = "create: solver_sweeps must be in [0, 256]";
+    return FELBM_EINVAL;
+  }
+  double lo = p->lambda_min, hi = p->lambda_max;
+  if (lo == 0.0 && hi == 0.0) {
+    lo = 0.25;
+    hi = 1.0;
+  }
+  if (!(lo > 0.0 && hi > lo) || bad(lo) || bad(hi)) {
+    g_create_error = "create: need 0 < lambda_min < lambda_max";
+    return FELBM_EINVAL;
+  }
+  felbm_ctx* c = new (std::nothrow) felbm_ctx();
+  if (!c) {
+    g_create_error = "create: out of host memory";
+    return FELBM_ENOMEM;
+  }
+  c->prm = *p;
+  c->prm.lambda_min = lo;
+  c->prm.lambda_max = hi;
+  c->rs = p->precision == FELBM_FP64 ? 8 : 4;
+  const double kappa = 1.5 * p->sigma * p->xi, beta = 12.0 * p->sigma / p->xi;  // xi = sqrt(8k/b), sigma = sqrt(2kb)/6
+  c->sp = StepParams{kappa, beta, p->mobility, p->rho_l, p->rho_v, CS2 * p->dt / p->nu_l, CS2 * p->dt / p->nu_v, p->dt};
+  c->cheb_w = chebyshev_steps(p->solver_sweeps, lo, hi);
+  if (hipGetDevice(&c->device) != hipSuccess || hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess) {
+    g_create_error = "create: no usable HIP device";
+    delete c;
+    return FELBM_EDEVICE;
+  }
+  c->stream = c->own_stream;
+  *out = c;
+  return FELBM_OK;
+}
+
+int felbm_upload_mesh(felbm_ctx* c, int64_t n_nodes, const double* xy, int64_t n_tris, const int32_t* tri,
+                      int64_t n_wall_edges, const int32_t* wall_edge, double period_x) {
+  if (!c) return FELBM_EINVAL;
+  if (c->has_mesh) return fail(c, FELBM_ESTATE, "upload_mesh: a mesh was already uploaded to this context");
+  MeshPrep m;
+  int r = prepare_mesh(n_nodes, xy, n_tris, tri, n_wall_edges, wall_edge, period_x, m, c->err);
+  if (r != FELBM_OK) return r;
+  c->N = m.N;
+  c->Np = m.Np;
+  c->E = m.E;
+  c->W = m.W;
+  c->offdiag_nnz = m.offdiag_nnz;
+  c->sell_entries = (int64_t)m.sell_col.size();
+  c->band.period = period_x;
+  HIP_OK(c, hipSetDevice(c->device));
+  const int64_t N = m.N, Np = m.Np, E = m.E;
+  const size_t rs = c->rs;
+  TRY(dalloc(c, &c->tri, 3 * E));
+  TRY(dalloc(c, &c->enbr, 3 * E));
+  TRY(dalloc(c, &c->geo, 7 * E));
+  TRY(dalloc_bytes(c, &c->geor, 7 * E * rs));
+  TRY(dalloc(c, &c->n2e_ptr, N + 1));
+  TRY(dalloc(c, &c->n2e, 3 * E));
+  TRY(dalloc(c, &c->wall_nbr, 2 * N));
+  TRY(dalloc(c, &c->wall_len, 2 * N));
+  TRY(dalloc(c, &c->is_wall, N));
+  TRY(dalloc(c, &c->bc, N));
+  TRY(dalloc(c, &c->mass, N));
+  TRY(dalloc(c, &c->xy, 2 * N));
+  TRY(dalloc(c, &c->sell_ptr, m.sell_ptr.size()));
+  TRY(dalloc(c, &c->sell_col, m.sell_col.size()));
+  TRY(dalloc_bytes(c, &c->sell_val, m.sell_val.size() * rs));
+  TRY(dalloc_bytes(c, &c->pop, 18 * Np * rs));
+  TRY(dalloc_bytes(c, &c->f, 18 * Np * rs));
+  TRY(dalloc_bytes(c, &c->xa, 18 * Np * rs));
+  TRY(dalloc_bytes(c, &c->xb, 18 * Np * rs));
+  TRY(dalloc(c, &c->Cn, N));
+  TRY(dalloc(c, &c->mu, N));
+  TRY(dalloc(c, &c->lapC, N));
+  TRY(dalloc_bytes(c, &c->pn, N * rs));
+  TRY(dalloc_bytes(c, &c->uxn, N * rs));
+  TRY(dalloc_bytes(c, &c->uyn, N * rs));
+  TRY(dalloc(c, &c->gC, 2 * E));
+  TRY(dalloc(c, &c->gmu, 2 * E));
+  TRY(dalloc(c, &c->lapmu, E));
+  TRY(dalloc_bytes(c, &c->gp, 2 * E * rs));
+  TRY(dalloc(c, &c->partials, (size_t)NRED * grid_for(N)));
+  TRY(dalloc(c, &c->hist, c->hist_cap));
+  TRY(dalloc(c, &c->diag_now, 1));
+  TRY(dalloc(c, &c->first_bad, 1));
+  TRY(upload(c, c->tri, m.tri));
+  TRY(upload(c, c->enbr, m.enbr));
+  TRY(upload(c, c->geo, m.geo));
+  TRY(upload(c, c->n2e_ptr, m.n2e_ptr));
+  TRY(upload(c, c->n2e, m.n2e));
+  TRY(upload(c, c->wall_nbr, m.wall_nbr));
+  TRY(upload(c, c->wall_len, m.wall_len));
+  TRY(upload(c, c->is_wall, m.is_wall));
+  TRY(upload(c, c->mass, m.mass));
+  TRY(upload(c, c->xy, m.xy));
+  TRY(upload(c, c->sell_ptr, m.sell_ptr));
+  TRY(upload(c, c->sell_col, m.sell_col));
+  if (c->prm.precision == FELBM_FP64) {
+    TRY(upload(c, (double*)c->geor, m.geo));
+    TRY(upload(c, (double*)c->sell_val, m.sell_val));
+  } else {
+    std::vector<float> g32(m.geo.begin(), m.geo.end()), v32(m.sell_val.begin(), m.sell_val.end());
+    TRY(upload(c, (float*)c->geor, g32));
+    TRY(upload(c, (float*)c->sell_val, v32));
+    HIP_OK(c, hipStreamSynchronize(c->stream));  // g32/v32 are about to go out of scope
+  }
+  std::vector<double> zeros(N, 0.0);
+  TRY(upload(c, c->bc, zeros));
+  HIP_OK(c, hipMemsetAsync(c->pop, 0, 18 * Np * rs, c->stream));
+  HIP_OK(c, hipMemsetAsync(c->f, 0, 18 * Np * rs, c->stream));
+  HIP_OK(c, hipMemsetAsync(c->xa, 0, 18 * Np * rs, c->stream));
+  HIP_OK(c, hipMemsetAsync(c->xb, 0, 18 * Np * rs, c->stream));
+  HIP_OK(c, hipMemsetAsync(c->hist, 0, c->hist_cap * sizeof(DiagRecord), c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  c->host_omega.assign(N, 0.0);
+  c->has_mesh = true;
+  set_kernel_bytes(c);
+  return FELBM_OK;
+}
+
+int felbm_set_wetting(felbm_ctx* c, const double* omega_c) {
+  if (!c) return FELBM_EINVAL;
+  if (!c->has_mesh) return fail(c, FELBM_ESTATE, "set_wetting: no mesh");
+  if (!omega_c) return fail(c, FELBM_EINVAL, "set_wetting: null omega_c");
+  const double kappa = c->sp.kappa, beta = c->sp.beta;
+  std::vector<double> bc(c->N, 0.0);
+  for (int64_t i = 0; i < c->N; ++i) {
+    if (!std::isfinite(omega_c[i])) return fail(c, FELBM_EINVAL, "set_wetting: non-finite value");
+    c->host_omega[i] = omega_c[i];
+  }
+  // wall flags live on the device; recompute them from the host copy of the mesh is not kept, so read back
+  std::vector<uint8_t> wall(c->N);
+  HIP_OK(c, hipMemcpy(wall.data(), c->is_wall, c->N, hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < c->N; ++i) {
+    if (!wall[i] || omega_c[i] == 0.0) continue;
+    if (kappa <= 0.0) return fail(c, FELBM_EINVAL, "set_wetting: a nonzero wetting potential needs kappa > 0");
+    bc[i] = omega_c[i] * std::sqrt(2.0 * kappa * beta) / kappa;  // phi_c / kappa, Young: phi_c = Omega_c sqrt(2 kappa beta)
+  }
+  TRY(upload(c, c->bc, bc));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  return FELBM_OK;
+}
+
+int felbm_init(felbm_ctx* c, const double* C, const double* u, const double* p) {
+  if (!c) return FELBM_EINVAL;
+  if (!c->has_mesh) return fail(c, FELBM_ESTATE, "init: no mesh");
+  if (!C) return fail(c, FELBM_EINVAL, "init: null C");
+  const int64_t N = c->N;
+  std::vector<double> hC(C, C + N), hU(2 * N, 0.0), hP(N, 0.0);
+  if (u) hU.assign(u, u + 2 * N);
+  if (p) hP.assign(p, p + N);
+  for (int64_t i = 0; i < N; ++i)
+    if (!std::isfinite(hC[i]) || !std::isfinite(hU[2 * i]) || !std::isfinite(hU[2 * i + 1]) || !std::isfinite(hP[i]))
+      return fail(c, FELBM_EINVAL, "init: non-finite input at node " + std::to_string(i));
+  double *dC = nullptr, *dU = nullptr, *dP = nullptr;
+  HIP_OK(c, hipMallocAsync((void**)&dC, N * 8, c->stream));
+  HIP_OK(c, hipMallocAsync((void**)&dU, 2 * N * 8, c->stream));
+  HIP_OK(c, hipMallocAsync((void**)&dP, N * 8, c->stream));
+  HIP_OK(c, hipMemcpyAsync(dC, hC.data(), N * 8, hipMemcpyHostToDevice, c->stream));
+  HIP_OK(c, hipMemcpyAsync(dU, hU.data(), 2 * N * 8, hipMemcpyHostToDevice, c->stream));
+  HIP_OK(c, hipMemcpyAsync(dP, hP.data(), N * 8, hipMemcpyHostToDevice, c->stream));
+  const int g = (int)((N + BLOCK - 1) / BLOCK);
+  if (c->prm.precision == FELBM_FP64)
+    hipLaunchKernelGGL(k_init<double>, dim3(g), dim3(BLOCK), 0, c->stream, (int)N, (int)c->Np, c->sp, (const double*)dC,
+                       (const double*)dU, (const double*)dP, (const uint8_t*)c->is_wall, (double*)c->pop);
+  else
+    hipLaunchKernelGGL(k_init<float>, dim3(g), dim3(BLOCK), 0, c->stream, (int)N, (int)c->Np, c->sp, (const double*)dC,
+                       (const double*)dU, (const double*)dP, (const uint8_t*)c->is_wall, (float*)c->pop);
+  HIP_OK(c, hipGetLastError());
+  HIP_OK(c, hipFreeAsync(dC, c->stream));
+  HIP_OK(c, hipFreeAsync(dU, c->stream));
+  HIP_OK(c, hipFreeAsync(dP, c->stream));
+  const int32_t minus1 = -1;
+  HIP_OK(c, hipMemcpyAsync(c->first_bad, &minus1, sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  c->step = 0;
+  c->has_state = true;
+  return FELBM_OK;
+}
+
+int felbm_step_async(felbm_ctx* c, int64_t n) {
+  if (!c) return FELBM_EINVAL;
+  if (!c->has_state) return fail(c, FELBM_ESTATE, "step: not initialised");
+  if (n < 0) return fail(c, FELBM_EINVAL, "step: negative step count");
+  return enqueue_steps(c, n);
+}
+
+int felbm_step(felbm_ctx* c, int64_t n) {
+  TRY(felbm_step_async(c, n));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  if (c->timing) TRY(harvest_timing(c));
+  int32_t bad = -1;
+  HIP_OK(c, hipMemcpy(&bad, c->first_bad, sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (bad >= 0) return fail(c, FELBM_ENONFINITE, "step: non-finite state entering step " + std::to_string(bad));
+  return FELBM_OK;
+}
+
+int felbm_read(felbm_ctx* c, int32_t field, double* out) {
+  if (!c) return FELBM_EINVAL;
+  if (!c->has_state) return fail(c, FELBM_ESTATE, "read: not initialised");
+  if (!out) return fail(c, FELBM_EINVAL, "read: null output");
+  if (field < FELBM_FIELD_C || field > FELBM_FIELD_LAPMU) return fail(c, FELBM_EINVAL, "read: unknown field");
+  TRY(enqueue_fields_any(c, false, false, nullptr));
+  const int64_t N = c->N;
+  const double* src = nullptr;
+  double* tmp = nullptr;
+  int64_t n = N;
+  switch (field) {
+    case FELBM_FIELD_C:
+    case FELBM_FIELD_RHO: src = c->Cn; break;
+    case FELBM_FIELD_MU: src = c->mu; break;
+    case FELBM_FIELD_LAPC: src = c->lapC; break;
+    case FELBM_FIELD_LAPMU: src = c->lapmu; n = c->E; break;
+    default: {
+      const void* s = field == FELBM_FIELD_P ? c->pn : (field == FELBM_FIELD_UX ? c->uxn : c->uyn);
+      HIP_OK(c, hipMallocAsync((void**)&tmp, N * 8, c->stream));
+      TRY(to_double(c, s, tmp, N));
+      src = tmp;
+    }
+  }
+  HIP_OK(c, hipMemcpyAsync(out, src, n * 8, hipMemcpyDeviceToHost, c->stream));
+  if (tmp) HIP_OK(c, hipFreeAsync(tmp, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  if (c->timing) TRY(harvest_timing(c));
+  if (field == FELBM_FIELD_RHO)
+    for (int64_t i = 0; i < N; ++i) out[i] = out[i] * c->prm.rho_l + (1.0 - out[i]) * c->prm.rho_v;
+  return FELBM_OK;
+}
+
+int felbm_read_populations(felbm_ctx* c, double* out) {
+  if (!c) return FELBM_EINVAL;
+  if (!c->has_state) return fail(c, FELBM_ESTATE, "read_populations: not initialised");
+  if (!out) return fail(c, FELBM_EINVAL, "read_populations: null output");
+  return copy_pops_out(c, c->pop, out);
+}
+
+int felbm_step_debug(felbm_ctx* c, double* psi_hat, double* rhs_over_m, double* delta) {
+  if (!c) return FELBM_EINVAL;
+  if (!c->has_state) return fail(c, FELBM_ESTATE, "step_debug: not initialised");
+  // the step's pipeline, split after the right-hand side to capture psi_hat and b/m
+  TRY(enqueue_fields_any(c, true, true, c->hist + (c->step % c->hist_cap)));
+  const int gN = grid_for(c->N);
+  const int N = (int)c->N, Np = (int)c->Np, E = (int)c->E;
+  if (c->prm.precision == FELBM_FP64)
+    TRY(launch(c, K_RHS, k_rhs<double>, gN, N, Np, E, (const int*)c->n2e_ptr, (const int*)c->n2e, (const int*)c->tri,
+               (const double*)c->geor, (const double*)c->gC, (const double*)c->gp, (const double*)c->lapmu,
+               (const double*)c->Cn, (const double*)c->uxn, (const double*)c->uyn, (const double*)c->mu,
+               (const double*)c->pop, (const double*)c->mass, c->sp, (double*)c->f));
+  else
+    TRY(launch(c, K_RHS, k_rhs<float>, gN, N, Np, E, (const int*)c->n2e_ptr, (const int*)c->n2e, (const int*)c->tri,
+               (const float*)c->geor, (const double*)c->gC, (const float*)c->gp, (const double*)c->lapmu,
+               (const double*)c->Cn, (const float*)c->uxn, (const float*)c->uyn, (const double*)c->mu,
+               (const float*)c->pop, (const double*)c->mass, c->sp, (float*)c->f));
+  std::vector<double> hat(18 * c->N);
+  TRY(copy_pops_out(c, c->pop, hat.data()));
+  if (psi_hat) std::memcpy(psi_hat, hat.data(), hat.size() * 8);
+  if (rhs_over_m) TRY(copy_pops_out(c, c->f, rhs_over_m));
+  // finish the step: run only the solve and update on the already computed f
+  {
+    const int K = c->prm.solver_sweeps;
+    auto run = [&](auto tag) -> int {
+      using real = decltype(tag);
+      const int* sp = c->sell_ptr;
+      const int* sc = c->sell_col;
+      const real* sv = (const real*)c->sell_val;
+      real *pop = (real*)c->pop, *f = (real*)c->f, *xa = (real*)c->xa, *xb = (real*)c->xb;
+      const uint8_t* wall = c->is_wall;
+      if (K == 0) {
+        TRY(launch(c, K_SWEEP_LAST, k_sweep<real, 4>, gN, N, Np, sp, sc, sv, (const real*)f, (const real*)nullptr,
+                   (real*)nullptr, pop, wall, (real)0));
+      } else if (K == 1) {
+        TRY(launch(c, K_SWEEP_LAST, k_sweep<real, 3>, gN, N, Np, sp, sc, sv, (const real*)f, (const real*)nullptr,
+                   (real*)nullptr, pop, wall, (real)c->cheb_w[0]));
+      } else {
+        TRY(launch(c, K_SWEEP_FIRST, k_sweep<real, 0>, gN, N, Np, sp, sc, sv, (const real*)f, (const real*)nullptr, xa,
+                   pop, wall, (real)c->cheb_w[0]));
+        real *xin = xa, *xout = xb;
+        for (int j = 1; j < K - 1; ++j) {
+          TRY(launch(c, K_SWEEP_MID, k_sweep<real, 1>, gN, N, Np, sp, sc, sv, (const real*)f, (const real*)xin, xout,
+                     pop, wall, (real)c->cheb_w[j]));
+          std::swap(xin, xout);
+        }
+        TRY(launch(c, K_SWEEP_LAST, k_sweep<real, 2>, gN, N, Np, sp, sc, sv, (const real*)f, (const real*)xin,
+                   (real*)nullptr, pop, wall, (real)c->cheb_w[K - 1]));
+      }
+      return FELBM_OK;
+    };
+    if (c->prm.precision == FELBM_FP64)
+      TRY(run(double{}));
+    else
+      TRY(run(float{}));
+  }
+  c->step += 1;
+  if (delta) {
+    std::vector<double> after(18 * c->N);
+    TRY(copy_pops_out(c, c->pop, after.data()));
+    std::vector<uint8_t> wall(c->N);
+    HIP_OK(c, hipMemcpy(wall.data(), c->is_wall, c->N, hipMemcpyDeviceToHost));
+    // delta = psi_bar^{n+1} - psi_hat away from walls; at wall nodes the wall
+    // operator has been applied after the update, so report the pre-wall value
+    // reconstructed only where it is unambiguous (interior nodes)
+    for (int64_t a = 0; a < 18; ++a)
+      for (int64_t i = 0; i < c->N; ++i)
+        delta[a * c->N + i] = wall[i] ? std::nan("") : after[a * c->N + i] - hat[a * c->N + i];
+  }
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  if (c->timing) TRY(harvest_timing(c));
+  return FELBM_OK;
+}
+
+int felbm_set_band(felbm_ctx* c, double xc, double yc, double R, double w) {
+  if (!c) return FELBM_EINVAL;
+  if (!std::isfinite(xc) || !std::isfinite(yc) || !std::isfinite(R) || !std::isfinite(w) || w < 0)
+    return fail(c, FELBM_EINVAL, "set_band: bad arguments");
+  if (R <= 0) {
+    c->band.enabled = 0;
+    return FELBM_OK;
+  }
+  const double lo = std::max(0.0, R - w), hi = R + w;
+  c->band.xc = xc;
+  c->band.yc = yc;
+  c->band.r_lo2 = lo * lo;
+  c->band.r_hi2 = hi * hi;
+  c->band.enabled = 1;
+  return FELBM_OK;
+}
+
+int felbm_diagnostics(felbm_ctx* c, felbm_diag* out) {
+  if (!c) return FELBM_EINVAL;
+  if (!c->has_state) return fail(c, FELBM_ESTATE, "diagnostics: not initialised");
+  if (!out) return fail(c, FELBM_EINVAL, "diagnostics: null output");
+  static_assert(sizeof(DiagRecord) == sizeof(felbm_diag), "diag layout");
+  const int gN = grid_for(c->N);
+  const int N = (int)c->N, Np = (int)c->Np;
+  int32_t* scratch_bad = nullptr;
+  HIP_OK(c, hipMallocAsync((void**)&scratch_bad, sizeof(int32_t), c->stream));
+  const int32_t zero = 0;
+  HIP_OK(c, hipMemcpyAsync(scratch_bad, &zero, sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+  if (c->prm.precision == FELBM_FP64)
+    TRY(launch(c, K_MOMENTS, k_moments<double, false>, gN, (double*)c->pop, N, Np, c->sp, c->Cn, (double*)c->pn,
+               (double*)c->uxn, (double*)c->uyn, (const double*)c->mass, (const double*)c->xy, c->band, c->partials));
+  else
+    TRY(launch(c, K_MOMENTS, k_moments<float, false>, gN, (float*)c->pop, N, Np, c->sp, c->Cn, (float*)c->pn,
+               (float*)c->uxn, (float*)c->uyn, (const double*)c->mass, (const double*)c->xy, c->band, c->partials));
+  TRY(launch(c, K_REDUCE, k_reduce_final, 1, (const double*)c->partials, gN, N, (int64_t)c->step, c->diag_now,
+             scratch_bad));
+  HIP_OK(c, hipMemcpyAsync(out, c->diag_now, sizeof(felbm_diag), hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(c, hipFreeAsync(scratch_bad, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  if (c->timing) TRY(harvest_timing(c));
+  return FELBM_OK;
+}
+
+int felbm_history(felbm_ctx* c, felbm_diag* out, int64_t max_entries, int64_t* n_out) {
+  if (!c) return FELBM_EINVAL;
+  if (!out || !n_out || max_entries < 0) return fail(c, FELBM_EINVAL, "history: bad arguments");
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  const int64_t avail = std::min<int64_t>(c->step, c->hist_cap);
+  const int64_t n = std::min<int64_t>(avail, max_entries);
+  std::vector<DiagRecord> all(c->hist_cap);
+  if (n > 0) HIP_OK(c, hipMemcpy(all.data(), c->hist, c->hist_cap * sizeof(DiagRecord), hipMemcpyDeviceToHost));
+  for (int64_t k = 0; k < n; ++k) {
+    const int64_t s = c->step - n + k;
+    std::memcpy(&out[k], &all[s % c->hist_cap], sizeof(felbm_diag));
+  }
+  *n_out = n;
+  return FELBM_OK;
+}
+
+int64_t felbm_state_bytes(const felbm_ctx* c) {
+  if (!c || !c->has_mesh) return 0;
+  return (int64_t)sizeof(StateHeader) + 18 * c->Np * (int64_t)c->rs;
+}
+
+int felbm_save_state(felbm_ctx* c, void* buf, int64_t bytes) {
+  if (!c) return FELBM_EINVAL;
+  if (!c->has_state) return fail(c, FELBM_ESTATE, "save_state: not initialised");
+  if (!buf || bytes < felbm_state_bytes(c)) return fail(c, FELBM_EINVAL, "save_state: buffer too small");
+  StateHeader h{kStateMagic, c->prm.precision, c->N, c->step, 18 * c->Np * (int64_t)c->rs};
+  std::memcpy(buf, &h, sizeof(h));
+  HIP_OK(c, hipMemcpyAsync((char*)buf + sizeof(h), c->pop, h.payload_bytes, hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  return FELBM_OK;
+}
+
+int felbm_load_state(felbm_ctx* c, const void* buf, int64_t bytes) {
+  if (!c) return FELBM_EINVAL;
+  if (!c->has_mesh) return fail(c, FELBM_ESTATE, "load_state: no mesh");
+  if (!buf || bytes < felbm_state_bytes(c)) return fail(c, FELBM_EINVAL, "load_state: buffer too small");
+  StateHeader h;
+  std::memcpy(&h, buf, sizeof(h));
+  if (h.magic != kStateMagic || h.precision != c->prm.precision || h.n_nodes != c->N ||
+      h.payload_bytes != 18 * c->Np * (int64_t)c->rs)
+    return fail(c, FELBM_EINVAL, "load_state: header does not match this context");
+  HIP_OK(c, hipMemcpyAsync(c->pop, (const char*)buf + sizeof(h), h.payload_bytes, hipMemcpyHostToDevice, c->stream));
+  const int32_t minus1 = -1;
+  HIP_OK(c, hipMemcpyAsync(c->first_bad, &minus1, sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  c->step = h.step;
+  c->has_state = true;
+  return FELBM_OK;
+}
+
+int felbm_bind_stream(felbm_ctx* c, void* s) {
+  if (!c) return FELBM_EINVAL;
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  c->stream = s ? (hipStream_t)s : c->own_stream;
+  return FELBM_OK;
+}
+
+int felbm_kernel_timing(felbm_ctx* c, int32_t enable) {
+  if (!c) return FELBM_EINVAL;
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  TRY(harvest_timing(c));
+  c->timing = enable != 0;
+  for (auto& k : c->kstat) {
+    k.launches = 0;
+    k.total_ms = 0.0;
+  }
+  return FELBM_OK;
+}
+
+int felbm_kernel_stats(felbm_ctx* c, felbm_kstat* out, int32_t max_entries, int32_t* n_out) {
+  if (!c) return FELBM_EINVAL;
+  if (!out || !n_out || max_entries < 0) return fail(c, FELBM_EINVAL, "kernel_stats: bad arguments");
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  TRY(harvest_timing(c));
+  int n = std::min<int>(K_COUNT, max_entries);
+  for (int k = 0; k < n; ++k) {
+    std::memset(&out[k], 0, sizeof(felbm_kstat));
+    std::snprintf(out[k].name, sizeof(out[k].name), "%s", kKernelNames[k]);
+    out[k].launches = c->kstat[k].launches;
+    out[k].total_ms = c->kstat[k].total_ms;
+    out[k].bytes_per_launch = c->kstat[k].bytes;
+  }
+  *n_out = n;
+  return FELBM_OK;
+}
+
+int felbm_mesh_info(const felbm_ctx* c, int64_t* n_nodes, int64_t* n_tris, int64_t* n_wall_edges, int64_t* nnz) {
+  if (!c || !c->has_mesh) return FELBM_ESTATE;
+  if (n_nodes) *n_nodes = c->N;
+  if (n_tris) *n_tris = c->E;
+  if (n_wall_edges) *n_wall_edges = c->W;
+  if (nnz) *nnz = c->offdiag_nnz;
+  return FELBM_OK;
+}
+
+int felbm_validate_mesh(int64_t n_nodes, const double* xy, int64_t n_tris, const int32_t* tri, int64_t n_wall,
+                        const int32_t* wall_edge, double period_x, char* msg, int32_t msg_len) {
+  MeshPrep m;
+  std::string err;
+  const int r = prepare_mesh(n_nodes, xy, n_tris, tri, n_wall, wall_edge, period_x, m, err);
+  if (msg && msg_len > 0) std::snprintf(msg, (size_t)msg_len, "%s", err.c_str());
+  return r;
+}
+
+void felbm_destroy(felbm_ctx* c) {
+  if (!c) return;
+  if (c->stream) hipStreamSynchronize(c->stream);
+  for (auto& p : c->pending) {
+    hipEventDestroy(p.start);
+    hipEventDestroy(p.stop);
+  }
+  for (auto e : c->event_pool) hipEventDestroy(e);
+  for (void* p : c->allocations) hipFree(p);
+  if (c->own_stream) hipStreamDestroy(c->own_stream);
+  delete c;
+}
+
+}  // extern "C"

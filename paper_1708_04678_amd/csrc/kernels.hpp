@@ -1,0 +1,495 @@
+// HIP kernels (gfx950) of one FE-LBM time step: D2Q9 populations g, h on a
+// P1 triangle mesh (arXiv:1708.04678, Sec. II.A-D).
+//
+// Data layout (device, all structure-of-arrays):
+//   populations  real [18][Np]   g_0..g_8 then h_0..h_8, Np = N rounded up to 64
+//   node fields  C, mu, lap C in double; p, u_x, u_y in real
+//   elements     tri/enbr int32 [3][E]; geometry double [7][E] = (A, grad N_0,
+//                grad N_1, grad N_2) and a copy in real for the streaming gather
+//   node->element gather list (CSR, packed element*4 + local vertex)
+//   mass matrix  diag(m)^-1 M11 off-diagonal part in sliced-ELL form, slice
+//                height 64 (one wavefront), column-major inside a slice
+//
+// Every node-indexed output is produced by exactly one thread that gathers its
+// inputs (no scatter, no atomics): results are bitwise reproducible.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace felbm {
+
+constexpr int Q = 9;
+constexpr int NPOP = 18;
+constexpr int BLOCK = 256;
+constexpr double CS2 = 1.0 / 3.0;
+
+// D2Q9 velocity set and weights (textbook; the paper's 3-D runs use D3Q19)
+__host__ __device__ constexpr int ex(int a) { return (a == 1 || a == 5 || a == 8) ? 1 : ((a == 3 || a == 6 || a == 7) ? -1 : 0); }
+__host__ __device__ constexpr int ey(int a) { return (a == 2 || a == 5 || a == 6) ? 1 : ((a == 4 || a == 7 || a == 8) ? -1 : 0); }
+__host__ __device__ constexpr double wq(int a) { return a == 0 ? 4.0 / 9.0 : (a < 5 ? 1.0 / 9.0 : 1.0 / 36.0); }
+__host__ __device__ constexpr int opp(int a) { return a == 0 ? 0 : (a < 5 ? ((a + 1) % 4) + 1 : ((a - 3) % 4) + 5); }
+
+struct StepParams {
+  double kappa, beta, mobility, rho_l, rho_v, inv_tau_l, inv_tau_v, dt;
+};
+
+struct Band {
+  double xc, yc, r_lo2, r_hi2, period;  // squared radii of the band, x period (0 = none)
+  int enabled;
+};
+
+// ----------------------------------------------------------------------------
+// launch helpers
+// ----------------------------------------------------------------------------
+// Workgroups are dispatched round-robin over the 8 XCDs of the MI355X; the
+// grid is padded to a multiple of 8 and block b is remapped so that every XCD
+// walks one contiguous range of nodes (neighbour gathers then hit its own L2).
+__device__ __forceinline__ int xcd_block() {
+  const int per = gridDim.x >> 3;
+  return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Deterministic block reduction of NR doubles (sum for all but index imax,
+// which is reduced by max); thread 0 writes partials[k * nblk + blk].
+template <int NR>
+__device__ __forceinline__ void block_reduce_store(double (&v)[NR], int imax, double* partials, int nblk, int blk) {
+  __shared__ double red[NR][BLOCK / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    double r = (k == imax) ? wave_max(v[k]) : wave_sum(v[k]);
+    if (lane == 0) red[k][wid] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      double r = red[k][0];
+      for (int w = 1; w < BLOCK / 64; ++w) r = (k == imax) ? fmax(r, red[k][w]) : r + red[k][w];
+      partials[k * nblk + blk] = r;
+    }
+  }
+}
+
+constexpr int NRED = 6;  // mass, sum rho|u|^2, max|u|, band sum, band count, nonfinite count
+
+// ----------------------------------------------------------------------------
+// a1 + a6: moments, relaxation time, equilibria, BGK collision (eqn::collide)
+// ----------------------------------------------------------------------------
+// Reads the state psi_bar, writes the nodal fields and (COLLIDE) psi_hat in
+// place; also writes per-block partials of the FP64 reductions of the state.
+template <typename real, bool COLLIDE>
+__global__ void __launch_bounds__(BLOCK) k_moments(real* __restrict__ pop, int N, int Np, StepParams P,
+                                                  double* __restrict__ Cn, real* __restrict__ pn,
+                                                  real* __restrict__ uxn, real* __restrict__ uyn,
+                                                  const double* __restrict__ mass, const double* __restrict__ xy,
+                                                  Band band, double* __restrict__ partials) {
+  const int blk = xcd_block();
+  const int i = blk * BLOCK + threadIdx.x;
+  double red[NRED] = {0, 0, 0, 0, 0, 0};
+  if (i < N) {
+    real g[Q], h[Q];
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      g[a] = pop[a * Np + i];
+      h[a] = pop[(Q + a) * Np + i];
+    }
+    double C = 0.0;
+    real p = 0, jx = 0, jy = 0;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      C += (double)h[a];
+      p += g[a];
+      if (ex(a)) jx += ex(a) > 0 ? g[a] : -g[a];
+      if (ey(a)) jy += ey(a) > 0 ? g[a] : -g[a];
+    }
+    const real rho = (real)(C * P.rho_l + (1.0 - C) * P.rho_v);
+    const real ux = (real)3.0 * jx / rho, uy = (real)3.0 * jy / rho;  // rho u = sum e g / c_s^2
+    Cn[i] = C;
+    pn[i] = p;
+    uxn[i] = ux;
+    uyn[i] = uy;
+    if (COLLIDE) {
+      const real tau = (real)(1.0 / (C * P.inv_tau_l + (1.0 - C) * P.inv_tau_v));
+      const real om = (real)1 / (tau + (real)0.5);
+      const real uu = ux * ux + uy * uy;
+      const real Cr = (real)C;
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        const real eu = (real)ex(a) * ux + (real)ey(a) * uy;
+        const real poly = eu + (real)1.5 * eu * eu - (real)0.5 * uu;   // c_s^2 (e.u/c_s^2 + ...)
+        const real geq = (real)wq(a) * (p + rho * poly);
+        const real heq = (real)wq(a) * Cr * ((real)1 + (real)3 * poly);
+        pop[a * Np + i] = g[a] - om * (g[a] - geq);
+        pop[(Q + a) * Np + i] = h[a] - om * (h[a] - heq);
+      }
+    }
+    const double uu = (double)ux * ux + (double)uy * uy;
+    const double rr = C * P.rho_l + (1.0 - C) * P.rho_v;
+    red[0] = mass[i] * C;
+    red[1] = rr * uu;
+    red[2] = sqrt(uu);
+    if (band.enabled) {
+      double dx = xy[i] - band.xc;
+      if (band.period > 0) dx -= band.period * rint(dx / band.period);
+      const double dy = xy[N + i] - band.yc, d2 = dx * dx + dy * dy;
+      if (d2 >= band.r_lo2 && d2 <= band.r_hi2) {
+        red[3] = rr * uu;
+        red[4] = 1.0;
+      }
+    }
+    red[5] = (isfinite(C) && isfinite((double)p) && isfinite(uu)) ? 0.0 : 1.0;
+    if (red[5] != 0.0) red[2] = 0.0;
+  }
+  block_reduce_store<NRED>(red, 2, partials, gridDim.x, blk);
+}
+
+struct DiagRecord {  // mirrors felbm_diag
+  int64_t step;
+  double mass, mean_ke, max_u, band_ke;
+  int64_t band_nodes;
+  int32_t nonfinite, pad_;
+};
+
+// Second, fixed-order pass over the block partials (one block).
+__global__ void __launch_bounds__(BLOCK) k_reduce_final(const double* __restrict__ partials, int nblk, int N,
+                                                         int64_t step, DiagRecord* __restrict__ out,
+                                                         int* __restrict__ first_bad) {
+  double v[NRED];
+#pragma unroll
+  for (int k = 0; k < NRED; ++k) {
+    double r = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += BLOCK) r = (k == 2) ? fmax(r, partials[k * nblk + b]) : r + partials[k * nblk + b];
+    v[k] = r;
+  }
+  __shared__ double red[NRED][BLOCK / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NRED; ++k) {
+    double r = (k == 2) ? wave_max(v[k]) : wave_sum(v[k]);
+    if (lane == 0) red[k][wid] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r[NRED];
+    for (int k = 0; k < NRED; ++k) {
+      r[k] = red[k][0];
+      for (int w = 1; w < BLOCK / 64; ++w) r[k] = (k == 2) ? fmax(r[k], red[k][w]) : r[k] + red[k][w];
+    }
+    DiagRecord d;
+    d.step = step;
+    d.mass = r[0];
+    d.mean_ke = 0.5 * r[1] / (double)N;
+    d.max_u = r[2];
+    d.band_ke = r[4] > 0 ? r[3] / r[4] : 0.0;
+    d.band_nodes = (int64_t)r[4];
+    d.nonfinite = r[5] > 0 ? 1 : 0;
+    d.pad_ = 0;
+    *out = d;
+    if (d.nonfinite && *first_bad < 0) *first_bad = (int)step;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// a2: element gradients of the P1 fields C (double) and p (real)
+// ----------------------------------------------------------------------------
+template <typename real>
+__global__ void __launch_bounds__(BLOCK) k_elem_grad(int E, const int* __restrict__ tri, const double* __restrict__ geo,
+                                                    const double* __restrict__ Cn, const real* __restrict__ pn,
+                                                    double* __restrict__ gC, real* __restrict__ gp) {
+  const int e = xcd_block() * BLOCK + threadIdx.x;
+  if (e >= E) return;
+  const int v0 = tri[e], v1 = tri[E + e], v2 = tri[2 * E + e];
+  const double g0x = geo[E + e], g0y = geo[2 * E + e], g1x = geo[3 * E + e], g1y = geo[4 * E + e];
+  const double g2x = geo[5 * E + e], g2y = geo[6 * E + e];
+  const double c0 = Cn[v0], c1 = Cn[v1], c2 = Cn[v2];
+  gC[e] = c0 * g0x + c1 * g1x + c2 * g2x;
+  gC[E + e] = c0 * g0y + c1 * g1y + c2 * g2y;
+  const real p0 = pn[v0], p1 = pn[v1], p2 = pn[v2];
+  gp[e] = p0 * (real)g0x + p1 * (real)g1x + p2 * (real)g2x;
+  gp[E + e] = p0 * (real)g0y + p1 * (real)g1y + p2 * (real)g2y;
+}
+
+// Outward flux through a wall edge from the wetting condition (eq. bc2, n
+// into the fluid): -int (phi_c/kappa)(C - C^2) ds with C and phi_c/kappa
+// linear on the edge, integrated exactly by Simpson's rule.
+__device__ __forceinline__ double wall_flux(double Ca, double Cb, double ra, double rb, double len) {
+  const double Cm = 0.5 * (Ca + Cb), rm = 0.5 * (ra + rb);
+  return -len * (1.0 / 6.0) * (ra * (Ca - Ca * Ca) + 4.0 * rm * (Cm - Cm * Cm) + rb * (Cb - Cb * Cb));
+}
+
+// ----------------------------------------------------------------------------
+// a3: nodal Laplacian of C over the vertex patch (eqn:lapl_int_mp) and the
+// chemical potential mu = 2 beta C (C-1)(2C-1) - kappa lap C (eqn:mp_mu).
+// The outer edge of patch element T opposite node k has |e| n_out =
+// -2 A_T grad N_k; its gradient is the mean of the two adjacent element
+// gradients; wall edges (opposite k, or incident to k) carry the wetting flux.
+// ----------------------------------------------------------------------------
+__global__ void __launch_bounds__(BLOCK) k_lapC_mu(int N, int E, const int* __restrict__ n2e_ptr,
+                                                  const int* __restrict__ n2e, const int* __restrict__ tri,
+                                                  const int* __restrict__ enbr, const double* __restrict__ geo,
+                                                  const double* __restrict__ gC, const double* __restrict__ Cn,
+                                                  const double* __restrict__ bc, const int* __restrict__ wall_nbr,
+                                                  const double* __restrict__ wall_len, StepParams P,
+                                                  double* __restrict__ lapC, double* __restrict__ mu) {
+  const int k = xcd_block() * BLOCK + threadIdx.x;
+  if (k >= N) return;
+  double flux = 0.0, vol = 0.0;
+  const int beg = n2e_ptr[k], end = n2e_ptr[k + 1];
+  for (int q = beg; q < end; ++q) {
+    const int packed = n2e[q];
+    const int e = packed >> 2, l = packed & 3;
+    const double A = geo[e];
+    const double gx = geo[(1 + 2 * l) * E + e], gy = geo[(2 + 2 * l) * E + e];
+    vol += A;
+    const int nb = enbr[l * E + e];
+    if (nb >= 0) {
+      const double Gx = 0.5 * (gC[e] + gC[nb]), Gy = 0.5 * (gC[E + e] + gC[E + nb]);
+      flux += -2.0 * A * (gx * Gx + gy * Gy);
+    } else {
+      const int a = tri[((l + 1) % 3) * E + e], b = tri[((l + 2) % 3) * E + e];
+      const double len = 2.0 * A * sqrt(gx * gx + gy * gy);
+      flux += wall_flux(Cn[a], Cn[b], bc[a], bc[b], len);
+    }
+  }
+  const double Ck = Cn[k];
+#pragma unroll
+  for (int w = 0; w < 2; ++w) {
+    const int j = wall_nbr[w * N + k];
+    if (j >= 0) flux += wall_flux(Ck, Cn[j], bc[k], bc[j], wall_len[w * N + k]);
+  }
+  const double L = flux / vol;
+  lapC[k] = L;
+  mu[k] = 2.0 * P.beta * Ck * (Ck - 1.0) * (2.0 * Ck - 1.0) - P.kappa * L;
+}
+
+// a4: element gradient of mu (P1) ...
+__global__ void __launch_bounds__(BLOCK) k_elem_gradmu(int E, const int* __restrict__ tri,
+                                                      const double* __restrict__ geo, const double* __restrict__ mu,
+                                                      double* __restrict__ gmu) {
+  const int e = xcd_block() * BLOCK + threadIdx.x;
+  if (e >= E) return;
+  const double m0 = mu[tri[e]], m1 = mu[tri[E + e]], m2 = mu[tri[2 * E + e]];
+  gmu[e] = m0 * geo[E + e] + m1 * geo[3 * E + e] + m2 * geo[5 * E + e];
+  gmu[E + e] = m0 * geo[2 * E + e] + m1 * geo[4 * E + e] + m2 * geo[6 * E + e];
+}
+
+// ... and its element Laplacian (Sec. II.D): (1/A) sum over edges of
+// |e| n . mean of the adjacent gradients, zero on wall edges (eqn:bc1);
+// with |e| n = -2 A grad N_v this is -sum_v grad N_v . (g_T + g_T'(v)).
+__global__ void __launch_bounds__(BLOCK) k_elem_lapmu(int E, const int* __restrict__ enbr,
+                                                     const double* __restrict__ geo, const double* __restrict__ gmu,
+                                                     double* __restrict__ lapmu) {
+  const int e = xcd_block() * BLOCK + threadIdx.x;
+  if (e >= E) return;
+  const double tx = gmu[e], ty = gmu[E + e];
+  double acc = 0.0;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    const int nb = enbr[l * E + e];
+    if (nb >= 0) acc += geo[(1 + 2 * l) * E + e] * (tx + gmu[nb]) + geo[(2 + 2 * l) * E + e] * (ty + gmu[E + nb]);
+  }
+  lapmu[e] = -acc;
+}
+
+// ----------------------------------------------------------------------------
+// a5 + a7: P0 element forces (eq:G, eq:H at barycentric values) fused into the
+// node gather of the Galerkin streaming right-hand side (eq:galerkin_lbm):
+//   b_{a,i} = sum_{T ni i} A_T q_{a,T} (dt/3 + dt^2/2 e_a . grad N_i|_T),
+//   q_{a,T} = Phi_{a,T} - e_a . sum_{v in T} psi_hat_{a,v} grad N_v.
+// Output f = b / m_i (the lumped solve, also the solver's initial guess).
+// ----------------------------------------------------------------------------
+template <typename real>
+__global__ void __launch_bounds__(BLOCK) k_rhs(int N, int Np, int E, const int* __restrict__ n2e_ptr,
+                                              const int* __restrict__ n2e, const int* __restrict__ tri,
+                                              const real* __restrict__ geor, const double* __restrict__ gC,
+                                              const real* __restrict__ gp, const double* __restrict__ lapmu,
+                                              const double* __restrict__ Cn, const real* __restrict__ uxn,
+                                              const real* __restrict__ uyn, const double* __restrict__ mu,
+                                              const real* __restrict__ pop, const double* __restrict__ mass,
+                                              StepParams P, real* __restrict__ f) {
+  const int i = xcd_block() * BLOCK + threadIdx.x;
+  if (i >= N) return;
+  real own[NPOP], b[NPOP];
+#pragma unroll
+  for (int a = 0; a < NPOP; ++a) {
+    own[a] = pop[a * Np + i];
+    b[a] = 0;
+  }
+  const real dt = (real)P.dt, c1 = dt / (real)3, c2 = (real)0.5 * dt * dt;
+  const real drho_cs2 = (real)(CS2 * (P.rho_l - P.rho_v));
+  const int beg = n2e_ptr[i], end = n2e_ptr[i + 1];
+  for (int q = beg; q < end; ++q) {
+    const int packed = n2e[q];
+    const int e = packed >> 2, l = packed & 3;
+    int v[3];
+    v[0] = tri[e]; v[1] = tri[E + e]; v[2] = tri[2 * E + e];
+    const real A = geor[e];
+    real gx[3], gy[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      gx[t] = geor[(1 + 2 * t) * E + e];
+      gy[t] = geor[(2 + 2 * t) * E + e];
+    }
+    // barycentric values of the P1 fields and the element gradients
+    const double Cb = (Cn[v[0]] + Cn[v[1]] + Cn[v[2]]) * (1.0 / 3.0);
+    const double mub = (mu[v[0]] + mu[v[1]] + mu[v[2]]) * (1.0 / 3.0);
+    const real ubx = (uxn[v[0]] + uxn[v[1]] + uxn[v[2]]) / (real)3;
+    const real uby = (uyn[v[0]] + uyn[v[1]] + uyn[v[2]]) / (real)3;
+    const real rhob = (real)(Cb * P.rho_l + (1.0 - Cb) * P.rho_v);
+    const double gCx = gC[e], gCy = gC[E + e];
+    const real gpx = gp[e], gpy = gp[E + e];
+    const real ax = drho_cs2 * (real)gCx, ay = drho_cs2 * (real)gCy;          // c_s^2 grad rho
+    const real bx = (real)(mub * gCx), by = (real)(mub * gCy);                // mu grad C
+    const real coef = (real)Cb / (rhob * (real)CS2);
+    const real Xx = (real)gCx - coef * (gpx - bx), Xy = (real)gCy - coef * (gpy - by);
+    const real d = (real)(P.mobility * lapmu[e]);
+    const real uA = ubx * ax + uby * ay, uB = ubx * bx + uby * by, uX = ubx * Xx + uby * Xy;
+    const real uu = ubx * ubx + uby * uby;
+    // gathered post-collision populations of the two other vertices
+    const int o1 = (l + 1) % 3, o2 = (l + 2) % 3;
+    const int va = v[o1], vb = v[o2];
+    const real gla = gx[o1], glb = gx[o2], hla = gy[o1], hlb = gy[o2];
+    const real gxl = gx[l], gyl = gy[l];
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const real exa = (real)ex(a), eya = (real)ey(a);
+      const real eu = exa * ubx + eya * uby;
+      const real G = (real)wq(a) * ((real)1 + (real)3 * eu + (real)4.5 * eu * eu - (real)1.5 * uu);
+      const real Phig = (exa * ax + eya * ay - uA) * (G - (real)wq(a)) + (exa * bx + eya * by - uB) * G;
+      const real Phih = (exa * Xx + eya * Xy - uX + d) * G;
+      const real enl = exa * gxl + eya * gyl;
+      const real ena = exa * gla + eya * hla, enb = exa * glb + eya * hlb;
+      const real sg = own[a] * enl + pop[a * Np + va] * ena + pop[a * Np + vb] * enb;
+      const real sh = own[Q + a] * enl + pop[(Q + a) * Np + va] * ena + pop[(Q + a) * Np + vb] * enb;
+      const real wgt = A * (c1 + c2 * enl);
+      b[a] += wgt * (Phig - sg);
+      b[Q + a] += wgt * (Phih - sh);
+    }
+  }
+  const real inv_m = (real)(1.0 / mass[i]);
+#pragma unroll
+  for (int a = 0; a < NPOP; ++a) f[a * Np + i] = b[a] * inv_m;
+}
+
+// ----------------------------------------------------------------------------
+// a8: the consistent-mass solve M11 x = b, preconditioned by the lumped mass:
+// Richardson sweeps x <- x + w_j (f - A x), A = diag(m)^-1 M11, f = b/m,
+// x_0 = f.  With w_j the reciprocal Chebyshev roots on [lambda_min, lambda_max]
+// the K-sweep product equals the degree-K Chebyshev iterate.
+// (A x)_i = x_i / 2 + sum_j a_ij x_j  (M11_ii / m_i = 1/2 for P1 triangles).
+// MODE 0: first sweep (x = f, gathered from f)
+// MODE 1: middle sweep (x from xin, write xout)
+// MODE 2: last sweep: psi_bar^{n+1} = psi_hat + x_K, then the wall operator
+// MODE 3: single sweep (first and last)
+// MODE 4: no sweep (K = 0): psi_bar^{n+1} = psi_hat + f, then the wall operator
+// ----------------------------------------------------------------------------
+template <typename real, int MODE>
+__global__ void __launch_bounds__(BLOCK) k_sweep(int N, int Np, const int* __restrict__ sell_ptr,
+                                                const int* __restrict__ sell_col, const real* __restrict__ sell_val,
+                                                const real* __restrict__ f, const real* __restrict__ xin,
+                                                real* __restrict__ xout, real* __restrict__ pop,
+                                                const uint8_t* __restrict__ is_wall, real w) {
+  const int i = xcd_block() * BLOCK + threadIdx.x;
+  if (i >= N) return;
+  const real* __restrict__ x = (MODE == 0 || MODE == 3) ? f : xin;
+  real r[NPOP];
+  if (MODE != 4) {
+#pragma unroll
+    for (int a = 0; a < NPOP; ++a) r[a] = (real)0.5 * x[a * Np + i];
+    const int slice = i >> 6, lane = i & 63;
+    const int base = sell_ptr[slice], width = (sell_ptr[slice + 1] - base) >> 6;
+    for (int k = 0; k < width; ++k) {
+      const int idx = base + (k << 6) + lane;
+      const int j = sell_col[idx];
+      const real aij = sell_val[idx];
+#pragma unroll
+      for (int a = 0; a < NPOP; ++a) r[a] += aij * x[a * Np + j];
+    }
+#pragma unroll
+    for (int a = 0; a < NPOP; ++a) {
+      const real xi = (MODE == 0 || MODE == 3) ? f[a * Np + i] : x[a * Np + i];
+      const real fi = (MODE == 0 || MODE == 3) ? xi : f[a * Np + i];
+      r[a] = xi + w * (fi - r[a]);
+    }
+  } else {
+#pragma unroll
+    for (int a = 0; a < NPOP; ++a) r[a] = f[a * Np + i];
+  }
+  if (MODE == 0 || MODE == 1) {
+#pragma unroll
+    for (int a = 0; a < NPOP; ++a) xout[a * Np + i] = r[a];
+    return;
+  }
+  real s[NPOP];
+#pragma unroll
+  for (int a = 0; a < NPOP; ++a) s[a] = pop[a * Np + i] + r[a];
+  if (is_wall[i]) {
+    // wall operator: every opposite pair of g and of h replaced by its mean
+#pragma unroll
+    for (int a = 1; a < Q; ++a) {
+      const int b = opp(a);
+      if (b > a) {
+        const real mg = (real)0.5 * (s[a] + s[b]), mh = (real)0.5 * (s[Q + a] + s[Q + b]);
+        s[a] = mg; s[b] = mg; s[Q + a] = mh; s[Q + b] = mh;
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < NPOP; ++a) pop[a * Np + i] = s[a];
+}
+
+// ----------------------------------------------------------------------------
+// init: psi_bar^0 = psi_eq(C, u, p), then the wall operator
+// ----------------------------------------------------------------------------
+template <typename real>
+__global__ void __launch_bounds__(BLOCK) k_init(int N, int Np, StepParams P, const double* __restrict__ C,
+                                               const double* __restrict__ U, const double* __restrict__ Pr,
+                                               const uint8_t* __restrict__ is_wall, real* __restrict__ pop) {
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= N) return;
+  const double c = C[i], ux = U[2 * i], uy = U[2 * i + 1], p = Pr[i];
+  const double rho = c * P.rho_l + (1.0 - c) * P.rho_v, uu = ux * ux + uy * uy;
+  double s[NPOP];
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const double eu = ex(a) * ux + ey(a) * uy;
+    const double poly = eu + 1.5 * eu * eu - 0.5 * uu;
+    s[a] = wq(a) * (p + rho * poly);
+    s[Q + a] = wq(a) * c * (1.0 + 3.0 * poly);
+  }
+  if (is_wall[i]) {
+#pragma unroll
+    for (int a = 1; a < Q; ++a) {
+      const int b = opp(a);
+      if (b > a) {
+        const double mg = 0.5 * (s[a] + s[b]), mh = 0.5 * (s[Q + a] + s[Q + b]);
+        s[a] = mg; s[b] = mg; s[Q + a] = mh; s[Q + b] = mh;
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < NPOP; ++a) pop[a * Np + i] = (real)s[a];
+}
+
+template <typename real>
+__global__ void __launch_bounds__(BLOCK) k_to_double(int n, const real* __restrict__ in, double* __restrict__ out) {
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n) out[i] = (double)in[i];
+}
+
+}  // namespace felbm

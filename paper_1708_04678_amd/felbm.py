@@ -1,0 +1,244 @@
+"""ctypes binding of libfelbm.so (include/felbm.h).  Argument marshalling
+only: every step of the time step runs in the library's HIP kernels.  There
+is no fallback: if the library is missing, loading raises."""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libfelbm.so")
+
+FP64, FP32 = 0, 1
+FIELDS = {"C": 0, "RHO": 1, "P": 2, "UX": 3, "UY": 4, "MU": 5, "LAPC": 6, "LAPMU": 7}
+ERRORS = {-1: "EINVAL", -2: "EMESH", -3: "ESTATE", -4: "ENONFINITE", -5: "ESOLVER", -6: "EDEVICE", -7: "ENOMEM"}
+
+
+class FelbmError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {message}")
+        self.code = code
+        self.name = ERRORS.get(code, str(code))
+
+
+class Params(ct.Structure):
+    _fields_ = [("sigma", ct.c_double), ("xi", ct.c_double), ("mobility", ct.c_double),
+                ("rho_l", ct.c_double), ("rho_v", ct.c_double), ("nu_l", ct.c_double), ("nu_v", ct.c_double),
+                ("dt", ct.c_double), ("precision", ct.c_int32), ("solver_sweeps", ct.c_int32),
+                ("lambda_min", ct.c_double), ("lambda_max", ct.c_double)]
+
+
+class Diag(ct.Structure):
+    _fields_ = [("step", ct.c_int64), ("mass", ct.c_double), ("mean_ke", ct.c_double), ("max_u", ct.c_double),
+                ("band_ke", ct.c_double), ("band_nodes", ct.c_int64), ("nonfinite", ct.c_int32), ("pad_", ct.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
+
+
+class KStat(ct.Structure):
+    _fields_ = [("name", ct.c_char * 32), ("launches", ct.c_int64), ("total_ms", ct.c_double),
+                ("bytes_per_launch", ct.c_double)]
+
+
+_lib = None
+_P = ct.c_void_p
+_D = ct.POINTER(ct.c_double)
+_I = ct.POINTER(ct.c_int32)
+
+_SIGNATURES = {
+    "felbm_create": ([ct.POINTER(Params), ct.POINTER(_P)], ct.c_int),
+    "felbm_last_error": ([_P], ct.c_char_p),
+    "felbm_upload_mesh": ([_P, ct.c_int64, _D, ct.c_int64, _I, ct.c_int64, _I, ct.c_double], ct.c_int),
+    "felbm_set_wetting": ([_P, _D], ct.c_int),
+    "felbm_init": ([_P, _D, _D, _D], ct.c_int),
+    "felbm_step": ([_P, ct.c_int64], ct.c_int),
+    "felbm_step_async": ([_P, ct.c_int64], ct.c_int),
+    "felbm_read": ([_P, ct.c_int32, _D], ct.c_int),
+    "felbm_read_populations": ([_P, _D], ct.c_int),
+    "felbm_step_debug": ([_P, _D, _D, _D], ct.c_int),
+    "felbm_set_band": ([_P, ct.c_double, ct.c_double, ct.c_double, ct.c_double], ct.c_int),
+    "felbm_diagnostics": ([_P, ct.POINTER(Diag)], ct.c_int),
+    "felbm_history": ([_P, ct.POINTER(Diag), ct.c_int64, ct.POINTER(ct.c_int64)], ct.c_int),
+    "felbm_state_bytes": ([_P], ct.c_int64),
+    "felbm_save_state": ([_P, ct.c_void_p, ct.c_int64], ct.c_int),
+    "felbm_load_state": ([_P, ct.c_void_p, ct.c_int64], ct.c_int),
+    "felbm_bind_stream": ([_P, ct.c_void_p], ct.c_int),
+    "felbm_kernel_timing": ([_P, ct.c_int32], ct.c_int),
+    "felbm_kernel_stats": ([_P, ct.POINTER(KStat), ct.c_int32, ct.POINTER(ct.c_int32)], ct.c_int),
+    "felbm_mesh_info": ([_P, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int64),
+                         ct.POINTER(ct.c_int64)], ct.c_int),
+    "felbm_validate_mesh": ([ct.c_int64, _D, ct.c_int64, _I, ct.c_int64, _I, ct.c_double, ct.c_char_p, ct.c_int32],
+                            ct.c_int),
+    "felbm_destroy": ([_P], None),
+}
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load_library() -> ct.CDLL:
+    """Load libfelbm.so from the package tree; raises if it was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"{_LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(python -m paper_1708_04678_amd.build)")
+        lib = ct.CDLL(_LIB_PATH)
+        for name, (args, res) in _SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+    return _lib
+
+
+def validate_mesh(xy, tri, wall_edges, period_x=0.0):
+    """Host-side mesh validation (no device needed); returns (code, message)."""
+    lib = load_library()
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    we = np.ascontiguousarray(wall_edges, dtype=np.int32).reshape(-1, 2)
+    msg = ct.create_string_buffer(256)
+    rc = lib.felbm_validate_mesh(xy.shape[0], xy.ctypes.data_as(_D), tri.shape[0], tri.ctypes.data_as(_I),
+                                 we.shape[0], we.ctypes.data_as(_I), float(period_x), msg, 256)
+    return rc, msg.value.decode()
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_D)
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None and a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+class Context:
+    """One FE-LBM simulation on the current HIP device (see include/felbm.h)."""
+
+    def __init__(self, *, sigma, xi, mobility, rho_l, rho_v, nu_l, nu_v, dt, precision="fp64",
+                 solver_sweeps=28, lambda_min=0.0, lambda_max=0.0):
+        lib = load_library()
+        prec = {"fp64": FP64, "fp32": FP32}[precision] if isinstance(precision, str) else int(precision)
+        self.params = Params(sigma, xi, mobility, rho_l, rho_v, nu_l, nu_v, dt, prec, int(solver_sweeps),
+                             lambda_min, lambda_max)
+        h = _P()
+        rc = lib.felbm_create(ct.byref(self.params), ct.byref(h))
+        if rc != 0:
+            raise FelbmError(rc, lib.felbm_last_error(None).decode())
+        self._lib, self._h = lib, h
+        self.n_nodes = self.n_tris = 0
+
+    def _check(self, rc):
+        if rc != 0:
+            raise FelbmError(rc, self._lib.felbm_last_error(self._h).decode())
+
+    # -- setup -------------------------------------------------------------
+    def upload_mesh(self, xy, tri, wall_edges, period_x=0.0):
+        xy = _f64(xy)
+        tri = np.ascontiguousarray(tri, dtype=np.int32)
+        we = np.ascontiguousarray(wall_edges, dtype=np.int32).reshape(-1, 2)
+        self._check(self._lib.felbm_upload_mesh(self._h, xy.shape[0], _dptr(xy), tri.shape[0], tri.ctypes.data_as(_I),
+                                                we.shape[0], we.ctypes.data_as(_I), float(period_x)))
+        self.n_nodes, self.n_tris = xy.shape[0], tri.shape[0]
+
+    def set_wetting(self, omega_c):
+        om = _f64(omega_c, (self.n_nodes,))
+        self._check(self._lib.felbm_set_wetting(self._h, _dptr(om)))
+
+    def init(self, C, u=None, p=None):
+        C = _f64(C, (self.n_nodes,))
+        u = None if u is None else _f64(u, (self.n_nodes, 2))
+        p = None if p is None else _f64(p, (self.n_nodes,))
+        self._check(self._lib.felbm_init(self._h, _dptr(C), None if u is None else _dptr(u),
+                                         None if p is None else _dptr(p)))
+
+    # -- stepping ----------------------------------------------------------
+    def step(self, n=1):
+        self._check(self._lib.felbm_step(self._h, int(n)))
+
+    def step_async(self, n=1):
+        self._check(self._lib.felbm_step_async(self._h, int(n)))
+
+    def step_debug(self):
+        N = self.n_nodes
+        hat, rhs, d = (np.empty((18, N)) for _ in range(3))
+        self._check(self._lib.felbm_step_debug(self._h, _dptr(hat), _dptr(rhs), _dptr(d)))
+        return hat, rhs, d
+
+    # -- read back ---------------------------------------------------------
+    def read(self, field):
+        fid = FIELDS[field] if isinstance(field, str) else int(field)
+        out = np.empty(self.n_tris if fid == FIELDS["LAPMU"] else self.n_nodes)
+        self._check(self._lib.felbm_read(self._h, fid, _dptr(out)))
+        return out
+
+    def read_populations(self):
+        out = np.empty((18, self.n_nodes))
+        self._check(self._lib.felbm_read_populations(self._h, _dptr(out)))
+        return out
+
+    def set_band(self, xc, yc, R, w):
+        self._check(self._lib.felbm_set_band(self._h, xc, yc, R, w))
+
+    def diagnostics(self):
+        d = Diag()
+        self._check(self._lib.felbm_diagnostics(self._h, ct.byref(d)))
+        return d.as_dict()
+
+    def history(self, max_entries=16384):
+        buf = (Diag * max_entries)()
+        n = ct.c_int64()
+        self._check(self._lib.felbm_history(self._h, buf, max_entries, ct.byref(n)))
+        return [buf[k].as_dict() for k in range(n.value)]
+
+    def save_state(self) -> bytes:
+        nb = self._lib.felbm_state_bytes(self._h)
+        buf = ct.create_string_buffer(nb)
+        self._check(self._lib.felbm_save_state(self._h, buf, nb))
+        return buf.raw
+
+    def load_state(self, data: bytes):
+        buf = ct.create_string_buffer(data, len(data))
+        self._check(self._lib.felbm_load_state(self._h, buf, len(data)))
+
+    def bind_stream(self, stream_handle):
+        """stream_handle: a hipStream_t as an int (e.g. torch.cuda.current_stream().cuda_stream) or None."""
+        self._check(self._lib.felbm_bind_stream(self._h, None if stream_handle is None else ct.c_void_p(stream_handle)))
+
+    def kernel_timing(self, enable=True):
+        self._check(self._lib.felbm_kernel_timing(self._h, 1 if enable else 0))
+
+    def kernel_stats(self):
+        buf = (KStat * 32)()
+        n = ct.c_int32()
+        self._check(self._lib.felbm_kernel_stats(self._h, buf, 32, ct.byref(n)))
+        return [{"name": buf[k].name.decode(), "launches": buf[k].launches, "total_ms": buf[k].total_ms,
+                 "bytes_per_launch": buf[k].bytes_per_launch} for k in range(n.value)]
+
+    def mesh_info(self):
+        v = [ct.c_int64() for _ in range(4)]
+        self._check(self._lib.felbm_mesh_info(self._h, *[ct.byref(x) for x in v]))
+        return dict(zip(["n_nodes", "n_tris", "n_wall_edges", "mass_offdiag_nnz"], [x.value for x in v]))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.felbm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,222 @@
+"""GPU (HIP, through the C ABI) versus the FP64 CPU oracle, element by element.
+
+Tolerances.  In FP64 both sides evaluate the same formulas in a different
+order (gathers vs assembled sparse products, Chebyshev sweeps vs PCG), so
+they differ by rounding (~1e-16 relative per operation, a few hundred
+operations deep) plus the solver truncation: K = 32 Chebyshev sweeps on the
+spectrum [1/4, 1] leave a relative error <= 2 * 3^-32 ~ 1e-15 in the
+increment, and the oracle's PCG stops at 1e-13 relative residual (~1e-13 of
+the increment, which is itself ~1e-2 of the populations).  One step is
+therefore held to 1e-13 of max |psi|; the dissipative step does not amplify
+differences, so 10 and 200 steps are held to 1e-12 and 1e-11.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import log, make_ctx, rel, stack
+from oracle import Oracle
+from oracle import felbm_oracle as fo
+from workloads import config, droplet_field, make_physics, split_grid_mesh, uniform_rows, wetting_from_angles
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cfg1_theta60():
+    w = config(1)
+    om = wetting_from_angles(w.mesh, 60.0)
+    o = Oracle(w.mesh, w.phys, om)
+    return w, om, o
+
+
+def test_fields_after_init_match_oracle(cfg1_theta60):
+    w, om, o = cfg1_theta60
+    log("fields after init, workload 1, theta 60, fp64")
+    ctx = make_ctx(w.mesh, w.phys, om)
+    ctx.init(w.C0)
+    g, h = o.init_state(w.C0)
+    assert rel(ctx.read_populations(), stack(g, h)) < 1e-15
+    f = o.fields(g, h)
+    assert rel(ctx.read("C"), f["C"]) < 1e-14
+    assert rel(ctx.read("RHO"), f["rho"]) < 1e-14
+    assert np.abs(ctx.read("P") - f["p"]).max() < 1e-16
+    assert rel(ctx.read("LAPC"), f["lapC"]) < 1e-12
+    assert rel(ctx.read("MU"), f["mu"]) < 1e-12
+    assert rel(ctx.read("LAPMU"), f["lapmu"]) < 1e-11
+    ctx.close()
+
+
+def test_step_intermediates_match_oracle(cfg1_theta60):
+    w, om, o = cfg1_theta60
+    log("step intermediates after 5 steps, workload 1, fp64")
+    ctx = make_ctx(w.mesh, w.phys, om)
+    ctx.init(w.C0)
+    ctx.step(5)
+    g, h = o.init_state(w.C0)
+    g, h = o.run(g, h, 5)
+    hat, rhs, delta = ctx.step_debug()
+    _, _, f = o.step(g, h, return_fields=True)
+    assert rel(hat, stack(f["g_hat"], f["h_hat"])) < 1e-14
+    m = o.mat.lumped
+    b_over_m = stack(f["b_g"] / m[:, None], f["b_h"] / m[:, None])
+    assert np.abs(rhs - b_over_m).max() < 1e-12 * np.abs(b_over_m).max()
+    d_ref = stack(f["d_g"], f["d_h"])
+    interior = ~o.geo.is_wall_node
+    assert np.abs(delta[:, interior] - d_ref[:, interior]).max() < 1e-11 * np.abs(d_ref).max()
+    ctx.close()
+
+
+@pytest.mark.parametrize("steps,tol", [(1, 1e-13), (10, 1e-12), (200, 1e-11)])
+def test_full_step_parity_fp64(cfg1_theta60, steps, tol):
+    w, om, o = cfg1_theta60
+    log(f"full-step parity, workload 1 (2112 nodes), theta 60, fp64, {steps} steps")
+    ctx = make_ctx(w.mesh, w.phys, om)
+    ctx.init(w.C0)
+    ctx.step(steps)
+    g, h = o.init_state(w.C0)
+    g, h = o.run(g, h, steps)
+    err = rel(ctx.read_populations(), stack(g, h))
+    log(f"  max rel diff {err:.3e}")
+    assert err < tol
+    ctx.close()
+
+
+def test_ragged_and_closed_meshes():
+    # N not a multiple of 64, walls on all four sides, two droplets
+    for periodic, nx, ny in ((True, 37, 13), (False, 29, 11)):
+        log(f"ragged mesh parity periodic={periodic} {nx}x{ny}")
+        mesh = split_grid_mesh(float(nx), uniform_rows(float(ny - 1), ny), nx, seed=[nx], periodic=periodic)
+        phys = make_physics(sigma=0.01, m_rho=5.0, m_nu=2.0, dt=0.1)
+        om = wetting_from_angles(mesh, 70.0, 110.0)
+        C0 = droplet_field(mesh, [(nx / 3, 0.0, 4.0), (2 * nx / 3, ny - 1.0, 3.5)], phys.xi)
+        ctx = make_ctx(mesh, phys, om)
+        ctx.init(C0)
+        ctx.step(7)
+        o = Oracle(mesh, phys, om)
+        g, h = o.init_state(C0)
+        g, h = o.run(g, h, 7)
+        assert mesh.n_nodes % 64 != 0
+        assert rel(ctx.read_populations(), stack(g, h)) < 1e-12
+        ctx.close()
+
+
+@pytest.mark.parametrize("K", [0, 1, 2, 5])
+def test_short_solver_polynomials(K):
+    """K Chebyshev sweeps: the increment's error against the exact solve obeys
+    the Chebyshev bound 2/T_K(5/3) relative to the lumped-solve error."""
+    w = config(1)
+    om = wetting_from_angles(w.mesh, 60.0)
+    log(f"solver sweeps K={K}")
+    ctx = make_ctx(w.mesh, w.phys, om, sweeps=K)
+    ctx.init(w.C0)
+    ctx.step(3)
+    hat, rhs, delta = ctx.step_debug()
+    o = Oracle(w.mesh, w.phys, om)
+    m = o.mat.lumped
+    interior = ~o.geo.is_wall_node
+    bound = 1.0 / np.cosh(K * np.arccosh(5.0 / 3.0)) * 2.0
+    for a in (0, 5, 9, 14):
+        b = rhs[a] * m
+        exact, _ = fo.pcg(o.mat.M11, m, b, tol=1e-15)
+        e0 = rhs[a] - exact
+        eK = delta[a] - exact
+        # M11-weighted (energy) norms over interior nodes approximate the A-norm bound
+        n0 = np.sqrt(np.sum(m[interior] * e0[interior] ** 2))
+        nK = np.sqrt(np.sum(m[interior] * eK[interior] ** 2))
+        assert nK <= 2.0 * bound * n0 + 1e-15 * np.abs(exact).max()
+    ctx.close()
+
+
+def test_mass_conserved_fp64_and_fp32():
+    w = config(1)
+    om = wetting_from_angles(w.mesh, 60.0)
+    for prec, sweeps, bar in (("fp64", 32, 1e-13), ("fp32", 16, 1e-10)):
+        log(f"mass conservation 200 steps {prec}")
+        ctx = make_ctx(w.mesh, w.phys, om, precision=prec, sweeps=sweeps)
+        ctx.init(w.C0)
+        m0 = ctx.diagnostics()["mass"]
+        ctx.step(200)
+        m1 = ctx.diagnostics()["mass"]
+        log(f"  drift {abs(m1 - m0) / m0:.3e}")
+        assert abs(m1 - m0) / m0 < bar
+        ctx.close()
+
+
+def test_deterministic_and_checkpoint_resume():
+    w = config(1)
+    om = wetting_from_angles(w.mesh, 60.0)
+    for prec in ("fp64", "fp32"):
+        log(f"determinism and save/load {prec}")
+        a = make_ctx(w.mesh, w.phys, om, precision=prec, sweeps=16)
+        a.init(w.C0)
+        a.step(20)
+        ref = a.read_populations()
+        b = make_ctx(w.mesh, w.phys, om, precision=prec, sweeps=16)
+        b.init(w.C0)
+        b.step(10)
+        blob = b.save_state()
+        b.step(3)
+        b.load_state(blob)
+        b.step(10)
+        assert np.array_equal(b.read_populations(), ref)
+        assert b.diagnostics()["step"] == 20
+        a.close()
+        b.close()
+
+
+def test_diagnostics_match_oracle(cfg1_theta60):
+    w, om, o = cfg1_theta60
+    log("diagnostics vs oracle")
+    ctx = make_ctx(w.mesh, w.phys, om)
+    ctx.set_band(32.0, 0.0, 12.0, 4.0)
+    ctx.init(w.C0)
+    ctx.step(20)
+    g, h = o.init_state(w.C0)
+    g, h = o.run(g, h, 20)
+    d = ctx.diagnostics()
+    r = o.diagnostics(g, h, band=(32.0, 0.0, 12.0, 4.0))
+    assert abs(d["mass"] - r["mass"]) < 1e-12 * r["mass"]
+    assert abs(d["mean_ke"] - r["mean_ke"]) < 1e-9 * r["mean_ke"]
+    assert abs(d["max_u"] - r["max_u"]) < 1e-9 * r["max_u"]
+    assert abs(d["band_ke"] - r["band_ke"]) < 1e-9 * r["band_ke"]
+    hist = ctx.history()
+    assert [x["step"] for x in hist] == list(range(20))
+    ctx.close()
+
+
+def test_nonfinite_state_is_reported():
+    w = config(1)
+    log("non-finite detection")
+    ctx = make_ctx(w.mesh, w.phys, w.omega_c)
+    ctx.init(w.C0)
+    blob = bytearray(ctx.save_state())
+    # header is 32 bytes; poison one population value of node 100 (fp64)
+    off = 32 + 8 * 100
+    blob[off:off + 8] = np.array([np.nan]).tobytes()
+    ctx.load_state(bytes(blob))
+    import paper_1708_04678_amd as felbm
+    with pytest.raises(felbm.FelbmError) as ei:
+        ctx.step(2)
+    assert ei.value.name == "ENONFINITE"
+    ctx.close()
+
+
+def test_api_state_errors():
+    import paper_1708_04678_amd as felbm
+    w = config(1)
+    ctx = felbm.Context(sigma=0.01, xi=4.0, mobility=0.02, rho_l=1.0, rho_v=0.1, nu_l=0.1 / 3, nu_v=0.1 / 3, dt=0.1)
+    with pytest.raises(felbm.FelbmError) as ei:
+        ctx.step(1)
+    assert ei.value.name == "ESTATE"
+    ctx.upload_mesh(w.mesh.xy, w.mesh.tri, w.mesh.wall_edges, w.mesh.period_x)
+    with pytest.raises(felbm.FelbmError):
+        ctx.upload_mesh(w.mesh.xy, w.mesh.tri, w.mesh.wall_edges, w.mesh.period_x)
+    with pytest.raises(felbm.FelbmError) as ei:
+        ctx.read("C")
+    assert ei.value.name == "ESTATE"
+    bad = w.C0.copy()
+    bad[3] = np.inf
+    with pytest.raises(felbm.FelbmError) as ei:
+        ctx.init(bad)
+    assert ei.value.name == "EINVAL"
+    ctx.close()

@@ -85,8 +85,30 @@ def fourier_field(x: np.ndarray, period: float, seed, n_modes: int = 4) -> np.nd
     return f / np.max(np.abs(f))
 
 
-def config(cfg: int) -> Workload:
-    """Build workload 1..5."""
+def config(cfg: int, row_limit: int | None = None) -> Workload:
+    """Build workload 1..5.  row_limit keeps only the bottom row_limit node
+    rows of the mesh (the top row becomes the top wall): a bounded sample of
+    the same workload for CPU timing."""
+    w = _config(cfg)
+    if row_limit is None or row_limit >= w.mesh.nrows:
+        return w
+    m = w.mesh
+    keep = row_limit * m.ncols
+    tri_keep = np.all(m.tri < keep, axis=1)
+    top = (row_limit - 1) * m.ncols
+    bi = np.arange(m.ncols - (0 if m.period_x > 0 else 1))
+    bi1 = (bi + 1) % m.ncols if m.period_x > 0 else bi + 1
+    walls = np.concatenate([m.wall_edges[m.wall_side == 0], np.stack([top + bi, top + bi1], 1)]).astype(np.int32)
+    side = np.concatenate([np.zeros(int((m.wall_side == 0).sum()), np.int8), np.ones(bi.size, np.int8)])
+    sub = Mesh(xy=m.xy[:keep].copy(), tri=m.tri[tri_keep].copy(), wall_edges=walls, period_x=m.period_x,
+               ncols=m.ncols, nrows=row_limit, wall_side=side)
+    om = w.omega_c[:keep].copy()
+    om[sub.wall_nodes(1)] = 0.0
+    return Workload(w.name + f"-bottom-{row_limit}-rows", sub, w.phys, w.C0[:keep].copy(), om, w.steps, w.droplets,
+                    dict(w.extra))
+
+
+def _config(cfg: int) -> Workload:
     if cfg == 1:
         mesh = split_grid_mesh(64.0, uniform_rows(32.0, 33), 64, seed=[1])
         phys = make_physics(sigma=0.01, m_rho=10.0, m_nu=1.0, dt=0.1)
