@@ -117,7 +117,10 @@ def main():
     from workloads import config
 
     torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream().cuda_stream
+    # a dedicated (default-priority) torch stream: the library and the timing events share it
+    tstream = torch.cuda.Stream()
+    torch.cuda.set_stream(tstream)
+    stream = tstream.cuda_stream
     log(f"workload {args.config}")
     w = config(args.config)
     N, E = w.mesh.n_nodes, w.mesh.n_tris

@@ -60,8 +60,12 @@ enum { FELBM_FP64 = 0, FELBM_FP32 = 1 };
  *   dt             time step
  *   precision      FELBM_FP64: everything in double.  FELBM_FP32: populations,
  *                  velocity/pressure fields, forces, streaming and solve in
- *                  float; the chain C -> lap C -> mu -> grad mu -> lap mu and
- *                  all global reductions in double.
+ *                  float; the chain C -> lap C -> mu -> grad mu -> lap mu,
+ *                  all global reductions and the conserved composition in
+ *                  double: C = sum_a h_a + r with a per-node FP64 remainder r,
+ *                  whose increment is the FP64 zeroth h-moment of the
+ *                  streaming right-hand side solved by the same sweeps with
+ *                  exactly mass-preserving column sums.
  *   solver_sweeps  K >= 0: the mass-matrix system M11 x = b is solved by K
  *                  preconditioned Richardson sweeps from x0 = b/m whose step
  *                  lengths are the reciprocal Chebyshev roots for the spectrum
@@ -162,13 +166,16 @@ int felbm_step_async(felbm_ctx* ctx, int64_t n_steps);
 int felbm_read(felbm_ctx* ctx, int32_t field, double* out);
 
 /* Copy the current populations to out [18][n_nodes] (g_0..g_8, h_0..h_8) as
- * double.  Errors: EINVAL, ESTATE. */
+ * double.  In FELBM_FP32 the composition is sum_a h_a plus an FP64 remainder
+ * (see felbm_params.precision), so FELBM_FIELD_C is the exact composition.
+ * Errors: EINVAL, ESTATE. */
 int felbm_read_populations(felbm_ctx* ctx, double* out);
 
 /* Advance one step and copy its intermediates (each may be NULL), all
  * [18][n_nodes] double: post-collision populations psi_hat (eqn::collide),
  * the lumped-scaled right-hand side b/m of eq:galerkin_lbm, and the solve's
- * increment delta with M11 delta = b (before the wall operator). */
+ * increment delta with M11 delta = b (NaN at wall nodes, where the wall
+ * operator has already been applied). */
 int felbm_step_debug(felbm_ctx* ctx, double* psi_hat, double* rhs_over_m, double* delta);
 
 /* Reduction band for band_ke: nodes with R - w <= |x - (xc, yc)| <= R + w

@@ -77,6 +77,8 @@ struct felbm_ctx {
   void *pop = nullptr, *f = nullptr, *xa = nullptr, *xb = nullptr;
   double *Cn = nullptr, *mu = nullptr, *lapC = nullptr, *gC = nullptr, *gmu = nullptr, *lapmu = nullptr;
   void *pn = nullptr, *uxn = nullptr, *uyn = nullptr, *gp = nullptr;
+  // FP32 only: FP64 composition transport (remainder, rhs moment, iterates, diagonal)
+  double *rC = nullptr, *fC = nullptr, *xCa = nullptr, *xCb = nullptr, *dlt = nullptr;
   double* partials = nullptr;
   DiagRecord* hist = nullptr;  // ring of per-step reductions
   DiagRecord* diag_now = nullptr;
@@ -144,18 +146,23 @@ hipEvent_t take_event(felbm_ctx* c) {
 // Launch a kernel on the context stream; with timing on, bracket it with
 // events recorded by the command processor at kernel start and end.
 template <typename F, typename... Args>
-int launch(felbm_ctx* c, int kid, F kernel, int grid, Args... args) {
+int launch_bs(felbm_ctx* c, int kid, F kernel, int grid, int block, Args... args) {
   if (c->timing) {
     hipEvent_t s = take_event(c), t = take_event(c);
     if (!s || !t) return fail(c, FELBM_EDEVICE, "hipEventCreate failed");
-    hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(BLOCK), 0, c->stream, s, t, 0, args...);
+    hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, c->stream, s, t, 0, args...);
     c->pending.push_back({kid, s, t});
   } else {
-    hipLaunchKernelGGL(kernel, dim3(grid), dim3(BLOCK), 0, c->stream, args...);
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, c->stream, args...);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(c, FELBM_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
   return FELBM_OK;
+}
+
+template <typename F, typename... Args>
+int launch(felbm_ctx* c, int kid, F kernel, int grid, Args... args) {
+  return launch_bs(c, kid, kernel, grid, BLOCK, args...);
 }
 
 int harvest_timing(felbm_ctx* c) {
@@ -190,9 +197,10 @@ void set_kernel_bytes(felbm_ctx* c) {
   c->kstat[K_GRADMU].bytes = E * (12 + 48 + 16) + N * 8;
   c->kstat[K_LAPMU].bytes = E * (12 + 48 + 16 + 8);
   c->kstat[K_RHS].bytes = 2 * pops + N * (4 + 8 + 8 + 2 * s + 8) + 3 * E * 4 + E * (12 + 7 * s + 16 + 2 * s + 8);
-  c->kstat[K_SWEEP_FIRST].bytes = 2 * pops + mat;
-  c->kstat[K_SWEEP_MID].bytes = 3 * pops + mat;
-  c->kstat[K_SWEEP_LAST].bytes = 4 * pops + mat + N;
+  const double cons = c->prm.precision == FELBM_FP32 ? 8.0 * N : 0.0;  // one FP64 composition vector
+  c->kstat[K_SWEEP_FIRST].bytes = 2 * pops + mat + 3 * cons;
+  c->kstat[K_SWEEP_MID].bytes = 3 * pops + mat + 4 * cons;
+  c->kstat[K_SWEEP_LAST].bytes = 4 * pops + mat + N + 5 * cons;
 }
 
 template <typename real>
@@ -202,12 +210,12 @@ int enqueue_fields(felbm_ctx* c, bool collide, bool record, DiagRecord* rec_targ
   real* pop = (real*)c->pop;
   if (collide)
     TRY(launch(c, K_MOMENTS, k_moments<real, true>, gN, pop, N, Np, c->sp, c->Cn, (real*)c->pn, (real*)c->uxn,
-               (real*)c->uyn, (const double*)c->mass, (const double*)c->xy, c->band, c->partials));
+               (real*)c->uyn, (const double*)c->mass, (const double*)c->xy, c->band, (const double*)c->rC, c->partials));
   else
     TRY(launch(c, K_MOMENTS, k_moments<real, false>, gN, pop, N, Np, c->sp, c->Cn, (real*)c->pn, (real*)c->uxn,
-               (real*)c->uyn, (const double*)c->mass, (const double*)c->xy, c->band, c->partials));
+               (real*)c->uyn, (const double*)c->mass, (const double*)c->xy, c->band, (const double*)c->rC, c->partials));
   if (record)
-    TRY(launch(c, K_REDUCE, k_reduce_final, 1, (const double*)c->partials, gN, N, (int64_t)c->step, rec_target,
+    TRY(launch_bs(c, K_REDUCE, k_reduce_final, 1, RBLOCK, (const double*)c->partials, gN, N, (int64_t)c->step, rec_target,
                c->first_bad));
   TRY(launch(c, K_GRAD, k_elem_grad<real>, gE, E, (const int*)c->tri, (const double*)c->geo, (const double*)c->Cn,
              (const real*)c->pn, c->gC, (real*)c->gp));
@@ -222,40 +230,64 @@ int enqueue_fields(felbm_ctx* c, bool collide, bool record, DiagRecord* rec_targ
 }
 
 template <typename real>
-int enqueue_step(felbm_ctx* c) {
+int enqueue_rhs(felbm_ctx* c) {
   const int gN = grid_for(c->N);
   const int N = (int)c->N, Np = (int)c->Np, E = (int)c->E;
-  TRY(enqueue_fields<real>(c, true, true, c->hist + (c->step % c->hist_cap)));
-  real* pop = (real*)c->pop;
-  real* f = (real*)c->f;
-  TRY(launch(c, K_RHS, k_rhs<real>, gN, N, Np, E, (const int*)c->n2e_ptr, (const int*)c->n2e, (const int*)c->tri,
-             (const real*)c->geor, (const double*)c->gC, (const real*)c->gp, (const double*)c->lapmu,
-             (const double*)c->Cn, (const real*)c->uxn, (const real*)c->uyn, (const double*)c->mu, (const real*)pop,
-             (const double*)c->mass, c->sp, f));
+  return launch(c, K_RHS, k_rhs<real>, gN, N, Np, E, (const int*)c->n2e_ptr, (const int*)c->n2e, (const int*)c->tri,
+                (const real*)c->geor, (const double*)c->geo, (const double*)c->gC, (const real*)c->gp,
+                (const double*)c->lapmu, (const double*)c->Cn, (const real*)c->uxn, (const real*)c->uyn,
+                (const double*)c->mu, (const real*)c->pop, (const double*)c->mass, c->sp, (real*)c->f, c->fC);
+}
+
+// K Chebyshev-step Richardson sweeps on f, then psi_bar^{n+1} = psi_hat + x_K
+// and the wall operator (fused into the last sweep)
+template <typename real>
+int enqueue_solve(felbm_ctx* c) {
+  const int gN = grid_for(c->N);
+  const int N = (int)c->N, Np = (int)c->Np;
   const int K = c->prm.solver_sweeps;
   const int* sp = c->sell_ptr;
   const int* sc = c->sell_col;
   const real* sv = (const real*)c->sell_val;
-  real *xa = (real*)c->xa, *xb = (real*)c->xb;
+  real *pop = (real*)c->pop, *f = (real*)c->f, *xa = (real*)c->xa, *xb = (real*)c->xb;
   const uint8_t* wall = c->is_wall;
+  ConsArgs cs{c->fC, nullptr, nullptr, c->dlt, c->Cn, c->rC, 0.0};
   if (K == 0) {
-    TRY(launch(c, K_SWEEP_LAST, k_sweep<real, 4>, gN, N, Np, sp, sc, sv, (const real*)f, (const real*)nullptr,
-               (real*)nullptr, pop, wall, (real)0));
-  } else if (K == 1) {
-    TRY(launch(c, K_SWEEP_LAST, k_sweep<real, 3>, gN, N, Np, sp, sc, sv, (const real*)f, (const real*)nullptr,
-               (real*)nullptr, pop, wall, (real)c->cheb_w[0]));
-  } else {
-    TRY(launch(c, K_SWEEP_FIRST, k_sweep<real, 0>, gN, N, Np, sp, sc, sv, (const real*)f, (const real*)nullptr, xa,
-               pop, wall, (real)c->cheb_w[0]));
-    real *xin = xa, *xout = xb;
-    for (int j = 1; j < K - 1; ++j) {
-      TRY(launch(c, K_SWEEP_MID, k_sweep<real, 1>, gN, N, Np, sp, sc, sv, (const real*)f, (const real*)xin, xout, pop,
-                 wall, (real)c->cheb_w[j]));
-      std::swap(xin, xout);
-    }
-    TRY(launch(c, K_SWEEP_LAST, k_sweep<real, 2>, gN, N, Np, sp, sc, sv, (const real*)f, (const real*)xin,
-               (real*)nullptr, pop, wall, (real)c->cheb_w[K - 1]));
+    return launch(c, K_SWEEP_LAST, k_sweep<real, 4>, gN, N, Np, sp, sc, sv, (const real*)f, (const real*)nullptr,
+                  (real*)nullptr, pop, wall, (real)0, cs);
   }
+  if (K == 1) {
+    cs.w = c->cheb_w[0];
+    return launch(c, K_SWEEP_LAST, k_sweep<real, 3>, gN, N, Np, sp, sc, sv, (const real*)f, (const real*)nullptr,
+                  (real*)nullptr, pop, wall, (real)c->cheb_w[0], cs);
+  }
+  cs.w = c->cheb_w[0];
+  cs.xCout = c->xCa;
+  TRY(launch(c, K_SWEEP_FIRST, k_sweep<real, 0>, gN, N, Np, sp, sc, sv, (const real*)f, (const real*)nullptr, xa, pop,
+             wall, (real)c->cheb_w[0], cs));
+  real *xin = xa, *xout = xb;
+  double *cin = c->xCa, *cout = c->xCb;
+  for (int j = 1; j < K - 1; ++j) {
+    cs.w = c->cheb_w[j];
+    cs.xCin = cin;
+    cs.xCout = cout;
+    TRY(launch(c, K_SWEEP_MID, k_sweep<real, 1>, gN, N, Np, sp, sc, sv, (const real*)f, (const real*)xin, xout, pop,
+               wall, (real)c->cheb_w[j], cs));
+    std::swap(xin, xout);
+    std::swap(cin, cout);
+  }
+  cs.w = c->cheb_w[K - 1];
+  cs.xCin = cin;
+  cs.xCout = nullptr;
+  return launch(c, K_SWEEP_LAST, k_sweep<real, 2>, gN, N, Np, sp, sc, sv, (const real*)f, (const real*)xin,
+                (real*)nullptr, pop, wall, (real)c->cheb_w[K - 1], cs);
+}
+
+template <typename real>
+int enqueue_step(felbm_ctx* c) {
+  TRY(enqueue_fields<real>(c, true, true, c->hist + (c->step % c->hist_cap)));
+  TRY(enqueue_rhs<real>(c));
+  TRY(enqueue_solve<real>(c));
   c->step += 1;
   return FELBM_OK;
 }
@@ -421,6 +453,13 @@ int felbm_upload_mesh(felbm_ctx* c, int64_t n_nodes, const double* xy, int64_t n
   TRY(dalloc(c, &c->gmu, 2 * E));
   TRY(dalloc(c, &c->lapmu, E));
   TRY(dalloc_bytes(c, &c->gp, 2 * E * rs));
+  if (c->prm.precision == FELBM_FP32) {
+    TRY(dalloc(c, &c->rC, Np));
+    TRY(dalloc(c, &c->fC, Np));
+    TRY(dalloc(c, &c->xCa, Np));
+    TRY(dalloc(c, &c->xCb, Np));
+    TRY(dalloc(c, &c->dlt, Np));
+  }
   TRY(dalloc(c, &c->partials, (size_t)NRED * grid_for(N)));
   TRY(dalloc(c, &c->hist, c->hist_cap));
   TRY(dalloc(c, &c->diag_now, 1));
@@ -444,7 +483,24 @@ int felbm_upload_mesh(felbm_ctx* c, int64_t n_nodes, const double* xy, int64_t n
     std::vector<float> g32(m.geo.begin(), m.geo.end()), v32(m.sell_val.begin(), m.sell_val.end());
     TRY(upload(c, (float*)c->geor, g32));
     TRY(upload(c, (float*)c->sell_val, v32));
-    HIP_OK(c, hipStreamSynchronize(c->stream));  // g32/v32 are about to go out of scope
+    // diagonal of the FP64 composition sweep: dlt_j = 1 - sum_i m_i a_ij / m_j
+    // with the stored (FP32) a_ij, so that m^T A = m^T exactly
+    std::vector<double> colsum(Np, 0.0), dlt(Np, 0.5);
+    const int64_t nslices = Np / 64;
+    for (int64_t s = 0; s < nslices; ++s) {
+      const int64_t base = m.sell_ptr[s], w = (m.sell_ptr[s + 1] - base) / 64;
+      for (int lane = 0; lane < 64; ++lane) {
+        const int64_t i = s * 64 + lane;
+        if (i >= N) continue;
+        for (int64_t k = 0; k < w; ++k) {
+          const int64_t idx = base + k * 64 + lane;
+          colsum[m.sell_col[idx]] += m.mass[i] * (double)v32[idx];
+        }
+      }
+    }
+    for (int64_t j = 0; j < N; ++j) dlt[j] = 1.0 - colsum[j] / m.mass[j];
+    TRY(upload(c, c->dlt, dlt));
+    HIP_OK(c, hipStreamSynchronize(c->stream));  // host vectors are about to go out of scope
   }
   std::vector<double> zeros(N, 0.0);
   TRY(upload(c, c->bc, zeros));
@@ -504,10 +560,10 @@ int felbm_init(felbm_ctx* c, const double* C, const double* u, const double* p) 
   const int g = (int)((N + BLOCK - 1) / BLOCK);
   if (c->prm.precision == FELBM_FP64)
     hipLaunchKernelGGL(k_init<double>, dim3(g), dim3(BLOCK), 0, c->stream, (int)N, (int)c->Np, c->sp, (const double*)dC,
-                       (const double*)dU, (const double*)dP, (const uint8_t*)c->is_wall, (double*)c->pop);
+                       (const double*)dU, (const double*)dP, (const uint8_t*)c->is_wall, (double*)c->pop, c->rC);
   else
     hipLaunchKernelGGL(k_init<float>, dim3(g), dim3(BLOCK), 0, c->stream, (int)N, (int)c->Np, c->sp, (const double*)dC,
-                       (const double*)dU, (const double*)dP, (const uint8_t*)c->is_wall, (float*)c->pop);
+                       (const double*)dU, (const double*)dP, (const uint8_t*)c->is_wall, (float*)c->pop, c->rC);
   HIP_OK(c, hipGetLastError());
   HIP_OK(c, hipFreeAsync(dC, c->stream));
   HIP_OK(c, hipFreeAsync(dU, c->stream));
@@ -581,66 +637,26 @@ int felbm_step_debug(felbm_ctx* c, double* psi_hat, double* rhs_over_m, double* 
   if (!c->has_state) return fail(c, FELBM_ESTATE, "step_debug: not initialised");
   // the step's pipeline, split after the right-hand side to capture psi_hat and b/m
   TRY(enqueue_fields_any(c, true, true, c->hist + (c->step % c->hist_cap)));
-  const int gN = grid_for(c->N);
-  const int N = (int)c->N, Np = (int)c->Np, E = (int)c->E;
   if (c->prm.precision == FELBM_FP64)
-    TRY(launch(c, K_RHS, k_rhs<double>, gN, N, Np, E, (const int*)c->n2e_ptr, (const int*)c->n2e, (const int*)c->tri,
-               (const double*)c->geor, (const double*)c->gC, (const double*)c->gp, (const double*)c->lapmu,
-               (const double*)c->Cn, (const double*)c->uxn, (const double*)c->uyn, (const double*)c->mu,
-               (const double*)c->pop, (const double*)c->mass, c->sp, (double*)c->f));
+    TRY(enqueue_rhs<double>(c));
   else
-    TRY(launch(c, K_RHS, k_rhs<float>, gN, N, Np, E, (const int*)c->n2e_ptr, (const int*)c->n2e, (const int*)c->tri,
-               (const float*)c->geor, (const double*)c->gC, (const float*)c->gp, (const double*)c->lapmu,
-               (const double*)c->Cn, (const float*)c->uxn, (const float*)c->uyn, (const double*)c->mu,
-               (const float*)c->pop, (const double*)c->mass, c->sp, (float*)c->f));
+    TRY(enqueue_rhs<float>(c));
   std::vector<double> hat(18 * c->N);
   TRY(copy_pops_out(c, c->pop, hat.data()));
   if (psi_hat) std::memcpy(psi_hat, hat.data(), hat.size() * 8);
   if (rhs_over_m) TRY(copy_pops_out(c, c->f, rhs_over_m));
-  // finish the step: run only the solve and update on the already computed f
-  {
-    const int K = c->prm.solver_sweeps;
-    auto run = [&](auto tag) -> int {
-      using real = decltype(tag);
-      const int* sp = c->sell_ptr;
-      const int* sc = c->sell_col;
-      const real* sv = (const real*)c->sell_val;
-      real *pop = (real*)c->pop, *f = (real*)c->f, *xa = (real*)c->xa, *xb = (real*)c->xb;
-      const uint8_t* wall = c->is_wall;
-      if (K == 0) {
-        TRY(launch(c, K_SWEEP_LAST, k_sweep<real, 4>, gN, N, Np, sp, sc, sv, (const real*)f, (const real*)nullptr,
-                   (real*)nullptr, pop, wall, (real)0));
-      } else if (K == 1) {
-        TRY(launch(c, K_SWEEP_LAST, k_sweep<real, 3>, gN, N, Np, sp, sc, sv, (const real*)f, (const real*)nullptr,
-                   (real*)nullptr, pop, wall, (real)c->cheb_w[0]));
-      } else {
-        TRY(launch(c, K_SWEEP_FIRST, k_sweep<real, 0>, gN, N, Np, sp, sc, sv, (const real*)f, (const real*)nullptr, xa,
-                   pop, wall, (real)c->cheb_w[0]));
-        real *xin = xa, *xout = xb;
-        for (int j = 1; j < K - 1; ++j) {
-          TRY(launch(c, K_SWEEP_MID, k_sweep<real, 1>, gN, N, Np, sp, sc, sv, (const real*)f, (const real*)xin, xout,
-                     pop, wall, (real)c->cheb_w[j]));
-          std::swap(xin, xout);
-        }
-        TRY(launch(c, K_SWEEP_LAST, k_sweep<real, 2>, gN, N, Np, sp, sc, sv, (const real*)f, (const real*)xin,
-                   (real*)nullptr, pop, wall, (real)c->cheb_w[K - 1]));
-      }
-      return FELBM_OK;
-    };
-    if (c->prm.precision == FELBM_FP64)
-      TRY(run(double{}));
-    else
-      TRY(run(float{}));
-  }
+  if (c->prm.precision == FELBM_FP64)
+    TRY(enqueue_solve<double>(c));
+  else
+    TRY(enqueue_solve<float>(c));
   c->step += 1;
   if (delta) {
     std::vector<double> after(18 * c->N);
     TRY(copy_pops_out(c, c->pop, after.data()));
     std::vector<uint8_t> wall(c->N);
     HIP_OK(c, hipMemcpy(wall.data(), c->is_wall, c->N, hipMemcpyDeviceToHost));
-    // delta = psi_bar^{n+1} - psi_hat away from walls; at wall nodes the wall
-    // operator has been applied after the update, so report the pre-wall value
-    // reconstructed only where it is unambiguous (interior nodes)
+    // delta = psi_bar^{n+1} - psi_hat at interior nodes; wall nodes get NaN
+    // because the wall operator has already been applied there
     for (int64_t a = 0; a < 18; ++a)
       for (int64_t i = 0; i < c->N; ++i)
         delta[a * c->N + i] = wall[i] ? std::nan("") : after[a * c->N + i] - hat[a * c->N + i];
@@ -680,11 +696,11 @@ int felbm_diagnostics(felbm_ctx* c, felbm_diag* out) {
   HIP_OK(c, hipMemcpyAsync(scratch_bad, &zero, sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
   if (c->prm.precision == FELBM_FP64)
     TRY(launch(c, K_MOMENTS, k_moments<double, false>, gN, (double*)c->pop, N, Np, c->sp, c->Cn, (double*)c->pn,
-               (double*)c->uxn, (double*)c->uyn, (const double*)c->mass, (const double*)c->xy, c->band, c->partials));
+               (double*)c->uxn, (double*)c->uyn, (const double*)c->mass, (const double*)c->xy, c->band, (const double*)c->rC, c->partials));
   else
     TRY(launch(c, K_MOMENTS, k_moments<float, false>, gN, (float*)c->pop, N, Np, c->sp, c->Cn, (float*)c->pn,
-               (float*)c->uxn, (float*)c->uyn, (const double*)c->mass, (const double*)c->xy, c->band, c->partials));
-  TRY(launch(c, K_REDUCE, k_reduce_final, 1, (const double*)c->partials, gN, N, (int64_t)c->step, c->diag_now,
+               (float*)c->uxn, (float*)c->uyn, (const double*)c->mass, (const double*)c->xy, c->band, (const double*)c->rC, c->partials));
+  TRY(launch_bs(c, K_REDUCE, k_reduce_final, 1, RBLOCK, (const double*)c->partials, gN, N, (int64_t)c->step, c->diag_now,
              scratch_bad));
   HIP_OK(c, hipMemcpyAsync(out, c->diag_now, sizeof(felbm_diag), hipMemcpyDeviceToHost, c->stream));
   HIP_OK(c, hipFreeAsync(scratch_bad, c->stream));
@@ -709,18 +725,27 @@ int felbm_history(felbm_ctx* c, felbm_diag* out, int64_t max_entries, int64_t* n
   return FELBM_OK;
 }
 
+namespace {
+int64_t payload_bytes(const felbm_ctx* c) {
+  // populations in compute precision, plus the FP64 composition remainder in FP32 mode
+  return 18 * c->Np * (int64_t)c->rs + (c->prm.precision == FELBM_FP32 ? c->Np * 8 : 0);
+}
+}  // namespace
+
 int64_t felbm_state_bytes(const felbm_ctx* c) {
   if (!c || !c->has_mesh) return 0;
-  return (int64_t)sizeof(StateHeader) + 18 * c->Np * (int64_t)c->rs;
+  return (int64_t)sizeof(StateHeader) + payload_bytes(c);
 }
 
 int felbm_save_state(felbm_ctx* c, void* buf, int64_t bytes) {
   if (!c) return FELBM_EINVAL;
   if (!c->has_state) return fail(c, FELBM_ESTATE, "save_state: not initialised");
   if (!buf || bytes < felbm_state_bytes(c)) return fail(c, FELBM_EINVAL, "save_state: buffer too small");
-  StateHeader h{kStateMagic, c->prm.precision, c->N, c->step, 18 * c->Np * (int64_t)c->rs};
+  StateHeader h{kStateMagic, c->prm.precision, c->N, c->step, payload_bytes(c)};
   std::memcpy(buf, &h, sizeof(h));
-  HIP_OK(c, hipMemcpyAsync((char*)buf + sizeof(h), c->pop, h.payload_bytes, hipMemcpyDeviceToHost, c->stream));
+  const int64_t pb = 18 * c->Np * (int64_t)c->rs;
+  HIP_OK(c, hipMemcpyAsync((char*)buf + sizeof(h), c->pop, pb, hipMemcpyDeviceToHost, c->stream));
+  if (c->rC) HIP_OK(c, hipMemcpyAsync((char*)buf + sizeof(h) + pb, c->rC, c->Np * 8, hipMemcpyDeviceToHost, c->stream));
   HIP_OK(c, hipStreamSynchronize(c->stream));
   return FELBM_OK;
 }
@@ -732,9 +757,11 @@ int felbm_load_state(felbm_ctx* c, const void* buf, int64_t bytes) {
   StateHeader h;
   std::memcpy(&h, buf, sizeof(h));
   if (h.magic != kStateMagic || h.precision != c->prm.precision || h.n_nodes != c->N ||
-      h.payload_bytes != 18 * c->Np * (int64_t)c->rs)
+      h.payload_bytes != payload_bytes(c))
     return fail(c, FELBM_EINVAL, "load_state: header does not match this context");
-  HIP_OK(c, hipMemcpyAsync(c->pop, (const char*)buf + sizeof(h), h.payload_bytes, hipMemcpyHostToDevice, c->stream));
+  const int64_t pb = 18 * c->Np * (int64_t)c->rs;
+  HIP_OK(c, hipMemcpyAsync(c->pop, (const char*)buf + sizeof(h), pb, hipMemcpyHostToDevice, c->stream));
+  if (c->rC) HIP_OK(c, hipMemcpyAsync(c->rC, (const char*)buf + sizeof(h) + pb, c->Np * 8, hipMemcpyHostToDevice, c->stream));
   const int32_t minus1 = -1;
   HIP_OK(c, hipMemcpyAsync(c->first_bad, &minus1, sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
   HIP_OK(c, hipStreamSynchronize(c->stream));

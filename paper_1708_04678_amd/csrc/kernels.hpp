@@ -92,12 +92,20 @@ constexpr int NRED = 6;  // mass, sum rho|u|^2, max|u|, band sum, band count, no
 // ----------------------------------------------------------------------------
 // Reads the state psi_bar, writes the nodal fields and (COLLIDE) psi_hat in
 // place; also writes per-block partials of the FP64 reductions of the state.
+// In FP32 the composition is C = sum_a h_a + r with the FP64 remainder r
+// (rC) carried between steps, see k_sweep.
+template <typename real>
+struct Conserve {
+  static constexpr bool on = sizeof(real) == 4;
+};
+
 template <typename real, bool COLLIDE>
 __global__ void __launch_bounds__(BLOCK) k_moments(real* __restrict__ pop, int N, int Np, StepParams P,
                                                   double* __restrict__ Cn, real* __restrict__ pn,
                                                   real* __restrict__ uxn, real* __restrict__ uyn,
                                                   const double* __restrict__ mass, const double* __restrict__ xy,
-                                                  Band band, double* __restrict__ partials) {
+                                                  Band band, const double* __restrict__ rC,
+                                                  double* __restrict__ partials) {
   const int blk = xcd_block();
   const int i = blk * BLOCK + threadIdx.x;
   double red[NRED] = {0, 0, 0, 0, 0, 0};
@@ -117,6 +125,7 @@ __global__ void __launch_bounds__(BLOCK) k_moments(real* __restrict__ pop, int N
       if (ex(a)) jx += ex(a) > 0 ? g[a] : -g[a];
       if (ey(a)) jy += ey(a) > 0 ? g[a] : -g[a];
     }
+    if (Conserve<real>::on) C += rC[i];
     const real rho = (real)(C * P.rho_l + (1.0 - C) * P.rho_v);
     const real ux = (real)3.0 * jx / rho, uy = (real)3.0 * jy / rho;  // rho u = sum e g / c_s^2
     Cn[i] = C;
@@ -165,18 +174,28 @@ struct DiagRecord {  // mirrors felbm_diag
   int32_t nonfinite, pad_;
 };
 
-// Second, fixed-order pass over the block partials (one block).
-__global__ void __launch_bounds__(BLOCK) k_reduce_final(const double* __restrict__ partials, int nblk, int N,
-                                                         int64_t step, DiagRecord* __restrict__ out,
-                                                         int* __restrict__ first_bad) {
+// Second, fixed-order pass over the block partials (one block of RBLOCK
+// threads, four independent accumulators per thread to hide load latency).
+constexpr int RBLOCK = 1024;
+__global__ void __launch_bounds__(RBLOCK) k_reduce_final(const double* __restrict__ partials, int nblk, int N,
+                                                          int64_t step, DiagRecord* __restrict__ out,
+                                                          int* __restrict__ first_bad) {
   double v[NRED];
 #pragma unroll
   for (int k = 0; k < NRED; ++k) {
-    double r = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += BLOCK) r = (k == 2) ? fmax(r, partials[k * nblk + b]) : r + partials[k * nblk + b];
-    v[k] = r;
+    const bool mx = (k == 2);
+    double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
+    const double* p = partials + (size_t)k * nblk;
+    int b = threadIdx.x;
+    for (; b + 3 * RBLOCK < nblk; b += 4 * RBLOCK) {
+      const double a0 = p[b], a1 = p[b + RBLOCK], a2 = p[b + 2 * RBLOCK], a3 = p[b + 3 * RBLOCK];
+      if (mx) { r0 = fmax(r0, a0); r1 = fmax(r1, a1); r2 = fmax(r2, a2); r3 = fmax(r3, a3); }
+      else { r0 += a0; r1 += a1; r2 += a2; r3 += a3; }
+    }
+    for (; b < nblk; b += RBLOCK) r0 = mx ? fmax(r0, p[b]) : r0 + p[b];
+    v[k] = mx ? fmax(fmax(r0, r1), fmax(r2, r3)) : (r0 + r1) + (r2 + r3);
   }
-  __shared__ double red[NRED][BLOCK / 64];
+  __shared__ double red[NRED][RBLOCK / 64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < NRED; ++k) {
@@ -188,7 +207,7 @@ __global__ void __launch_bounds__(BLOCK) k_reduce_final(const double* __restrict
     double r[NRED];
     for (int k = 0; k < NRED; ++k) {
       r[k] = red[k][0];
-      for (int w = 1; w < BLOCK / 64; ++w) r[k] = (k == 2) ? fmax(r[k], red[k][w]) : r[k] + red[k][w];
+      for (int w = 1; w < RBLOCK / 64; ++w) r[k] = (k == 2) ? fmax(r[k], red[k][w]) : r[k] + red[k][w];
     }
     DiagRecord d;
     d.step = step;
@@ -316,12 +335,14 @@ __global__ void __launch_bounds__(BLOCK) k_elem_lapmu(int E, const int* __restri
 template <typename real>
 __global__ void __launch_bounds__(BLOCK) k_rhs(int N, int Np, int E, const int* __restrict__ n2e_ptr,
                                               const int* __restrict__ n2e, const int* __restrict__ tri,
-                                              const real* __restrict__ geor, const double* __restrict__ gC,
-                                              const real* __restrict__ gp, const double* __restrict__ lapmu,
-                                              const double* __restrict__ Cn, const real* __restrict__ uxn,
-                                              const real* __restrict__ uyn, const double* __restrict__ mu,
-                                              const real* __restrict__ pop, const double* __restrict__ mass,
-                                              StepParams P, real* __restrict__ f) {
+                                              const real* __restrict__ geor, const double* __restrict__ geo,
+                                              const double* __restrict__ gC, const real* __restrict__ gp,
+                                              const double* __restrict__ lapmu, const double* __restrict__ Cn,
+                                              const real* __restrict__ uxn, const real* __restrict__ uyn,
+                                              const double* __restrict__ mu, const real* __restrict__ pop,
+                                              const double* __restrict__ mass, StepParams P, real* __restrict__ f,
+                                              double* __restrict__ fC) {
+  constexpr bool CONS = Conserve<real>::on;
   const int i = xcd_block() * BLOCK + threadIdx.x;
   if (i >= N) return;
   real own[NPOP], b[NPOP];
@@ -330,6 +351,7 @@ __global__ void __launch_bounds__(BLOCK) k_rhs(int N, int Np, int E, const int* 
     own[a] = pop[a * Np + i];
     b[a] = 0;
   }
+  double bC = 0.0;
   const real dt = (real)P.dt, c1 = dt / (real)3, c2 = (real)0.5 * dt * dt;
   const real drho_cs2 = (real)(CS2 * (P.rho_l - P.rho_v));
   const int beg = n2e_ptr[i], end = n2e_ptr[i + 1];
@@ -348,21 +370,30 @@ __global__ void __launch_bounds__(BLOCK) k_rhs(int N, int Np, int E, const int* 
     // barycentric values of the P1 fields and the element gradients
     const double Cb = (Cn[v[0]] + Cn[v[1]] + Cn[v[2]]) * (1.0 / 3.0);
     const double mub = (mu[v[0]] + mu[v[1]] + mu[v[2]]) * (1.0 / 3.0);
-    const real ubx = (uxn[v[0]] + uxn[v[1]] + uxn[v[2]]) / (real)3;
-    const real uby = (uyn[v[0]] + uyn[v[1]] + uyn[v[2]]) / (real)3;
-    const real rhob = (real)(Cb * P.rho_l + (1.0 - Cb) * P.rho_v);
+    const real ux0 = uxn[v[0]], ux1 = uxn[v[1]], ux2 = uxn[v[2]];
+    const real uy0 = uyn[v[0]], uy1 = uyn[v[1]], uy2 = uyn[v[2]];
+    const real ubx = (ux0 + ux1 + ux2) / (real)3, uby = (uy0 + uy1 + uy2) / (real)3;
+    const double rhobd = Cb * P.rho_l + (1.0 - Cb) * P.rho_v;
+    const real rhob = (real)rhobd;
     const double gCx = gC[e], gCy = gC[E + e];
     const real gpx = gp[e], gpy = gp[E + e];
     const real ax = drho_cs2 * (real)gCx, ay = drho_cs2 * (real)gCy;          // c_s^2 grad rho
     const real bx = (real)(mub * gCx), by = (real)(mub * gCy);                // mu grad C
     const real coef = (real)Cb / (rhob * (real)CS2);
     const real Xx = (real)gCx - coef * (gpx - bx), Xy = (real)gCy - coef * (gpy - by);
-    const real d = (real)(P.mobility * lapmu[e]);
+    const double lm = lapmu[e];
+    const real d = (real)(P.mobility * lm);
     const real uA = ubx * ax + uby * ay, uB = ubx * bx + uby * by, uX = ubx * Xx + uby * Xy;
     const real uu = ubx * ubx + uby * uby;
-    // gathered post-collision populations of the two other vertices
+    // post-collision populations of the two other vertices
     const int o1 = (l + 1) % 3, o2 = (l + 2) % 3;
     const int va = v[o1], vb = v[o2];
+    real ha[Q], hb[Q];
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      ha[a] = pop[(Q + a) * Np + va];
+      hb[a] = pop[(Q + a) * Np + vb];
+    }
     const real gla = gx[o1], glb = gx[o2], hla = gy[o1], hlb = gy[o2];
     const real gxl = gx[l], gyl = gy[l];
 #pragma unroll
@@ -375,15 +406,63 @@ __global__ void __launch_bounds__(BLOCK) k_rhs(int N, int Np, int E, const int* 
       const real enl = exa * gxl + eya * gyl;
       const real ena = exa * gla + eya * hla, enb = exa * glb + eya * hlb;
       const real sg = own[a] * enl + pop[a * Np + va] * ena + pop[a * Np + vb] * enb;
-      const real sh = own[Q + a] * enl + pop[(Q + a) * Np + va] * ena + pop[(Q + a) * Np + vb] * enb;
+      const real sh = own[Q + a] * enl + ha[a] * ena + hb[a] * enb;
       const real wgt = A * (c1 + c2 * enl);
       b[a] += wgt * (Phig - sg);
       b[Q + a] += wgt * (Phih - sh);
+    }
+    if (CONS) {
+      // zeroth h-moment of this element's contribution in FP64 from the moment
+      // identities of Gamma (sum Gamma = 1, sum e Gamma = u, sum e e Gamma =
+      // c_s^2 I + u u): sum_a q_a = M lap mu - div J, sum_a e_a q_a =
+      // c_s^2 X + M lap mu u - div Pi, with J = sum e h_hat, Pi = sum e e h_hat.
+      // Evaluated in the element's fixed vertex order so that the three
+      // vertices' shares are bitwise identical and telescope.
+      double Jx[3], Jy[3], Pxx[3], Pxy[3], Pyy[3];
+#pragma unroll
+      for (int t = 0; t < 3; ++t) { Jx[t] = Jy[t] = Pxx[t] = Pxy[t] = Pyy[t] = 0.0; }
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        const double hv[3] = {(double)(l == 0 ? own[Q + a] : (o1 == 0 ? ha[a] : hb[a])),
+                              (double)(l == 1 ? own[Q + a] : (o1 == 1 ? ha[a] : hb[a])),
+                              (double)(l == 2 ? own[Q + a] : (o1 == 2 ? ha[a] : hb[a]))};
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          if (ex(a)) Jx[t] += ex(a) * hv[t];
+          if (ey(a)) Jy[t] += ey(a) * hv[t];
+          if (ex(a)) Pxx[t] += hv[t];
+          if (ex(a) && ey(a)) Pxy[t] += ex(a) * ey(a) * hv[t];
+          if (ey(a)) Pyy[t] += hv[t];
+        }
+      }
+      const double Ad = geo[e];
+      double gxd[3], gyd[3];
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        gxd[t] = geo[(1 + 2 * t) * E + e];
+        gyd[t] = geo[(2 + 2 * t) * E + e];
+      }
+      double divJ = 0.0, dPx = 0.0, dPy = 0.0;
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        divJ += gxd[t] * Jx[t] + gyd[t] * Jy[t];
+        dPx += gxd[t] * Pxx[t] + gyd[t] * Pxy[t];
+        dPy += gxd[t] * Pxy[t] + gyd[t] * Pyy[t];
+      }
+      const double uxd = ((double)ux0 + (double)ux1 + (double)ux2) * (1.0 / 3.0);
+      const double uyd = ((double)uy0 + (double)uy1 + (double)uy2) * (1.0 / 3.0);
+      const double cf = Cb / (rhobd * CS2);
+      const double Xdx = gCx - cf * ((double)gpx - mub * gCx), Xdy = gCy - cf * ((double)gpy - mub * gCy);
+      const double Ml = P.mobility * lm;
+      const double s0 = Ml - divJ;
+      const double s1x = CS2 * Xdx + Ml * uxd - dPx, s1y = CS2 * Xdy + Ml * uyd - dPy;
+      bC += Ad * (P.dt * (1.0 / 3.0) * s0 + 0.5 * P.dt * P.dt * (gxd[l] * s1x + gyd[l] * s1y));
     }
   }
   const real inv_m = (real)(1.0 / mass[i]);
 #pragma unroll
   for (int a = 0; a < NPOP; ++a) f[a * Np + i] = b[a] * inv_m;
+  if (CONS) fC[i] = bC / mass[i];
 }
 
 // ----------------------------------------------------------------------------
@@ -397,20 +476,39 @@ __global__ void __launch_bounds__(BLOCK) k_rhs(int N, int Np, int E, const int* 
 // MODE 2: last sweep: psi_bar^{n+1} = psi_hat + x_K, then the wall operator
 // MODE 3: single sweep (first and last)
 // MODE 4: no sweep (K = 0): psi_bar^{n+1} = psi_hat + f, then the wall operator
+// In FP32 the same sweeps also advance the composition increment X_C in FP64
+// (right-hand side fC, the zeroth h-moment of b/m); its diagonal dlt_j makes
+// the column sums sum_i m_i A_ij = m_j exact for the stored a_ij, so every
+// sweep keeps sum_i m_i X_C,i = sum_i m_i fC_i to FP64 rounding.  The last
+// sweep stores r = (C^n + X_C) - sum_a h_a^{n+1}.
 // ----------------------------------------------------------------------------
+struct ConsArgs {
+  const double* fC;    // [Np]
+  const double* xCin;  // [Np]
+  double* xCout;       // [Np]
+  const double* dlt;   // [Np]
+  const double* Cn;    // [Np] composition entering the step
+  double* rC;          // [Np] remainder written by the last sweep
+  double w;
+};
+
 template <typename real, int MODE>
 __global__ void __launch_bounds__(BLOCK) k_sweep(int N, int Np, const int* __restrict__ sell_ptr,
                                                 const int* __restrict__ sell_col, const real* __restrict__ sell_val,
                                                 const real* __restrict__ f, const real* __restrict__ xin,
                                                 real* __restrict__ xout, real* __restrict__ pop,
-                                                const uint8_t* __restrict__ is_wall, real w) {
+                                                const uint8_t* __restrict__ is_wall, real w, ConsArgs cs) {
+  constexpr bool CONS = Conserve<real>::on;
   const int i = xcd_block() * BLOCK + threadIdx.x;
   if (i >= N) return;
   const real* __restrict__ x = (MODE == 0 || MODE == 3) ? f : xin;
+  const double* __restrict__ xC = (MODE == 0 || MODE == 3) ? cs.fC : cs.xCin;
   real r[NPOP];
+  double rc = 0.0;
   if (MODE != 4) {
 #pragma unroll
     for (int a = 0; a < NPOP; ++a) r[a] = (real)0.5 * x[a * Np + i];
+    if (CONS) rc = cs.dlt[i] * xC[i];
     const int slice = i >> 6, lane = i & 63;
     const int base = sell_ptr[slice], width = (sell_ptr[slice + 1] - base) >> 6;
     for (int k = 0; k < width; ++k) {
@@ -419,20 +517,28 @@ __global__ void __launch_bounds__(BLOCK) k_sweep(int N, int Np, const int* __res
       const real aij = sell_val[idx];
 #pragma unroll
       for (int a = 0; a < NPOP; ++a) r[a] += aij * x[a * Np + j];
+      if (CONS) rc += (double)aij * xC[j];
     }
 #pragma unroll
     for (int a = 0; a < NPOP; ++a) {
-      const real xi = (MODE == 0 || MODE == 3) ? f[a * Np + i] : x[a * Np + i];
+      const real xi = x[a * Np + i];
       const real fi = (MODE == 0 || MODE == 3) ? xi : f[a * Np + i];
       r[a] = xi + w * (fi - r[a]);
+    }
+    if (CONS) {
+      const double xi = xC[i];
+      const double fi = (MODE == 0 || MODE == 3) ? xi : cs.fC[i];
+      rc = xi + cs.w * (fi - rc);
     }
   } else {
 #pragma unroll
     for (int a = 0; a < NPOP; ++a) r[a] = f[a * Np + i];
+    if (CONS) rc = cs.fC[i];
   }
   if (MODE == 0 || MODE == 1) {
 #pragma unroll
     for (int a = 0; a < NPOP; ++a) xout[a * Np + i] = r[a];
+    if (CONS) cs.xCout[i] = rc;
     return;
   }
   real s[NPOP];
@@ -451,6 +557,12 @@ __global__ void __launch_bounds__(BLOCK) k_sweep(int N, int Np, const int* __res
   }
 #pragma unroll
   for (int a = 0; a < NPOP; ++a) pop[a * Np + i] = s[a];
+  if (CONS) {
+    double sh = 0.0;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) sh += (double)s[Q + a];
+    cs.rC[i] = (cs.Cn[i] + rc) - sh;
+  }
 }
 
 // ----------------------------------------------------------------------------
@@ -459,7 +571,8 @@ __global__ void __launch_bounds__(BLOCK) k_sweep(int N, int Np, const int* __res
 template <typename real>
 __global__ void __launch_bounds__(BLOCK) k_init(int N, int Np, StepParams P, const double* __restrict__ C,
                                                const double* __restrict__ U, const double* __restrict__ Pr,
-                                               const uint8_t* __restrict__ is_wall, real* __restrict__ pop) {
+                                               const uint8_t* __restrict__ is_wall, real* __restrict__ pop,
+                                               double* __restrict__ rC) {
   const int i = blockIdx.x * BLOCK + threadIdx.x;
   if (i >= N) return;
   const double c = C[i], ux = U[2 * i], uy = U[2 * i + 1], p = Pr[i];
@@ -482,8 +595,14 @@ __global__ void __launch_bounds__(BLOCK) k_init(int N, int Np, StepParams P, con
       }
     }
   }
+  double sh = 0.0;
 #pragma unroll
-  for (int a = 0; a < NPOP; ++a) pop[a * Np + i] = (real)s[a];
+  for (int a = 0; a < NPOP; ++a) {
+    const real v = (real)s[a];
+    pop[a * Np + i] = v;
+    if (a >= Q) sh += (double)v;
+  }
+  if (Conserve<real>::on) rC[i] = c - sh;
 }
 
 template <typename real>

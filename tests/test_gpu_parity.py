@@ -142,6 +142,34 @@ def test_mass_conserved_fp64_and_fp32():
         ctx.close()
 
 
+def test_fp32_precision_form_vs_fp64_oracle(cfg1_theta60):
+    """FP32 populations and arithmetic (FP64 mu chain, reductions and
+    composition) against the FP64 oracle after 200 steps, on the bars the
+    precision form is held to: spurious-current maximum within 5%, mass drift
+    below 1e-10 relative; the populations themselves differ at FP32 rounding
+    level (unit roundoff 6e-8, a few hundred operations per step)."""
+    w, om, o = cfg1_theta60
+    log("fp32 precision form vs fp64 oracle, workload 1, 200 steps")
+    ctx = make_ctx(w.mesh, w.phys, om, precision="fp32", sweeps=16)
+    ctx.init(w.C0)
+    m0 = ctx.diagnostics()["mass"]
+    ctx.step(200)
+    d = ctx.diagnostics()
+    g, h = o.init_state(w.C0)
+    g, h = o.run(g, h, 200)
+    r = o.diagnostics(g, h)
+    pops = rel(ctx.read_populations(), stack(g, h))
+    cerr = np.abs(ctx.read("C") - h.sum(1)).max()
+    log(f"  pops rel {pops:.2e}  C abs {cerr:.2e}  max_u {d['max_u']:.6e} vs {r['max_u']:.6e}  "
+        f"mass drift {abs(d['mass'] - m0) / m0:.2e}")
+    assert pops < 1e-5
+    assert cerr < 1e-5
+    assert abs(d["max_u"] - r["max_u"]) / r["max_u"] < 0.05
+    assert abs(d["mass"] - m0) / m0 < 1e-10
+    assert abs(d["mass"] - r["mass"]) / r["mass"] < 1e-10
+    ctx.close()
+
+
 def test_deterministic_and_checkpoint_resume():
     w = config(1)
     om = wetting_from_angles(w.mesh, 60.0)
