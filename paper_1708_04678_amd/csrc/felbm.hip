@@ -21,10 +21,12 @@ namespace {
 
 enum KernelId {
   K_MOMENTS = 0, K_REDUCE, K_GRAD, K_LAPC, K_GRADMU, K_LAPMU, K_RHS, K_SWEEP_FIRST, K_SWEEP_MID, K_SWEEP_LAST,
-  K_COUNT
+  K_PAIR_FIRST, K_PAIR_MID, K_PAIR_LAST, K_COUNT
 };
-const char* const kKernelNames[K_COUNT] = {"moments_collide", "reduce_final", "elem_grad", "lapC_mu", "elem_gradmu",
-                                           "elem_lapmu", "rhs_gather", "sweep_first", "sweep_mid", "sweep_last"};
+const char* const kKernelNames[K_COUNT] = {"moments_collide", "reduce_final", "elem_grad", "lapC_mu",
+                                           "elem_gradmu", "elem_lapmu", "rhs_gather", "sweep_first",
+                                           "sweep_mid", "sweep_last", "sweep2_first", "sweep2_mid",
+                                           "sweep2_last"};
 
 struct KStat {
   int64_t launches = 0;
@@ -45,6 +47,7 @@ struct StateHeader {
   int64_t n_nodes;
   int64_t step;
   int64_t payload_bytes;
+  uint64_t perm_hash;  // internal node order the payload is laid out in
 };
 
 inline int grid_for(int64_t n) {
@@ -77,6 +80,20 @@ struct felbm_ctx {
   void *pop = nullptr, *f = nullptr, *xa = nullptr, *xb = nullptr;
   double *Cn = nullptr, *mu = nullptr, *lapC = nullptr, *gC = nullptr, *gmu = nullptr, *lapmu = nullptr;
   void *pn = nullptr, *uxn = nullptr, *uyn = nullptr, *gp = nullptr;
+  // LDS-tiled solve: per-tile halo lists and matrix rows with local slots
+  bool use_lds = false;
+  int ntiles = 0, tile_slots = 0;
+  uint32_t lds_bytes = 0;
+  int32_t *tile_off = nullptr, *halo_off = nullptr, *halo = nullptr;
+  uint16_t* tslot = nullptr;
+  void* tval = nullptr;
+  // two-sweep (temporally blocked) solve: ring-1 rows and ring-2 lists per tile
+  bool use_pair = false;
+  int pair_slots = 0, pair_slots1 = 0;
+  uint32_t pair_lds = 0;
+  int32_t *ring_off = nullptr, *ring_w = nullptr, *r2_off = nullptr, *r2 = nullptr;
+  uint16_t* rslot = nullptr;
+  void* rval = nullptr;
   // FP32 only: FP64 composition transport (remainder, rhs moment, iterates, diagonal)
   double *rC = nullptr, *fC = nullptr, *xCa = nullptr, *xCb = nullptr, *dlt = nullptr;
   double* partials = nullptr;
@@ -85,6 +102,9 @@ struct felbm_ctx {
   int32_t* first_bad = nullptr;
   int64_t hist_cap = 16384;
   std::vector<double> host_omega;
+  // internal orderings (see mesh_prep.hpp)
+  std::vector<int32_t> node_perm, elem_perm;
+  uint64_t perm_hash = 0;
   // timing
   bool timing = false;
   KStat kstat[K_COUNT];
@@ -146,14 +166,14 @@ hipEvent_t take_event(felbm_ctx* c) {
 // Launch a kernel on the context stream; with timing on, bracket it with
 // events recorded by the command processor at kernel start and end.
 template <typename F, typename... Args>
-int launch_bs(felbm_ctx* c, int kid, F kernel, int grid, int block, Args... args) {
+int launch_sm(felbm_ctx* c, int kid, F kernel, int grid, int block, uint32_t shmem, Args... args) {
   if (c->timing) {
     hipEvent_t s = take_event(c), t = take_event(c);
     if (!s || !t) return fail(c, FELBM_EDEVICE, "hipEventCreate failed");
-    hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, c->stream, s, t, 0, args...);
+    hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(block), shmem, c->stream, s, t, 0, args...);
     c->pending.push_back({kid, s, t});
   } else {
-    hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, c->stream, args...);
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), shmem, c->stream, args...);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(c, FELBM_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
@@ -161,8 +181,13 @@ int launch_bs(felbm_ctx* c, int kid, F kernel, int grid, int block, Args... args
 }
 
 template <typename F, typename... Args>
+int launch_bs(felbm_ctx* c, int kid, F kernel, int grid, int block, Args... args) {
+  return launch_sm(c, kid, kernel, grid, block, 0u, args...);
+}
+
+template <typename F, typename... Args>
 int launch(felbm_ctx* c, int kid, F kernel, int grid, Args... args) {
-  return launch_bs(c, kid, kernel, grid, BLOCK, args...);
+  return launch_sm(c, kid, kernel, grid, BLOCK, 0u, args...);
 }
 
 int harvest_timing(felbm_ctx* c) {
@@ -239,48 +264,94 @@ int enqueue_rhs(felbm_ctx* c) {
                 (const double*)c->mu, (const real*)c->pop, (const double*)c->mass, c->sp, (real*)c->f, c->fC);
 }
 
+template <typename real, int MODE>
+int sweep(felbm_ctx* c, int kid, const real* xin, real* xout, real w, const ConsArgs& cs) {
+  const int N = (int)c->N, Np = (int)c->Np;
+  real* pop = (real*)c->pop;
+  const real* f = (const real*)c->f;
+  if (c->use_lds) {
+    TileArgs ta{c->tile_off, c->tslot, c->halo_off, c->halo, c->ntiles, c->tile_slots};
+    const int grid = (c->ntiles + 7) / 8 * 8;
+    return launch_sm(c, kid, k_sweep_lds<real, MODE>, grid, BLOCK, c->lds_bytes, N, Np, ta, (const real*)c->tval, f, xin,
+                     xout, pop, (const uint8_t*)c->is_wall, w, cs);
+  }
+  return launch(c, kid, k_sweep<real, MODE>, grid_for(c->N), N, Np, (const int*)c->sell_ptr, (const int*)c->sell_col,
+                (const real*)c->sell_val, f, xin, xout, pop, (const uint8_t*)c->is_wall, w, cs);
+}
+
 // K Chebyshev-step Richardson sweeps on f, then psi_bar^{n+1} = psi_hat + x_K
 // and the wall operator (fused into the last sweep)
+template <typename real, int PMODE>
+int sweep2(felbm_ctx* c, int kid, const real* xin, real* xout, double w0, double w1, const ConsArgs& cs) {
+  PairArgs pa{c->tile_off, c->tslot, c->ring_off, c->ring_w, c->rslot, c->halo_off, c->halo,
+              c->r2_off, c->r2, c->ntiles, c->pair_slots, c->pair_slots1};
+  const int grid = (c->ntiles + 7) / 8 * 8;
+  return launch_sm(c, kid, k_sweep2<real, PMODE>, grid, BLOCK, c->pair_lds, (int)c->N, (int)c->Np, pa,
+                   (const real*)c->tval, (const real*)c->rval, (const real*)c->f, xin, xout, (real*)c->pop,
+                   (const uint8_t*)c->is_wall, (real)w0, (real)w1, cs, w0, w1);
+}
+
+// The same K sweeps, two per launch (a single first sweep when K is odd).
+template <typename real>
+int enqueue_solve_pairs(felbm_ctx* c) {
+  const int K = c->prm.solver_sweeps;
+  const std::vector<double>& w = c->cheb_w;
+  real *cur = (real*)c->xa, *nxt = (real*)c->xb;
+  double *ccur = c->xCa, *cnxt = c->xCb;
+  ConsArgs cs{c->fC, nullptr, nullptr, c->dlt, c->Cn, c->rC, 0.0};
+  int j = 0;
+  if (K % 2 == 1) {
+    cs.w = w[0];
+    cs.xCout = ccur;
+    TRY((sweep<real, 0>(c, K_SWEEP_FIRST, nullptr, cur, (real)w[0], cs)));
+    j = 1;
+  }
+  while (j < K) {
+    const bool first = (j == 0), last = (j + 2 == K);
+    cs.xCin = ccur;
+    cs.xCout = last ? nullptr : cnxt;
+    if (first && last)
+      TRY((sweep2<real, 3>(c, K_PAIR_LAST, nullptr, nullptr, w[j], w[j + 1], cs)));
+    else if (first)
+      TRY((sweep2<real, 0>(c, K_PAIR_FIRST, nullptr, nxt, w[j], w[j + 1], cs)));
+    else if (last)
+      TRY((sweep2<real, 2>(c, K_PAIR_LAST, cur, nullptr, w[j], w[j + 1], cs)));
+    else
+      TRY((sweep2<real, 1>(c, K_PAIR_MID, cur, nxt, w[j], w[j + 1], cs)));
+    if (!last) {
+      std::swap(cur, nxt);
+      std::swap(ccur, cnxt);
+    }
+    j += 2;
+  }
+  return FELBM_OK;
+}
+
 template <typename real>
 int enqueue_solve(felbm_ctx* c) {
-  const int gN = grid_for(c->N);
-  const int N = (int)c->N, Np = (int)c->Np;
   const int K = c->prm.solver_sweeps;
-  const int* sp = c->sell_ptr;
-  const int* sc = c->sell_col;
-  const real* sv = (const real*)c->sell_val;
-  real *pop = (real*)c->pop, *f = (real*)c->f, *xa = (real*)c->xa, *xb = (real*)c->xb;
-  const uint8_t* wall = c->is_wall;
+  if (c->use_pair && K >= 2) return enqueue_solve_pairs<real>(c);
+  real *xa = (real*)c->xa, *xb = (real*)c->xb;
   ConsArgs cs{c->fC, nullptr, nullptr, c->dlt, c->Cn, c->rC, 0.0};
-  if (K == 0) {
-    return launch(c, K_SWEEP_LAST, k_sweep<real, 4>, gN, N, Np, sp, sc, sv, (const real*)f, (const real*)nullptr,
-                  (real*)nullptr, pop, wall, (real)0, cs);
-  }
-  if (K == 1) {
-    cs.w = c->cheb_w[0];
-    return launch(c, K_SWEEP_LAST, k_sweep<real, 3>, gN, N, Np, sp, sc, sv, (const real*)f, (const real*)nullptr,
-                  (real*)nullptr, pop, wall, (real)c->cheb_w[0], cs);
-  }
+  if (K == 0) return sweep<real, 4>(c, K_SWEEP_LAST, nullptr, nullptr, (real)0, cs);
   cs.w = c->cheb_w[0];
+  if (K == 1) return sweep<real, 3>(c, K_SWEEP_LAST, nullptr, nullptr, (real)c->cheb_w[0], cs);
   cs.xCout = c->xCa;
-  TRY(launch(c, K_SWEEP_FIRST, k_sweep<real, 0>, gN, N, Np, sp, sc, sv, (const real*)f, (const real*)nullptr, xa, pop,
-             wall, (real)c->cheb_w[0], cs));
+  TRY((sweep<real, 0>(c, K_SWEEP_FIRST, nullptr, xa, (real)c->cheb_w[0], cs)));
   real *xin = xa, *xout = xb;
   double *cin = c->xCa, *cout = c->xCb;
   for (int j = 1; j < K - 1; ++j) {
     cs.w = c->cheb_w[j];
     cs.xCin = cin;
     cs.xCout = cout;
-    TRY(launch(c, K_SWEEP_MID, k_sweep<real, 1>, gN, N, Np, sp, sc, sv, (const real*)f, (const real*)xin, xout, pop,
-               wall, (real)c->cheb_w[j], cs));
+    TRY((sweep<real, 1>(c, K_SWEEP_MID, xin, xout, (real)c->cheb_w[j], cs)));
     std::swap(xin, xout);
     std::swap(cin, cout);
   }
   cs.w = c->cheb_w[K - 1];
   cs.xCin = cin;
   cs.xCout = nullptr;
-  return launch(c, K_SWEEP_LAST, k_sweep<real, 2>, gN, N, Np, sp, sc, sv, (const real*)f, (const real*)xin,
-                (real*)nullptr, pop, wall, (real)c->cheb_w[K - 1], cs);
+  return sweep<real, 2>(c, K_SWEEP_LAST, xin, nullptr, (real)c->cheb_w[K - 1], cs);
 }
 
 template <typename real>
@@ -322,12 +393,15 @@ int copy_pops_out(felbm_ctx* c, const void* dev, double* out) {
   double* tmp = nullptr;
   HIP_OK(c, hipMallocAsync((void**)&tmp, 18 * c->Np * sizeof(double), c->stream));
   int r = to_double(c, dev, tmp, 18 * c->Np);
+  std::vector<double> host(18 * c->Np);
   if (r == FELBM_OK) {
-    hipError_t e = hipMemcpy2DAsync(out, c->N * sizeof(double), tmp, c->Np * sizeof(double), c->N * sizeof(double), 18,
-                                    hipMemcpyDeviceToHost, c->stream);
+    hipError_t e = hipMemcpyAsync(host.data(), tmp, host.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) r = fail(c, FELBM_EDEVICE, std::string("population copy failed: ") + hipGetErrorString(e));
   }
+  if (r == FELBM_OK)
+    for (int64_t a = 0; a < 18; ++a)
+      for (int64_t k = 0; k < c->N; ++k) out[a * c->N + c->node_perm[k]] = host[a * c->Np + k];
   hipFreeAsync(tmp, c->stream);
   hipStreamSynchronize(c->stream);
   return r;
@@ -346,6 +420,183 @@ std::vector<double> chebyshev_steps(int K, double lo, double hi) {
     --j;
   }
   return out;
+}
+
+// Ring-1 rows (the rows of the tile's halo nodes, in slots of tile + ring 1 +
+// ring 2) and ring-2 node lists for the two-sweep kernel.
+int build_pairs(felbm_ctx* c, const MeshPrep& m, const std::vector<int32_t>& r1_off, const std::vector<int32_t>& r1,
+                const std::vector<int32_t>& tile_off, const std::vector<uint16_t>& tslot) {
+  const int64_t N = m.N, nt = (N + TILE - 1) / TILE;
+  std::vector<int32_t> ring_off(nt + 1, 0), ring_w(nt, 0), r2_off(nt + 1, 0), r2;
+  std::vector<uint16_t> rslot;
+  std::vector<double> rval;
+  int64_t max12 = 0, max1 = 0;
+  for (int64_t t = 0; t < nt; ++t) {
+    const int64_t lo = t * TILE, hi = std::min<int64_t>(N, lo + TILE);
+    const int32_t* ring = r1.data() + r1_off[t];
+    const int64_t n1 = r1_off[t + 1] - r1_off[t];
+    auto in_ring1 = [&](int32_t j) { return std::binary_search(ring, ring + n1, j); };
+    std::vector<int32_t> l2;
+    int64_t rw = 0;
+    for (int64_t h = 0; h < n1; ++h) {
+      const int32_t j = ring[h];
+      rw = std::max<int64_t>(rw, m.csr_ptr[j + 1] - m.csr_ptr[j]);
+      for (int32_t q = m.csr_ptr[j]; q < m.csr_ptr[j + 1]; ++q) {
+        const int32_t k = m.csr_col[q];
+        if ((k < lo || k >= hi) && !in_ring1(k)) l2.push_back(k);
+      }
+    }
+    std::sort(l2.begin(), l2.end());
+    l2.erase(std::unique(l2.begin(), l2.end()), l2.end());
+    if (rw > MAXW) return FELBM_OK;  // keep one sweep per launch
+    max12 = std::max<int64_t>(max12, n1 + (int64_t)l2.size());
+    max1 = std::max<int64_t>(max1, n1);
+    const size_t base = rslot.size();
+    rslot.resize(base + rw * n1);
+    rval.resize(base + rw * n1);
+    for (int64_t k = 0; k < rw; ++k)
+      for (int64_t h = 0; h < n1; ++h) {
+        const int32_t j = ring[h];
+        const size_t idx = base + k * n1 + h;
+        rslot[idx] = (uint16_t)(TILE + h);
+        rval[idx] = 0.0;
+        if (k < m.csr_ptr[j + 1] - m.csr_ptr[j]) {
+          const int32_t q = m.csr_col[m.csr_ptr[j] + k];
+          int64_t s;
+          if (q >= lo && q < hi)
+            s = q - lo;
+          else if (in_ring1(q))
+            s = TILE + (std::lower_bound(ring, ring + n1, q) - ring);
+          else
+            s = TILE + n1 + (std::lower_bound(l2.begin(), l2.end(), q) - l2.begin());
+          rslot[idx] = (uint16_t)s;
+          rval[idx] = m.csr_val[m.csr_ptr[j] + k];
+        }
+      }
+    ring_w[t] = (int32_t)rw;
+    ring_off[t + 1] = (int32_t)rslot.size();
+    r2.insert(r2.end(), l2.begin(), l2.end());
+    r2_off[t + 1] = (int32_t)r2.size();
+  }
+  (void)tile_off;
+  (void)tslot;
+  if (max1 > HALO_MAX || max12 > 2 * HALO_MAX) return FELBM_OK;  // keep one sweep per launch
+  // FP32 keeps one sweep per launch: the staging of its 18 populations in a
+  // single LDS pass is faster than two-sweep blocking in several passes
+  if (c->prm.precision == FELBM_FP32) return FELBM_OK;
+  const int64_t S = SLOTS2, S1 = SLOTS1;
+  const int G = c->prm.precision == FELBM_FP32 ? PAIR_G32 : PAIR_G64;
+  const size_t lds = (((size_t)G * (S + 2 * S1 - TILE) * c->rs + 15) & ~(size_t)15) +
+                     (c->prm.precision == FELBM_FP32 ? (size_t)(S + 2 * S1 - TILE) * 8 : 0);
+  if (lds > 65536) return FELBM_OK;
+  TRY(dalloc(c, &c->ring_off, ring_off.size()));
+  TRY(dalloc(c, &c->ring_w, ring_w.size()));
+  TRY(dalloc(c, &c->r2_off, r2_off.size()));
+  TRY(dalloc(c, &c->r2, r2.size()));
+  TRY(dalloc(c, &c->rslot, rslot.size()));
+  TRY(dalloc_bytes(c, &c->rval, rval.size() * c->rs));
+  TRY(upload(c, c->ring_off, ring_off));
+  TRY(upload(c, c->ring_w, ring_w));
+  TRY(upload(c, c->r2_off, r2_off));
+  TRY(upload(c, c->r2, r2));
+  TRY(upload(c, c->rslot, rslot));
+  if (c->prm.precision == FELBM_FP64) {
+    TRY(upload(c, (double*)c->rval, rval));
+  } else {
+    std::vector<float> v32(rval.begin(), rval.end());
+    TRY(upload(c, (float*)c->rval, v32));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+  }
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  c->pair_slots = (int)S;
+  c->pair_slots1 = (int)S1;
+  c->pair_lds = (uint32_t)lds;
+  c->use_pair = true;
+  const double s = (double)c->rs, Nd = (double)N;
+  const double tmat = (double)tslot.size() * (2.0 + s) + (double)r1.size() * 4.0;
+  const double cons = c->prm.precision == FELBM_FP32 ? 8.0 * Nd : 0.0;
+  c->kstat[K_PAIR_FIRST].bytes = 2 * 18 * Nd * s + tmat + 4 * cons;
+  c->kstat[K_PAIR_MID].bytes = 3 * 18 * Nd * s + tmat + 4 * cons;
+  c->kstat[K_PAIR_LAST].bytes = 5 * 18 * Nd * s + tmat + Nd + 6 * cons;
+  return FELBM_OK;
+}
+
+// Per-tile halo lists and local-slot matrix rows for the LDS-staged sweep.
+// Falls back to the global sliced-ELL sweep when a tile row is wider than
+// MAXW or the staging buffers would exceed 64 KiB of LDS.
+int build_tiles(felbm_ctx* c, const MeshPrep& m) {
+  const int64_t N = m.N, nt = (N + TILE - 1) / TILE;
+  std::vector<int32_t> tile_off(nt + 1, 0), halo_off(nt + 1, 0), halo;
+  std::vector<uint16_t> slot;
+  std::vector<double> val;
+  int64_t maxh = 0;
+  for (int64_t t = 0; t < nt; ++t) {
+    const int64_t lo = t * TILE, hi = std::min<int64_t>(N, lo + TILE);
+    std::vector<int32_t> hl;
+    int64_t width = 0;
+    for (int64_t i = lo; i < hi; ++i) {
+      width = std::max<int64_t>(width, m.csr_ptr[i + 1] - m.csr_ptr[i]);
+      for (int32_t q = m.csr_ptr[i]; q < m.csr_ptr[i + 1]; ++q)
+        if (m.csr_col[q] < lo || m.csr_col[q] >= hi) hl.push_back(m.csr_col[q]);
+    }
+    std::sort(hl.begin(), hl.end());
+    hl.erase(std::unique(hl.begin(), hl.end()), hl.end());
+    if (width > MAXW) return FELBM_OK;  // keep the sliced-ELL sweep
+    maxh = std::max<int64_t>(maxh, (int64_t)hl.size());
+    const size_t base = slot.size();
+    slot.resize(base + width * TILE);
+    val.resize(base + width * TILE);
+    for (int64_t k = 0; k < width; ++k)
+      for (int lane = 0; lane < TILE; ++lane) {
+        const int64_t i = lo + lane, idx = base + k * TILE + lane;
+        slot[idx] = (uint16_t)lane;
+        val[idx] = 0.0;
+        if (i < hi && k < m.csr_ptr[i + 1] - m.csr_ptr[i]) {
+          const int32_t j = m.csr_col[m.csr_ptr[i] + k];
+          const int64_t s = (j >= lo && j < hi) ? j - lo
+                                                  : TILE + (std::lower_bound(hl.begin(), hl.end(), j) - hl.begin());
+          slot[idx] = (uint16_t)s;
+          val[idx] = m.csr_val[m.csr_ptr[i] + k];
+        }
+      }
+    tile_off[t + 1] = (int32_t)slot.size();
+    halo.insert(halo.end(), hl.begin(), hl.end());
+    halo_off[t + 1] = (int32_t)halo.size();
+  }
+  if (maxh > HALO_MAX) return FELBM_OK;  // keep the sliced-ELL sweep
+  const int64_t slots = SLOTS1;
+  const int G = c->prm.precision == FELBM_FP32 ? 18 : 9;
+  const size_t lds = (((size_t)G * slots * c->rs + 15) & ~(size_t)15) + (c->prm.precision == FELBM_FP32 ? slots * 8 : 0);
+  if (lds > 65536) return FELBM_OK;
+  TRY(dalloc(c, &c->tile_off, tile_off.size()));
+  TRY(dalloc(c, &c->halo_off, halo_off.size()));
+  TRY(dalloc(c, &c->halo, halo.size()));
+  TRY(dalloc(c, &c->tslot, slot.size()));
+  TRY(dalloc_bytes(c, &c->tval, val.size() * c->rs));
+  TRY(upload(c, c->tile_off, tile_off));
+  TRY(upload(c, c->halo_off, halo_off));
+  TRY(upload(c, c->halo, halo));
+  TRY(upload(c, c->tslot, slot));
+  if (c->prm.precision == FELBM_FP64) {
+    TRY(upload(c, (double*)c->tval, val));
+  } else {
+    std::vector<float> v32(val.begin(), val.end());
+    TRY(upload(c, (float*)c->tval, v32));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+  }
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  c->ntiles = (int)nt;
+  c->tile_slots = (int)slots;
+  c->lds_bytes = (uint32_t)lds;
+  c->use_lds = true;
+  const double s = (double)c->rs, Nd = (double)N;
+  const double tmat = (double)slot.size() * (2.0 + s) + (double)halo.size() * 4.0;
+  const double cons = c->prm.precision == FELBM_FP32 ? 8.0 * Nd : 0.0;
+  c->kstat[K_SWEEP_FIRST].bytes = 2 * 18 * Nd * s + tmat + 3 * cons;
+  c->kstat[K_SWEEP_MID].bytes = 3 * 18 * Nd * s + tmat + 4 * cons;
+  c->kstat[K_SWEEP_LAST].bytes = 4 * 18 * Nd * s + tmat + Nd + 5 * cons;
+  TRY(build_pairs(c, m, halo_off, halo, tile_off, slot));
+  return FELBM_OK;
 }
 
 }  // namespace
@@ -419,6 +670,9 @@ int felbm_upload_mesh(felbm_ctx* c, int64_t n_nodes, const double* xy, int64_t n
   c->E = m.E;
   c->W = m.W;
   c->offdiag_nnz = m.offdiag_nnz;
+  c->node_perm = m.node_perm;
+  c->elem_perm = m.elem_perm;
+  c->perm_hash = m.perm_hash;
   c->sell_entries = (int64_t)m.sell_col.size();
   c->band.period = period_x;
   HIP_OK(c, hipSetDevice(c->device));
@@ -502,6 +756,8 @@ int felbm_upload_mesh(felbm_ctx* c, int64_t n_nodes, const double* xy, int64_t n
     TRY(upload(c, c->dlt, dlt));
     HIP_OK(c, hipStreamSynchronize(c->stream));  // host vectors are about to go out of scope
   }
+  set_kernel_bytes(c);
+  TRY(build_tiles(c, m));
   std::vector<double> zeros(N, 0.0);
   TRY(upload(c, c->bc, zeros));
   HIP_OK(c, hipMemsetAsync(c->pop, 0, 18 * Np * rs, c->stream));
@@ -512,7 +768,6 @@ int felbm_upload_mesh(felbm_ctx* c, int64_t n_nodes, const double* xy, int64_t n
   HIP_OK(c, hipStreamSynchronize(c->stream));
   c->host_omega.assign(N, 0.0);
   c->has_mesh = true;
-  set_kernel_bytes(c);
   return FELBM_OK;
 }
 
@@ -522,17 +777,19 @@ int felbm_set_wetting(felbm_ctx* c, const double* omega_c) {
   if (!omega_c) return fail(c, FELBM_EINVAL, "set_wetting: null omega_c");
   const double kappa = c->sp.kappa, beta = c->sp.beta;
   std::vector<double> bc(c->N, 0.0);
-  for (int64_t i = 0; i < c->N; ++i) {
-    if (!std::isfinite(omega_c[i])) return fail(c, FELBM_EINVAL, "set_wetting: non-finite value");
-    c->host_omega[i] = omega_c[i];
+  for (int64_t k = 0; k < c->N; ++k) {
+    const double v = omega_c[c->node_perm[k]];
+    if (!std::isfinite(v)) return fail(c, FELBM_EINVAL, "set_wetting: non-finite value");
+    c->host_omega[k] = v;
   }
   // wall flags live on the device; recompute them from the host copy of the mesh is not kept, so read back
   std::vector<uint8_t> wall(c->N);
   HIP_OK(c, hipMemcpy(wall.data(), c->is_wall, c->N, hipMemcpyDeviceToHost));
   for (int64_t i = 0; i < c->N; ++i) {
-    if (!wall[i] || omega_c[i] == 0.0) continue;
+    const double om = c->host_omega[i];
+    if (!wall[i] || om == 0.0) continue;
     if (kappa <= 0.0) return fail(c, FELBM_EINVAL, "set_wetting: a nonzero wetting potential needs kappa > 0");
-    bc[i] = omega_c[i] * std::sqrt(2.0 * kappa * beta) / kappa;  // phi_c / kappa, Young: phi_c = Omega_c sqrt(2 kappa beta)
+    bc[i] = om * std::sqrt(2.0 * kappa * beta) / kappa;  // phi_c / kappa, Young: phi_c = Omega_c sqrt(2 kappa beta)
   }
   TRY(upload(c, c->bc, bc));
   HIP_OK(c, hipStreamSynchronize(c->stream));
@@ -544,9 +801,16 @@ int felbm_init(felbm_ctx* c, const double* C, const double* u, const double* p) 
   if (!c->has_mesh) return fail(c, FELBM_ESTATE, "init: no mesh");
   if (!C) return fail(c, FELBM_EINVAL, "init: null C");
   const int64_t N = c->N;
-  std::vector<double> hC(C, C + N), hU(2 * N, 0.0), hP(N, 0.0);
-  if (u) hU.assign(u, u + 2 * N);
-  if (p) hP.assign(p, p + N);
+  std::vector<double> hC(N), hU(2 * N, 0.0), hP(N, 0.0);
+  for (int64_t k = 0; k < N; ++k) {
+    const int64_t s = c->node_perm[k];
+    hC[k] = C[s];
+    if (u) {
+      hU[2 * k] = u[2 * s];
+      hU[2 * k + 1] = u[2 * s + 1];
+    }
+    if (p) hP[k] = p[s];
+  }
   for (int64_t i = 0; i < N; ++i)
     if (!std::isfinite(hC[i]) || !std::isfinite(hU[2 * i]) || !std::isfinite(hU[2 * i + 1]) || !std::isfinite(hP[i]))
       return fail(c, FELBM_EINVAL, "init: non-finite input at node " + std::to_string(i));
@@ -616,10 +880,13 @@ int felbm_read(felbm_ctx* c, int32_t field, double* out) {
       src = tmp;
     }
   }
-  HIP_OK(c, hipMemcpyAsync(out, src, n * 8, hipMemcpyDeviceToHost, c->stream));
+  std::vector<double> host(n);
+  HIP_OK(c, hipMemcpyAsync(host.data(), src, n * 8, hipMemcpyDeviceToHost, c->stream));
   if (tmp) HIP_OK(c, hipFreeAsync(tmp, c->stream));
   HIP_OK(c, hipStreamSynchronize(c->stream));
   if (c->timing) TRY(harvest_timing(c));
+  const std::vector<int32_t>& perm = field == FELBM_FIELD_LAPMU ? c->elem_perm : c->node_perm;
+  for (int64_t k = 0; k < n; ++k) out[perm[k]] = host[k];
   if (field == FELBM_FIELD_RHO)
     for (int64_t i = 0; i < N; ++i) out[i] = out[i] * c->prm.rho_l + (1.0 - out[i]) * c->prm.rho_v;
   return FELBM_OK;
@@ -653,8 +920,9 @@ int felbm_step_debug(felbm_ctx* c, double* psi_hat, double* rhs_over_m, double* 
   if (delta) {
     std::vector<double> after(18 * c->N);
     TRY(copy_pops_out(c, c->pop, after.data()));
-    std::vector<uint8_t> wall(c->N);
-    HIP_OK(c, hipMemcpy(wall.data(), c->is_wall, c->N, hipMemcpyDeviceToHost));
+    std::vector<uint8_t> wall_int(c->N), wall(c->N);
+    HIP_OK(c, hipMemcpy(wall_int.data(), c->is_wall, c->N, hipMemcpyDeviceToHost));
+    for (int64_t k = 0; k < c->N; ++k) wall[c->node_perm[k]] = wall_int[k];
     // delta = psi_bar^{n+1} - psi_hat at interior nodes; wall nodes get NaN
     // because the wall operator has already been applied there
     for (int64_t a = 0; a < 18; ++a)
@@ -741,7 +1009,7 @@ int felbm_save_state(felbm_ctx* c, void* buf, int64_t bytes) {
   if (!c) return FELBM_EINVAL;
   if (!c->has_state) return fail(c, FELBM_ESTATE, "save_state: not initialised");
   if (!buf || bytes < felbm_state_bytes(c)) return fail(c, FELBM_EINVAL, "save_state: buffer too small");
-  StateHeader h{kStateMagic, c->prm.precision, c->N, c->step, payload_bytes(c)};
+  StateHeader h{kStateMagic, c->prm.precision, c->N, c->step, payload_bytes(c), c->perm_hash};
   std::memcpy(buf, &h, sizeof(h));
   const int64_t pb = 18 * c->Np * (int64_t)c->rs;
   HIP_OK(c, hipMemcpyAsync((char*)buf + sizeof(h), c->pop, pb, hipMemcpyDeviceToHost, c->stream));
@@ -757,7 +1025,7 @@ int felbm_load_state(felbm_ctx* c, const void* buf, int64_t bytes) {
   StateHeader h;
   std::memcpy(&h, buf, sizeof(h));
   if (h.magic != kStateMagic || h.precision != c->prm.precision || h.n_nodes != c->N ||
-      h.payload_bytes != payload_bytes(c))
+      h.payload_bytes != payload_bytes(c) || h.perm_hash != c->perm_hash)
     return fail(c, FELBM_EINVAL, "load_state: header does not match this context");
   const int64_t pb = 18 * c->Np * (int64_t)c->rs;
   HIP_OK(c, hipMemcpyAsync(c->pop, (const char*)buf + sizeof(h), pb, hipMemcpyHostToDevice, c->stream));
@@ -819,7 +1087,7 @@ int felbm_validate_mesh(int64_t n_nodes, const double* xy, int64_t n_tris, const
                         const int32_t* wall_edge, double period_x, char* msg, int32_t msg_len) {
   MeshPrep m;
   std::string err;
-  const int r = prepare_mesh(n_nodes, xy, n_tris, tri, n_wall, wall_edge, period_x, m, err);
+  const int r = prepare_mesh(n_nodes, xy, n_tris, tri, n_wall, wall_edge, period_x, m, err, false);
   if (msg && msg_len > 0) std::snprintf(msg, (size_t)msg_len, "%s", err.c_str());
   return r;
 }

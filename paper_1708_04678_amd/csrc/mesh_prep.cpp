@@ -10,10 +10,145 @@ namespace felbm {
 
 namespace {
 inline double unwrap(double dx, double period) { return period > 0 ? dx - period * std::nearbyint(dx / period) : dx; }
+
+// Recursive coordinate bisection into blocks of `block` nodes.  Each split
+// puts a multiple of `block` nodes on the left and takes whichever axis (x or
+// y median split) cuts fewer mesh edges, so blocks come out compact in graph
+// distance also on graded or anisotropic meshes.
+struct Bisector {
+  const std::vector<double>& x;
+  const std::vector<double>& y;
+  const std::vector<int32_t>& adj_ptr;
+  const std::vector<int32_t>& adj;
+  std::vector<int32_t>& ord;
+  std::vector<int64_t> tag;
+  int block;
+  int64_t next_tag = 0;
+
+  int64_t cut(int64_t lo, int64_t mid, int64_t hi, const std::vector<int32_t>& cand) {
+    const int64_t tl = ++next_tag, tr = ++next_tag;
+    for (int64_t k = lo; k < mid; ++k) tag[cand[k - lo]] = tl;
+    for (int64_t k = mid; k < hi; ++k) tag[cand[k - lo]] = tr;
+    int64_t c = 0;
+    for (int64_t k = lo; k < mid; ++k) {
+      const int32_t v = cand[k - lo];
+      for (int32_t q = adj_ptr[v]; q < adj_ptr[v + 1]; ++q) c += tag[adj[q]] == tr;
+    }
+    return c;
+  }
+
+  // granularity of a split: multiples of `block` above one block, then of
+  // block/4, block/16, ... inside it, down to leaves of four nodes
+  void split(int64_t lo, int64_t hi) {
+    const int64_t n = hi - lo;
+    if (n <= 4) return;
+    int64_t g = block;
+    while (g > 4 && g >= n) g /= 4;
+    int64_t nl = ((n / 2 + g / 2) / g) * g;
+    nl = std::max<int64_t>(g, std::min<int64_t>(nl, ((n - 1) / g) * g));
+    std::vector<int32_t> best, cand(ord.begin() + lo, ord.begin() + hi);
+    int64_t best_cut = -1;
+    for (int axis = 0; axis < 2; ++axis) {
+      const std::vector<double>& c = axis == 0 ? x : y;
+      std::nth_element(cand.begin(), cand.begin() + nl, cand.end(), [&](int32_t a, int32_t b) {
+        return c[a] < c[b] || (c[a] == c[b] && a < b);
+      });
+      const int64_t ct = cut(lo, lo + nl, hi, cand);
+      if (best_cut < 0 || ct < best_cut) {
+        best_cut = ct;
+        best = cand;
+      }
+    }
+    std::copy(best.begin(), best.end(), ord.begin() + lo);
+    split(lo, lo + nl);
+    split(lo + nl, hi);
+  }
+};
 }  // namespace
 
+static int build_internal(int64_t n_nodes, const double* xy, int64_t n_tris, const int32_t* tri, int64_t n_wall,
+                          const int32_t* wall_edge, double period_x, MeshPrep& m, std::string& err);
+
 int prepare_mesh(int64_t n_nodes, const double* xy, int64_t n_tris, const int32_t* tri, int64_t n_wall,
-                 const int32_t* wall_edge, double period_x, MeshPrep& m, std::string& err) {
+                 const int32_t* wall_edge, double period_x, MeshPrep& m, std::string& err, bool reorder, int block) {
+  // validate and build once in the caller's order (all messages use caller indices)
+  MeshPrep v;
+  int r = build_internal(n_nodes, xy, n_tris, tri, n_wall, wall_edge, period_x, v, err);
+  if (r != FELBM_OK) return r;
+  const int64_t N = n_nodes, E = n_tris;
+  if (!reorder) {
+    m = std::move(v);
+    m.node_perm.resize(N);
+    m.node_iperm.resize(N);
+    m.elem_perm.resize(E);
+    for (int64_t i = 0; i < N; ++i) m.node_perm[i] = m.node_iperm[i] = (int32_t)i;
+    for (int64_t e = 0; e < E; ++e) m.elem_perm[e] = (int32_t)e;
+    return FELBM_OK;
+  }
+  std::vector<int32_t> perm(N);
+  for (int64_t i = 0; i < N; ++i) perm[i] = (int32_t)i;
+  if (reorder && N > block) {
+    // node graph = off-diagonal pattern of the mass matrix, from the validated build
+    std::vector<int32_t> adj_ptr(N + 1, 0), adj;
+    {
+      std::vector<std::vector<int32_t>> nb(N);
+      for (int64_t e = 0; e < E; ++e)
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b)
+            if (a != b) nb[tri[3 * e + a]].push_back(tri[3 * e + b]);
+      for (int64_t i = 0; i < N; ++i) {
+        auto& l = nb[i];
+        std::sort(l.begin(), l.end());
+        l.erase(std::unique(l.begin(), l.end()), l.end());
+        adj_ptr[i + 1] = adj_ptr[i] + (int32_t)l.size();
+      }
+      adj.reserve(adj_ptr[N]);
+      for (auto& l : nb) adj.insert(adj.end(), l.begin(), l.end());
+    }
+    std::vector<double> xs(N), ys(N);
+    for (int64_t i = 0; i < N; ++i) {
+      xs[i] = xy[2 * i];
+      ys[i] = xy[2 * i + 1];
+    }
+    Bisector bis{xs, ys, adj_ptr, adj, perm, std::vector<int64_t>(N, 0), block};
+    bis.split(0, N);
+  }
+  std::vector<int32_t> iperm(N);
+  for (int64_t k = 0; k < N; ++k) iperm[perm[k]] = (int32_t)k;
+  // triangles sorted by smallest internal vertex, then by caller index
+  std::vector<int32_t> eperm(E);
+  for (int64_t e = 0; e < E; ++e) eperm[e] = (int32_t)e;
+  if (reorder) {
+    std::vector<int32_t> key(E);
+    for (int64_t e = 0; e < E; ++e)
+      key[e] = std::min(iperm[tri[3 * e]], std::min(iperm[tri[3 * e + 1]], iperm[tri[3 * e + 2]]));
+    std::stable_sort(eperm.begin(), eperm.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+  }
+  std::vector<double> pxy(2 * N);
+  for (int64_t k = 0; k < N; ++k) {
+    pxy[2 * k] = xy[2 * perm[k]];
+    pxy[2 * k + 1] = xy[2 * perm[k] + 1];
+  }
+  std::vector<int32_t> ptri(3 * E), pwall(2 * n_wall);
+  for (int64_t e = 0; e < E; ++e)
+    for (int t = 0; t < 3; ++t) ptri[3 * e + t] = iperm[tri[3 * eperm[e] + t]];
+  for (int64_t w = 0; w < 2 * n_wall; ++w) pwall[w] = iperm[wall_edge[w]];
+  r = build_internal(N, pxy.data(), E, ptri.data(), n_wall, pwall.data(), period_x, m, err);
+  if (r != FELBM_OK) return r;
+  uint64_t hsh = 1469598103934665603ull;  // FNV-1a over the node permutation
+  for (int64_t k = 0; k < N; ++k) {
+    hsh ^= (uint64_t)(uint32_t)perm[k];
+    hsh *= 1099511628211ull;
+  }
+  m.node_perm = std::move(perm);
+  m.node_iperm = std::move(iperm);
+  m.elem_perm = std::move(eperm);
+  m.perm_hash = hsh;
+  return FELBM_OK;
+}
+
+static int build_internal(int64_t n_nodes, const double* xy, int64_t n_tris, const int32_t* tri, int64_t n_wall,
+                          const int32_t* wall_edge, double period_x, MeshPrep& m, std::string& err) {
   if (n_nodes <= 0 || n_tris <= 0 || n_wall < 0 || !xy || !tri || (n_wall > 0 && !wall_edge)) {
     err = "upload_mesh: null pointer or non-positive size";
     return FELBM_EINVAL;
@@ -207,6 +342,15 @@ int prepare_mesh(int64_t n_nodes, const double* xy, int64_t n_tris, const int32_
     m.offdiag_nnz += (int64_t)o;
     maxdeg = std::max<int64_t>(maxdeg, (int64_t)o);
   }
+  m.csr_ptr.assign(N + 1, 0);
+  for (int64_t i = 0; i < N; ++i) m.csr_ptr[i + 1] = m.csr_ptr[i] + (int32_t)rows[i].size();
+  m.csr_col.resize(m.csr_ptr[N]);
+  m.csr_val.resize(m.csr_ptr[N]);
+  for (int64_t i = 0; i < N; ++i)
+    for (size_t k = 0; k < rows[i].size(); ++k) {
+      m.csr_col[m.csr_ptr[i] + k] = rows[i][k].first;
+      m.csr_val[m.csr_ptr[i] + k] = rows[i][k].second;
+    }
   const int64_t nslices = m.Np / 64;
   m.sell_ptr.assign(nslices + 1, 0);
   for (int64_t s = 0; s < nslices; ++s) {

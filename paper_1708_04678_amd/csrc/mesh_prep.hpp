@@ -27,12 +27,24 @@ struct MeshPrep {
   std::vector<int32_t> sell_ptr;   // [Np/64 + 1] entry offset of each slice
   std::vector<int32_t> sell_col;
   std::vector<double> sell_val;
+  // the same rows in CSR form: row i holds (j, a_ij) for its mesh neighbours j, sorted by j
+  std::vector<int32_t> csr_ptr, csr_col;
+  std::vector<double> csr_val;
   int64_t offdiag_nnz = 0;         // true (unpadded) off-diagonal count
   double period_x = 0.0;
+  // internal orderings: node_perm[internal] = caller node, node_iperm[caller] = internal,
+  // elem_perm[internal] = caller triangle
+  std::vector<int32_t> node_perm, node_iperm, elem_perm;
+  uint64_t perm_hash = 0;
 };
 
 // Returns 0 on success or a negative FELBM_E* code with a message in err.
+// Arrays in `out` are in the internal order: nodes are renumbered by recursive
+// bisection into compact blocks of `block` consecutive nodes (the workgroup
+// tile of the gather kernels), triangles sorted by their smallest internal
+// vertex.  reorder = false keeps the caller's order.
 int prepare_mesh(int64_t n_nodes, const double* xy, int64_t n_tris, const int32_t* tri, int64_t n_wall,
-                 const int32_t* wall_edge, double period_x, MeshPrep& out, std::string& err);
+                 const int32_t* wall_edge, double period_x, MeshPrep& out, std::string& err,
+                 bool reorder = true, int block = 256);
 
 }  // namespace felbm

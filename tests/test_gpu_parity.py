@@ -218,8 +218,8 @@ def test_nonfinite_state_is_reported():
     ctx = make_ctx(w.mesh, w.phys, w.omega_c)
     ctx.init(w.C0)
     blob = bytearray(ctx.save_state())
-    # header is 32 bytes; poison one population value of node 100 (fp64)
-    off = 32 + 8 * 100
+    # header is 40 bytes; poison one population value of internal node 100 (fp64)
+    off = 40 + 8 * 100
     blob[off:off + 8] = np.array([np.nan]).tobytes()
     ctx.load_state(bytes(blob))
     import paper_1708_04678_amd as felbm
