@@ -202,6 +202,38 @@ int felbm_load_state(felbm_ctx* ctx, const void* buf, int64_t bytes);
  * the library's own stream).  The stream is not owned by the library. */
 int felbm_bind_stream(felbm_ctx* ctx, void* hip_stream);
 
+/* ---- adjoint (reverse mode) ------------------------------------------------
+ * Gradients of a loss of the final composition with respect to the per-node
+ * wetting potential Omega_c (the parameter of eq. bc2 and Young's relation,
+ * Sec. II.B), by a hand-written vector-Jacobian product of every step.
+ *
+ * felbm_forward_ckpt: advance n_steps >= 1 from the current state (like
+ *   felbm_step) and keep the state every `every` steps on the device
+ *   (ceil(n_steps/every) + every states of 18 populations per node).
+ * felbm_backward: reverse the last felbm_forward_ckpt run.  dL_dC_dev
+ *   [n_nodes] (device, caller node order, double) is dL/dC of the final
+ *   composition C = sum_a h_a; dL_domega_dev [n_nodes] (device, caller order,
+ *   double) receives dL/dOmega_c (nonzero at wall nodes only).  Segments
+ *   between checkpoints are recomputed forward; the final state and the step
+ *   counter are restored afterwards.  Runs on the bound stream and waits.
+ *   Errors: ESTATE (no forward_ckpt run), EINVAL, EDEVICE.
+ * felbm_backward_host: the same with host arrays. */
+int felbm_forward_ckpt(felbm_ctx* ctx, int64_t n_steps, int64_t every);
+int felbm_backward(felbm_ctx* ctx, const double* dL_dC_dev, double* dL_domega_dev);
+int felbm_backward_host(felbm_ctx* ctx, const double* dL_dC, double* dL_domega);
+
+/* The same with a general seed (host arrays, caller order): dL/dpsi_bar of
+ * the final populations dL_dpsi [18][n_nodes] (may be NULL) plus dL_dC
+ * [n_nodes] (may be NULL) added to every h_a; outputs dL_domega [n_nodes] and,
+ * if not NULL, dL/dpsi_bar of the populations the run started from,
+ * dL_dpsi0 [18][n_nodes]. */
+int felbm_backward_full(felbm_ctx* ctx, const double* dL_dpsi, const double* dL_dC, double* dL_domega,
+                        double* dL_dpsi0);
+
+/* Lumped mass vector m_i = int phi_i (row sums of M11) in caller order, for
+ * losses such as int C dx = sum_i m_i C_i.  Errors: EINVAL, ESTATE. */
+int felbm_lumped_mass(felbm_ctx* ctx, double* out);
+
 /* Per-kernel timing with HIP events recorded around every launch of the
  * step's kernels (for measurement; adds event records to the stream). */
 typedef struct {

@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "adjoint.hpp"
 #include "felbm.h"
 #include "kernels.hpp"
 #include "mesh_prep.hpp"
@@ -21,12 +22,14 @@ namespace {
 
 enum KernelId {
   K_MOMENTS = 0, K_REDUCE, K_GRAD, K_LAPC, K_GRADMU, K_LAPMU, K_RHS, K_SWEEP_FIRST, K_SWEEP_MID, K_SWEEP_LAST,
-  K_PAIR_FIRST, K_PAIR_MID, K_PAIR_LAST, K_COUNT
+  K_PAIR_FIRST, K_PAIR_MID, K_PAIR_LAST, K_ADJ_PREP, K_ADJ_FORCE, K_ADJ_STREAM, K_ADJ_GMU, K_ADJ_MU, K_ADJ_GC,
+  K_ADJ_NODE, K_COUNT
 };
 const char* const kKernelNames[K_COUNT] = {"moments_collide", "reduce_final", "elem_grad", "lapC_mu",
                                            "elem_gradmu", "elem_lapmu", "rhs_gather", "sweep_first",
                                            "sweep_mid", "sweep_last", "sweep2_first", "sweep2_mid",
-                                           "sweep2_last"};
+                                           "sweep2_last", "adj_prep", "adj_force", "adj_stream",
+                                           "adj_gmu", "adj_mu", "adj_gC", "adj_node"};
 
 struct KStat {
   int64_t launches = 0;
@@ -94,6 +97,14 @@ struct felbm_ctx {
   int32_t *ring_off = nullptr, *ring_w = nullptr, *r2_off = nullptr, *r2 = nullptr;
   uint16_t* rslot = nullptr;
   void* rval = nullptr;
+  // adjoint: element reverse adjacency, caller<->internal maps, reverse buffers, checkpoints
+  int32_t *erev = nullptr, *d_node_perm = nullptr;
+  void *lam = nullptr, *lhat = nullptr;
+  double *ea = nullptr, *lgmu = nullptr, *lgC = nullptr, *lmu = nullptr, *gomega = nullptr;
+  void* ck_buf = nullptr;     // checkpoints every ck_every steps
+  void* seg_buf = nullptr;    // replayed states of one segment
+  int64_t ck_steps = 0, ck_every = 0, ck_count = 0, ck_start = 0;
+  size_t ck_cap = 0, seg_cap = 0;
   // FP32 only: FP64 composition transport (remainder, rhs moment, iterates, diagonal)
   double *rC = nullptr, *fC = nullptr, *xCa = nullptr, *xCb = nullptr, *dlt = nullptr;
   double* partials = nullptr;
@@ -420,6 +431,121 @@ std::vector<double> chebyshev_steps(int K, double lo, double hi) {
     --j;
   }
   return out;
+}
+
+// ---------------------------------------------------------------------------
+// adjoint (reverse pass) of the step, with checkpoints
+// ---------------------------------------------------------------------------
+size_t dev_state_bytes(const felbm_ctx* c) {
+  return (size_t)18 * c->Np * c->rs + (c->prm.precision == FELBM_FP32 ? (size_t)c->Np * 8 : 0);
+}
+
+int state_to(felbm_ctx* c, void* dst) {
+  const size_t pb = (size_t)18 * c->Np * c->rs;
+  HIP_OK(c, hipMemcpyAsync(dst, c->pop, pb, hipMemcpyDeviceToDevice, c->stream));
+  if (c->rC) HIP_OK(c, hipMemcpyAsync((char*)dst + pb, c->rC, c->Np * 8, hipMemcpyDeviceToDevice, c->stream));
+  return FELBM_OK;
+}
+
+int state_from(felbm_ctx* c, const void* src) {
+  const size_t pb = (size_t)18 * c->Np * c->rs;
+  HIP_OK(c, hipMemcpyAsync(c->pop, src, pb, hipMemcpyDeviceToDevice, c->stream));
+  if (c->rC) HIP_OK(c, hipMemcpyAsync(c->rC, (const char*)src + pb, c->Np * 8, hipMemcpyDeviceToDevice, c->stream));
+  return FELBM_OK;
+}
+
+int ensure_adjoint_buffers(felbm_ctx* c) {
+  if (c->lam) return FELBM_OK;
+  const size_t pb = (size_t)18 * c->Np * c->rs;
+  TRY(dalloc_bytes(c, &c->lam, pb));
+  TRY(dalloc_bytes(c, &c->lhat, pb));
+  TRY(dalloc(c, &c->ea, (size_t)EA_N * c->E));
+  TRY(dalloc(c, &c->lgmu, 2 * c->E));
+  TRY(dalloc(c, &c->lgC, 2 * c->E));
+  TRY(dalloc(c, &c->lmu, c->Np));
+  TRY(dalloc(c, &c->gomega, c->Np));
+  return FELBM_OK;
+}
+
+AdjGeom adj_geom(felbm_ctx* c) {
+  return AdjGeom{c->tri,  c->enbr,     c->erev, c->geo, c->n2e_ptr, c->n2e,     c->mass,
+                 c->wall_nbr, c->wall_len, c->bc, c->is_wall, (int)c->N, (int)c->Np, (int)c->E};
+}
+
+// transpose of the solve: the same K sweeps applied to f = (W lam)/m, result returned
+template <typename real>
+int enqueue_adjoint_solve(felbm_ctx* c, real** result) {
+  const int K = c->prm.solver_sweeps;
+  real *xa = (real*)c->xa, *xb = (real*)c->xb;
+  if (K == 0) {
+    HIP_OK(c, hipMemcpyAsync(xa, c->f, (size_t)18 * c->Np * c->rs, hipMemcpyDeviceToDevice, c->stream));
+    *result = xa;
+    return FELBM_OK;
+  }
+  // the FP32 sweeps also carry the FP64 composition scalar: run it on zeros
+  if (c->fC) HIP_OK(c, hipMemsetAsync(c->fC, 0, c->Np * 8, c->stream));
+  ConsArgs cs{c->fC, nullptr, c->xCa, c->dlt, c->Cn, nullptr, c->cheb_w[0]};
+  const std::vector<double>& w = c->cheb_w;
+  real *cur = xa, *nxt = xb;
+  double *ccur = c->xCa, *cnxt = c->xCb;
+  int j = 0;
+  if (!(c->use_pair && K >= 2) || K % 2 == 1) {
+    TRY((sweep<real, 0>(c, K_SWEEP_FIRST, nullptr, cur, (real)w[0], cs)));
+    j = 1;
+  }
+  if (c->use_pair && K >= 2) {
+    while (j < K) {
+      cs.xCin = ccur;
+      cs.xCout = cnxt;
+      if (j == 0)
+        TRY((sweep2<real, 0>(c, K_PAIR_FIRST, nullptr, nxt, w[0], w[1], cs)));
+      else
+        TRY((sweep2<real, 1>(c, K_PAIR_MID, cur, nxt, w[j], w[j + 1], cs)));
+      std::swap(cur, nxt);
+      std::swap(ccur, cnxt);
+      j += 2;
+    }
+  } else {
+    for (; j < K; ++j) {
+      cs.w = w[j];
+      cs.xCin = ccur;
+      cs.xCout = cnxt;
+      TRY((sweep<real, 1>(c, K_SWEEP_MID, cur, nxt, (real)w[j], cs)));
+      std::swap(cur, nxt);
+      std::swap(ccur, cnxt);
+    }
+  }
+  *result = cur;
+  return FELBM_OK;
+}
+
+// one reverse step: lam (= dL/dpsi_bar^{n+1}) -> dL/dpsi_bar^n, gomega += dL/dOmega_c.
+// Requires psi_bar^n in pop and its forward fields recomputed.
+template <typename real>
+int enqueue_adjoint_step(felbm_ctx* c) {
+  const int gN = grid_for(c->N), gE = grid_for(c->E);
+  AdjGeom g = adj_geom(c);
+  real* lam = (real*)c->lam;
+  TRY(launch(c, K_ADJ_PREP, k_adj_prep<real>, gN, g, (const real*)lam, (real*)c->f));
+  real* lb = nullptr;
+  TRY(enqueue_adjoint_solve<real>(c, &lb));
+  TRY(launch(c, K_ADJ_FORCE, k_adj_force<real>, gE, g, c->sp, (const real*)lb, (const double*)c->Cn,
+             (const real*)c->uxn, (const real*)c->uyn, (const double*)c->mu, (const double*)c->gC, (const real*)c->gp,
+             (const double*)c->lapmu, c->ea));
+  TRY(launch(c, K_ADJ_STREAM, k_adj_stream<real>, gN, g, c->sp.dt, (const real*)lam, (const real*)lb,
+             (real*)c->lhat));
+  TRY(launch(c, K_ADJ_GMU, k_adj_gmu, gE, g, (const double*)c->ea, c->lgmu));
+  TRY(launch(c, K_ADJ_MU, k_adj_mu, gN, g, (const double*)c->ea, (const double*)c->lgmu, c->lmu));
+  TRY(launch(c, K_ADJ_GC, k_adj_gC, gE, g, c->sp, (const double*)c->ea, (const double*)c->lmu, c->lgC));
+  const double bc_scale = c->sp.kappa > 0 ? std::sqrt(2.0 * c->sp.kappa * c->sp.beta) / c->sp.kappa : 0.0;
+  TRY(launch(c, K_ADJ_NODE, k_adj_node<real>, gN, g, c->sp, bc_scale, (const real*)c->pop, (const double*)c->Cn,
+             (const real*)c->pn, (const real*)c->uxn, (const real*)c->uyn, (const double*)c->ea,
+             (const double*)c->lgC, (const double*)c->lmu, (const real*)c->lhat, lam, c->gomega));
+  return FELBM_OK;
+}
+
+int enqueue_adjoint_step_any(felbm_ctx* c) {
+  return c->prm.precision == FELBM_FP64 ? enqueue_adjoint_step<double>(c) : enqueue_adjoint_step<float>(c);
 }
 
 // Ring-1 rows (the rows of the tile's halo nodes, in slots of tile + ring 1 +
@@ -756,6 +882,21 @@ int felbm_upload_mesh(felbm_ctx* c, int64_t n_nodes, const double* xy, int64_t n
     TRY(upload(c, c->dlt, dlt));
     HIP_OK(c, hipStreamSynchronize(c->stream));  // host vectors are about to go out of scope
   }
+  {
+    std::vector<int32_t> erev(3 * E, -1);
+    for (int64_t e = 0; e < E; ++e)
+      for (int l = 0; l < 3; ++l) {
+        const int32_t nb = m.enbr[l * E + e];
+        if (nb < 0) continue;
+        for (int r = 0; r < 3; ++r)
+          if (m.enbr[r * E + nb] == (int32_t)e) erev[l * E + e] = r;
+      }
+    TRY(dalloc(c, &c->erev, 3 * E));
+    TRY(upload(c, c->erev, erev));
+    TRY(dalloc(c, &c->d_node_perm, N));
+    TRY(upload(c, c->d_node_perm, m.node_perm));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+  }
   set_kernel_bytes(c);
   TRY(build_tiles(c, m));
   std::vector<double> zeros(N, 0.0);
@@ -1074,6 +1215,162 @@ int felbm_kernel_stats(felbm_ctx* c, felbm_kstat* out, int32_t max_entries, int3
   return FELBM_OK;
 }
 
+int felbm_forward_ckpt(felbm_ctx* c, int64_t n_steps, int64_t every) {
+  if (!c) return FELBM_EINVAL;
+  if (!c->has_state) return fail(c, FELBM_ESTATE, "forward_ckpt: not initialised");
+  if (n_steps < 1 || every < 1) return fail(c, FELBM_EINVAL, "forward_ckpt: n_steps and every must be >= 1");
+  TRY(ensure_adjoint_buffers(c));
+  const size_t sb = dev_state_bytes(c);
+  const int64_t nck = (n_steps + every - 1) / every;
+  const size_t need_ck = (size_t)nck * sb, need_seg = (size_t)std::min(every, n_steps) * sb;
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  if (need_ck > c->ck_cap) {
+    if (c->ck_buf) HIP_OK(c, hipFree(c->ck_buf));
+    c->ck_buf = nullptr;
+    c->ck_cap = 0;
+    if (hipMalloc(&c->ck_buf, need_ck) != hipSuccess) return fail(c, FELBM_ENOMEM, "forward_ckpt: checkpoint storage");
+    c->ck_cap = need_ck;
+  }
+  if (need_seg > c->seg_cap) {
+    if (c->seg_buf) HIP_OK(c, hipFree(c->seg_buf));
+    c->seg_buf = nullptr;
+    c->seg_cap = 0;
+    if (hipMalloc(&c->seg_buf, need_seg) != hipSuccess) return fail(c, FELBM_ENOMEM, "forward_ckpt: segment storage");
+    c->seg_cap = need_seg;
+  }
+  c->ck_steps = n_steps;
+  c->ck_every = every;
+  c->ck_count = nck;
+  c->ck_start = c->step;
+  for (int64_t s = 0; s < n_steps; ++s) {
+    if (s % every == 0) TRY(state_to(c, (char*)c->ck_buf + (size_t)(s / every) * sb));
+    TRY(enqueue_steps(c, 1));
+  }
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  if (c->timing) TRY(harvest_timing(c));
+  int32_t bad = -1;
+  HIP_OK(c, hipMemcpy(&bad, c->first_bad, sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (bad >= 0) return fail(c, FELBM_ENONFINITE, "forward_ckpt: non-finite state entering step " + std::to_string(bad));
+  return FELBM_OK;
+}
+
+namespace {
+// reverse the last forward_ckpt run from the seed already in c->lam
+int run_backward(felbm_ctx* c, double* dL_domega_dev) {
+  const size_t sb = dev_state_bytes(c);
+  const int N = (int)c->N;
+  const int g1 = (N + BLOCK - 1) / BLOCK;
+  // the forward's final state, restored when done
+  void* final_state = nullptr;
+  HIP_OK(c, hipMallocAsync(&final_state, sb, c->stream));
+  TRY(state_to(c, final_state));
+  const int64_t end_step = c->step;
+  HIP_OK(c, hipMemsetAsync(c->gomega, 0, c->Np * 8, c->stream));
+  for (int64_t seg = c->ck_count - 1; seg >= 0; --seg) {
+    const int64_t m0 = seg * c->ck_every, m1 = std::min(c->ck_steps, m0 + c->ck_every);
+    // replay the segment, keeping every state
+    TRY(state_from(c, (const char*)c->ck_buf + (size_t)seg * sb));
+    c->step = c->ck_start + m0;
+    for (int64_t m = m0; m < m1; ++m) {
+      TRY(state_to(c, (char*)c->seg_buf + (size_t)(m - m0) * sb));
+      if (m + 1 < m1) TRY(enqueue_steps(c, 1));
+    }
+    for (int64_t m = m1 - 1; m >= m0; --m) {
+      TRY(state_from(c, (const char*)c->seg_buf + (size_t)(m - m0) * sb));
+      TRY(enqueue_fields_any(c, false, false, nullptr));
+      TRY(enqueue_adjoint_step_any(c));
+    }
+  }
+  hipLaunchKernelGGL(k_to_caller, dim3(g1), dim3(BLOCK), 0, c->stream, N, (const int*)c->d_node_perm,
+                     (const double*)c->gomega, dL_domega_dev);
+  HIP_OK(c, hipGetLastError());
+  TRY(state_from(c, final_state));
+  HIP_OK(c, hipFreeAsync(final_state, c->stream));
+  c->step = end_step;
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  if (c->timing) TRY(harvest_timing(c));
+  return FELBM_OK;
+}
+}  // namespace
+
+int felbm_backward(felbm_ctx* c, const double* dL_dC_dev, double* dL_domega_dev) {
+  if (!c) return FELBM_EINVAL;
+  if (c->ck_steps <= 0) return fail(c, FELBM_ESTATE, "backward: no felbm_forward_ckpt run to reverse");
+  if (!dL_dC_dev || !dL_domega_dev) return fail(c, FELBM_EINVAL, "backward: null device pointer");
+  const int N = (int)c->N, Np = (int)c->Np;
+  const int g1 = (N + BLOCK - 1) / BLOCK;
+  if (c->prm.precision == FELBM_FP64)
+    hipLaunchKernelGGL(k_adj_init<double>, dim3(g1), dim3(BLOCK), 0, c->stream, N, Np, (const int*)c->d_node_perm,
+                       dL_dC_dev, (double*)c->lam);
+  else
+    hipLaunchKernelGGL(k_adj_init<float>, dim3(g1), dim3(BLOCK), 0, c->stream, N, Np, (const int*)c->d_node_perm,
+                       dL_dC_dev, (float*)c->lam);
+  HIP_OK(c, hipGetLastError());
+  return run_backward(c, dL_domega_dev);
+}
+
+int felbm_backward_full(felbm_ctx* c, const double* dL_dpsi, const double* dL_dC, double* dL_domega,
+                        double* dL_dpsi0) {
+  if (!c) return FELBM_EINVAL;
+  if (c->ck_steps <= 0) return fail(c, FELBM_ESTATE, "backward_full: no felbm_forward_ckpt run to reverse");
+  if (!dL_domega) return fail(c, FELBM_EINVAL, "backward_full: null dL_domega");
+  const int64_t N = c->N, Np = c->Np;
+  std::vector<double> seed(18 * Np, 0.0);
+  for (int64_t k = 0; k < N; ++k) {
+    const int64_t s = c->node_perm[k];
+    for (int a = 0; a < 18; ++a) {
+      double v = dL_dpsi ? dL_dpsi[a * N + s] : 0.0;
+      if (dL_dC && a >= 9) v += dL_dC[s];
+      seed[a * Np + k] = v;
+    }
+  }
+  if (c->prm.precision == FELBM_FP64) {
+    HIP_OK(c, hipMemcpyAsync(c->lam, seed.data(), seed.size() * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+  } else {
+    std::vector<float> s32(seed.begin(), seed.end());
+    HIP_OK(c, hipMemcpyAsync(c->lam, s32.data(), s32.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+  }
+  double* dout = nullptr;
+  HIP_OK(c, hipMalloc((void**)&dout, N * 8));
+  int r = run_backward(c, dout);
+  if (r == FELBM_OK && hipMemcpy(dL_domega, dout, N * 8, hipMemcpyDeviceToHost) != hipSuccess)
+    r = fail(c, FELBM_EDEVICE, "backward_full: copy out");
+  (void)hipFree(dout);
+  if (r == FELBM_OK && dL_dpsi0) r = copy_pops_out(c, c->lam, dL_dpsi0);
+  return r;
+}
+
+int felbm_backward_host(felbm_ctx* c, const double* dL_dC, double* dL_domega) {
+  if (!c) return FELBM_EINVAL;
+  if (!dL_dC || !dL_domega) return fail(c, FELBM_EINVAL, "backward_host: null pointer");
+  double *din = nullptr, *dout = nullptr;
+  HIP_OK(c, hipMalloc((void**)&din, c->N * 8));
+  if (hipMalloc((void**)&dout, c->N * 8) != hipSuccess) {
+    hipFree(din);
+    return fail(c, FELBM_ENOMEM, "backward_host: allocation");
+  }
+  int r = FELBM_OK;
+  if (hipMemcpy(din, dL_dC, c->N * 8, hipMemcpyHostToDevice) != hipSuccess) r = fail(c, FELBM_EDEVICE, "copy in");
+  if (r == FELBM_OK) r = felbm_backward(c, din, dout);
+  if (r == FELBM_OK && hipMemcpy(dL_domega, dout, c->N * 8, hipMemcpyDeviceToHost) != hipSuccess)
+    r = fail(c, FELBM_EDEVICE, "copy out");
+  (void)hipFree(din);
+  (void)hipFree(dout);
+  return r;
+}
+
+int felbm_lumped_mass(felbm_ctx* c, double* out) {
+  if (!c) return FELBM_EINVAL;
+  if (!c->has_mesh) return fail(c, FELBM_ESTATE, "lumped_mass: no mesh");
+  if (!out) return fail(c, FELBM_EINVAL, "lumped_mass: null output");
+  std::vector<double> m(c->N);
+  HIP_OK(c, hipMemcpy(m.data(), c->mass, c->N * 8, hipMemcpyDeviceToHost));
+  for (int64_t k = 0; k < c->N; ++k) out[c->node_perm[k]] = m[k];
+  return FELBM_OK;
+}
+
 int felbm_mesh_info(const felbm_ctx* c, int64_t* n_nodes, int64_t* n_tris, int64_t* n_wall_edges, int64_t* nnz) {
   if (!c || !c->has_mesh) return FELBM_ESTATE;
   if (n_nodes) *n_nodes = c->N;
@@ -1101,6 +1398,8 @@ void felbm_destroy(felbm_ctx* c) {
   }
   for (auto e : c->event_pool) hipEventDestroy(e);
   for (void* p : c->allocations) hipFree(p);
+  if (c->ck_buf) hipFree(c->ck_buf);
+  if (c->seg_buf) hipFree(c->seg_buf);
   if (c->own_stream) hipStreamDestroy(c->own_stream);
   delete c;
 }

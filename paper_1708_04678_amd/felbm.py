@@ -71,6 +71,11 @@ _SIGNATURES = {
                          ct.POINTER(ct.c_int64)], ct.c_int),
     "felbm_validate_mesh": ([ct.c_int64, _D, ct.c_int64, _I, ct.c_int64, _I, ct.c_double, ct.c_char_p, ct.c_int32],
                             ct.c_int),
+    "felbm_forward_ckpt": ([_P, ct.c_int64, ct.c_int64], ct.c_int),
+    "felbm_backward": ([_P, ct.c_void_p, ct.c_void_p], ct.c_int),
+    "felbm_backward_host": ([_P, _D, _D], ct.c_int),
+    "felbm_lumped_mass": ([_P, _D], ct.c_int),
+    "felbm_backward_full": ([_P, _D, _D, _D, _D], ct.c_int),
     "felbm_destroy": ([_P], None),
 }
 
@@ -83,6 +88,14 @@ def load_library() -> ct.CDLL:
     """Load libfelbm.so from the package tree; raises if it was not built."""
     global _lib
     if _lib is None:
+        # One HIP runtime per process: torch ships its own copy of the HIP
+        # runtime under the same soname, and whichever is loaded first serves
+        # both.  Loading torch's first keeps torch usable and makes torch
+        # streams valid handles for felbm_bind_stream.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(_LIB_PATH):
             raise RuntimeError(f"{_LIB_PATH} is missing: build it with __graft_entry__.build() "
                                "(python -m paper_1708_04678_amd.build)")
@@ -220,6 +233,36 @@ class Context:
         self._check(self._lib.felbm_kernel_stats(self._h, buf, 32, ct.byref(n)))
         return [{"name": buf[k].name.decode(), "launches": buf[k].launches, "total_ms": buf[k].total_ms,
                  "bytes_per_launch": buf[k].bytes_per_launch} for k in range(n.value)]
+
+    # -- adjoint ---------------------------------------------------------------
+    def forward_ckpt(self, n_steps, every):
+        self._check(self._lib.felbm_forward_ckpt(self._h, int(n_steps), int(every)))
+
+    def backward(self, dL_dC_dev_ptr, dL_domega_dev_ptr):
+        """Device pointers (ints) to N doubles each, caller node order."""
+        self._check(self._lib.felbm_backward(self._h, ct.c_void_p(dL_dC_dev_ptr), ct.c_void_p(dL_domega_dev_ptr)))
+
+    def backward_host(self, dL_dC):
+        g = _f64(dL_dC, (self.n_nodes,))
+        out = np.empty(self.n_nodes)
+        self._check(self._lib.felbm_backward_host(self._h, _dptr(g), _dptr(out)))
+        return out
+
+    def backward_full(self, dL_dpsi=None, dL_dC=None, want_dpsi0=True):
+        N = self.n_nodes
+        dpsi = None if dL_dpsi is None else _f64(dL_dpsi, (18, N))
+        dC = None if dL_dC is None else _f64(dL_dC, (N,))
+        gom = np.empty(N)
+        d0 = np.empty((18, N)) if want_dpsi0 else None
+        self._check(self._lib.felbm_backward_full(self._h, None if dpsi is None else _dptr(dpsi),
+                                                  None if dC is None else _dptr(dC), _dptr(gom),
+                                                  None if d0 is None else _dptr(d0)))
+        return gom, d0
+
+    def lumped_mass(self):
+        out = np.empty(self.n_nodes)
+        self._check(self._lib.felbm_lumped_mass(self._h, _dptr(out)))
+        return out
 
     def mesh_info(self):
         v = [ct.c_int64() for _ in range(4)]

@@ -1,0 +1,180 @@
+"""Hand-written adjoint of the step (GPU, through the C ABI) against the FP64
+oracle's complex-step tangent and against finite differences.
+
+The adjoint is the transpose of the discrete step's Jacobian, so for any
+seed lam and any direction (d_psi, d_Omega) the dot-product identity
+<lam, J_psi d_psi + J_Omega d_Omega> = <J_psi^T lam, d_psi> + <J_Omega^T lam, d_Omega>
+holds to rounding when both sides use the same step.  The oracle's
+complex-step tangent is exact to rounding, and its PCG solve (1e-13
+relative residual) and the GPU's 32 Chebyshev sweeps (2 * 3^-32) agree to
+~1e-13, so FP64 is held to 1e-11 relative.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import log, make_ctx, stack
+from oracle import Oracle
+from workloads import config, droplet_field, make_physics, split_grid_mesh, uniform_rows, wetting_from_angles
+
+pytestmark = pytest.mark.gpu
+
+
+def small_case(seed=5):
+    mesh = split_grid_mesh(24.0, uniform_rows(12.0, 13), 24, seed=[seed])
+    phys = make_physics(sigma=0.01, m_rho=5.0, m_nu=2.0, dt=0.1)
+    om = wetting_from_angles(mesh, 70.0, 100.0)
+    C0 = droplet_field(mesh, [(12.0, 0.0, 6.0)], phys.xi)
+    return mesh, phys, om, C0
+
+
+def oracle_tangent(mesh, phys, om, C0, d_psi, d_om, n):
+    """Complex-step derivative of the populations after n steps along (d_psi, d_om)."""
+    h = 1e-30
+    o = Oracle(mesh, phys, om.astype(complex) + 1j * h * d_om)
+    g, hh = o.init_state(C0)
+    g = g + 1j * h * d_psi[:9].T
+    hh = hh + 1j * h * d_psi[9:].T
+    g, hh = o.run(g, hh, n)
+    return stack(g.imag / h, hh.imag / h)
+
+
+@pytest.mark.parametrize("n,every", [(1, 1), (4, 2), (5, 3)])
+def test_dot_product_identity_fp64(n, every):
+    mesh, phys, om, C0 = small_case()
+    log(f"adjoint dot-product test, {n} steps, checkpoint every {every}")
+    rng = np.random.default_rng(n)
+    N = mesh.n_nodes
+    lam = rng.normal(size=(18, N))
+    d_psi = rng.normal(size=(18, N)) * 1e-2
+    d_om = np.zeros(N)
+    walls = mesh.wall_nodes()
+    d_om[walls] = rng.normal(size=walls.size)
+    ctx = make_ctx(mesh, phys, om)
+    ctx.init(C0)
+    ctx.forward_ckpt(n, every)
+    g_om, lam0 = ctx.backward_full(dL_dpsi=lam)
+    T = oracle_tangent(mesh, phys, om, C0, d_psi, d_om, n)
+    lhs = np.sum(lam * T)
+    rhs = np.sum(lam0 * d_psi) + np.sum(g_om * d_om)
+    log(f"  <lam, J d> = {lhs:.15e}  <J^T lam, d> = {rhs:.15e}")
+    scale = np.abs(lam * T).sum() + np.abs(lam0 * d_psi).sum() + np.abs(g_om * d_om).sum()
+    assert abs(lhs - rhs) <= 1e-11 * scale
+    # the wetting gradient lives on wall nodes only
+    assert np.all(g_om[~np.isin(np.arange(N), walls)] == 0.0)
+    ctx.close()
+
+
+def test_wetting_gradient_matches_oracle_tangent_per_node():
+    mesh, phys, om, C0 = small_case(seed=6)
+    n = 6
+    log("dL/dOmega per wall node vs oracle complex step, 6 steps")
+    N = mesh.n_nodes
+    x = mesh.xy[:, 0]
+    ctx = make_ctx(mesh, phys, om)
+    m = ctx.lumped_mass()
+    dLdC = m * x   # L = sum_i m_i x_i C_i (first moment of the composition)
+    ctx.init(C0)
+    ctx.forward_ckpt(n, 2)
+    g_om = ctx.backward_host(dLdC)
+    bottom = mesh.wall_nodes(0)
+    for k in bottom[[2, 9, 13, 17]]:
+        d_om = np.zeros(N)
+        d_om[k] = 1.0
+        T = oracle_tangent(mesh, phys, om, C0, np.zeros((18, N)), d_om, n)
+        ref = np.sum(dLdC * T[9:].sum(0))
+        log(f"  node {k}: adjoint {g_om[k]:.12e} tangent {ref:.12e}")
+        assert abs(g_om[k] - ref) <= 1e-9 * abs(ref) + 1e-15
+    ctx.close()
+
+
+def test_checkpoint_interval_does_not_change_gradient():
+    mesh, phys, om, C0 = small_case(seed=7)
+    log("gradient independent of the checkpoint interval")
+    outs = []
+    for every in (1, 4, 12):
+        ctx = make_ctx(mesh, phys, om)
+        ctx.init(C0)
+        ctx.forward_ckpt(12, every)
+        outs.append(ctx.backward_host(ctx.lumped_mass()))
+        ctx.close()
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+def wetted_centroid_loss(mesh, m, C):
+    """Loss of the adjoint workload: droplet centroid x plus the wetted length
+    squared; returns L and dL/dC."""
+    x = mesh.xy[:, 0]
+    M0, M1 = np.sum(m * C), np.sum(m * x * C)
+    xc = M1 / M0
+    we = mesh.wall_edges[mesh.wall_side == 0]
+    dx = mesh.xy[we[:, 1], 0] - mesh.xy[we[:, 0], 0]
+    dx -= mesh.period_x * np.round(dx / mesh.period_x)
+    L_w = np.sum(np.abs(dx) * 0.5 * (C[we[:, 0]] + C[we[:, 1]]))
+    dL = m * x / M0 - M1 * m / M0 ** 2
+    dLw = np.zeros_like(C)
+    np.add.at(dLw, we[:, 0], 0.5 * np.abs(dx))
+    np.add.at(dLw, we[:, 1], 0.5 * np.abs(dx))
+    return xc + L_w ** 2, dL + 2.0 * L_w * dLw
+
+
+def test_adjoint_workload_fp32_vs_fd_fp64():
+    """Adjoint workload (256 x 128 mesh, seeded wettability field with theta in
+    50-130 deg, 500 steps, checkpoint every 50): FP32 forward and FP32 adjoint
+    against central differences (h = 1e-4) of the FP64 forward, at 8 seeded
+    wall nodes; bar 2% relative per component."""
+    w = config(4)
+    mesh, phys = w.mesh, w.phys
+    n, every = w.steps, w.extra["ckpt_every"]
+    log(f"adjoint workload: {mesh.n_nodes} nodes, {n} steps, ckpt {every}")
+    c32 = make_ctx(mesh, phys, w.omega_c, precision="fp32", sweeps=12)
+    m = c32.lumped_mass()
+    c32.init(w.C0)
+    c32.forward_ckpt(n, every)
+    L32, dLdC = wetted_centroid_loss(mesh, m, c32.read("C"))
+    g32 = c32.backward_host(dLdC)
+    c32.close()
+    c64 = make_ctx(mesh, phys, w.omega_c, precision="fp64", sweeps=26)
+
+    def loss(om):
+        c64.set_wetting(om)
+        c64.init(w.C0)
+        c64.step(n)
+        return wetted_centroid_loss(mesh, m, c64.read("C"))[0]
+
+    bottom = mesh.wall_nodes(0)
+    pick = np.random.default_rng([4, 5]).choice(bottom, 8, replace=False)
+    hstep = 1e-4
+    for k in pick:
+        e = np.zeros(mesh.n_nodes)
+        e[k] = hstep
+        fd = (loss(w.omega_c + e) - loss(w.omega_c - e)) / (2 * hstep)
+        log(f"  node {k}: adjoint fp32 {g32[k]:.6e}  fd fp64 {fd:.6e}")
+        assert abs(g32[k] - fd) <= 0.02 * abs(fd) + 1e-3 * np.abs(g32).max()
+    c64.close()
+
+
+def test_torch_autograd_function():
+    """The torch.autograd.Function path (device buffers and stream from torch)
+    gives the same gradient as the host-array reverse pass."""
+    import torch
+    from paper_1708_04678_amd.autograd import composition_after
+    mesh, phys, om, C0 = small_case(seed=8)
+    log("torch.autograd.Function wrapper")
+    ctx = make_ctx(mesh, phys, om)
+    m = torch.tensor(ctx.lumped_mass(), device="cuda")
+    x = torch.tensor(mesh.xy[:, 0], device="cuda")
+    omega = torch.tensor(om, device="cuda", requires_grad=True)
+    C = composition_after(omega, ctx, C0, 8, 3)
+    loss = torch.sum(m * x * C) / torch.sum(m * C)
+    loss.backward()
+    g_torch = omega.grad.cpu().numpy()
+    ref_ctx = make_ctx(mesh, phys, om)
+    ref_ctx.init(C0)
+    ref_ctx.forward_ckpt(8, 3)
+    Cn = ref_ctx.read("C")
+    mm = ref_ctx.lumped_mass()
+    M0, M1 = np.sum(mm * Cn), np.sum(mm * mesh.xy[:, 0] * Cn)
+    g_ref = ref_ctx.backward_host(mm * mesh.xy[:, 0] / M0 - M1 * mm / M0 ** 2)
+    assert np.allclose(g_torch, g_ref, rtol=1e-12, atol=1e-15 * np.abs(g_ref).max())
+    ctx.close()
+    ref_ctx.close()
