@@ -74,6 +74,41 @@ def kernel_pass(ctx, steps):
     return stats
 
 
+def adjoint_run(felbm, stream, sweeps):
+    """Reverse pass of the graded 1024 x 512 workload (527,360 nodes): FP32
+    forward with a checkpoint every 100 steps, FP32 adjoint of the loss
+    1/2 sum_i m_i (C_i - C*_i)^2 after 2000 steps, gradient w.r.t. the
+    wetting potential of every wall node."""
+    import numpy as np
+    from workloads import config
+    w = config(5)
+    n, every = w.steps, w.extra["ckpt_every"]
+    ctx, _ = make_ctx(felbm, w, "fp32", sweeps, stream)
+    m = ctx.lumped_mass()
+    t0 = time.perf_counter()
+    ctx.step(n)
+    t_plain = time.perf_counter() - t0
+    ctx.init(w.C0)
+    t0 = time.perf_counter()
+    ctx.forward_ckpt(n, every)
+    t_fwd = time.perf_counter() - t0
+    C = ctx.read("C")
+    dLdC = m * (C - w.extra["C_target"])
+    t0 = time.perf_counter()
+    g = ctx.backward_host(dLdC)
+    t_bwd = time.perf_counter() - t0
+    state = 18 * 4 * ((w.mesh.n_nodes + 63) // 64 * 64) + 8 * ((w.mesh.n_nodes + 63) // 64 * 64)
+    n_states = (n + every - 1) // every + every
+    ctx.close()
+    return {"workload": w.name, "nodes": w.mesh.n_nodes, "steps": n, "ckpt_every": every,
+            "forward_plain_s": round(t_plain, 3), "forward_ckpt_s": round(t_fwd, 3), "backward_s": round(t_bwd, 3),
+            "backward_over_forward": round(t_bwd / t_plain, 3),
+            "checkpoint_bytes": n_states * state, "states_kept": n_states,
+            "loss": float(0.5 * np.sum(m * (C - w.extra["C_target"]) ** 2)),
+            "grad_norm": float(np.sqrt(np.sum(g * g))),
+            "adjoint_MNUPS": round(w.mesh.n_nodes * n / t_bwd / 1e6, 2)}
+
+
 def cpu_baseline(cfg, rows):
     """The FP64 CPU oracle, as it stands, on the bottom `rows` node rows of the
     same mesh (one step after one warm-up step)."""
@@ -107,6 +142,7 @@ def main():
     ap.add_argument("--sweeps64", type=int, default=26, help="solver sweeps per step in FP64")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=349)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -196,6 +232,10 @@ def main():
         c64.close()
     out["mass_drift_fp32"] = abs(d32["mass"] - d0["mass"]) / d0["mass"]
     c32.close()
+
+    if not args.no_adjoint:
+        log("adjoint (graded 1024x512, 2000 steps)")
+        out["adjoint"] = adjoint_run(felbm, stream, args.sweeps32)
 
     if not args.no_cpu_baseline:
         log(f"cpu baseline (oracle, bottom {args.cpu_rows} rows)")
