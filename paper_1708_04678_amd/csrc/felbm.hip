@@ -639,7 +639,7 @@ int build_pairs(felbm_ctx* c, const MeshPrep& m, const std::vector<int32_t>& r1_
   c->pair_lds = (uint32_t)lds;
   c->use_pair = true;
   const double s = (double)c->rs, Nd = (double)N;
-  const double tmat = (double)tslot.size() * (2.0 + s) + (double)r1.size() * 4.0;
+  const double tmat = (double)m.offdiag_nnz * (2.0 + s) + (double)r1.size() * 4.0;
   const double cons = c->prm.precision == FELBM_FP32 ? 8.0 * Nd : 0.0;
   c->kstat[K_PAIR_FIRST].bytes = 2 * 18 * Nd * s + tmat + 4 * cons;
   c->kstat[K_PAIR_MID].bytes = 3 * 18 * Nd * s + tmat + 4 * cons;
@@ -715,8 +715,9 @@ int build_tiles(felbm_ctx* c, const MeshPrep& m) {
   c->tile_slots = (int)slots;
   c->lds_bytes = (uint32_t)lds;
   c->use_lds = true;
+  // algorithmic bytes: true nonzeros only (padding entries are not counted)
   const double s = (double)c->rs, Nd = (double)N;
-  const double tmat = (double)slot.size() * (2.0 + s) + (double)halo.size() * 4.0;
+  const double tmat = (double)m.offdiag_nnz * (2.0 + s) + (double)halo.size() * 4.0;
   const double cons = c->prm.precision == FELBM_FP32 ? 8.0 * Nd : 0.0;
   c->kstat[K_SWEEP_FIRST].bytes = 2 * 18 * Nd * s + tmat + 3 * cons;
   c->kstat[K_SWEEP_MID].bytes = 3 * 18 * Nd * s + tmat + 4 * cons;
