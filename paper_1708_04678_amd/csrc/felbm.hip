@@ -283,6 +283,9 @@ int sweep(felbm_ctx* c, int kid, const real* xin, real* xout, real w, const Cons
   if (c->use_lds) {
     TileArgs ta{c->tile_off, c->tslot, c->halo_off, c->halo, c->ntiles, c->tile_slots};
     const int grid = (c->ntiles + 7) / 8 * 8;
+    if constexpr (std::is_same<real, float>::value)
+      return launch_sm(c, kid, k_sweep_dma<MODE>, grid, BLOCK, c->lds_bytes, N, Np, ta, (const float*)c->tval, f, xin,
+                       xout, pop, (const uint8_t*)c->is_wall, w, cs);
     return launch_sm(c, kid, k_sweep_lds<real, MODE>, grid, BLOCK, c->lds_bytes, N, Np, ta, (const real*)c->tval, f, xin,
                      xout, pop, (const uint8_t*)c->is_wall, w, cs);
   }
@@ -413,8 +416,8 @@ int copy_pops_out(felbm_ctx* c, const void* dev, double* out) {
   if (r == FELBM_OK)
     for (int64_t a = 0; a < 18; ++a)
       for (int64_t k = 0; k < c->N; ++k) out[a * c->N + c->node_perm[k]] = host[a * c->Np + k];
-  hipFreeAsync(tmp, c->stream);
-  hipStreamSynchronize(c->stream);
+  (void)hipFreeAsync(tmp, c->stream);
+  (void)hipStreamSynchronize(c->stream);
   return r;
 }
 
@@ -1349,7 +1352,7 @@ int felbm_backward_host(felbm_ctx* c, const double* dL_dC, double* dL_domega) {
   double *din = nullptr, *dout = nullptr;
   HIP_OK(c, hipMalloc((void**)&din, c->N * 8));
   if (hipMalloc((void**)&dout, c->N * 8) != hipSuccess) {
-    hipFree(din);
+    (void)hipFree(din);
     return fail(c, FELBM_ENOMEM, "backward_host: allocation");
   }
   int r = FELBM_OK;
