@@ -90,6 +90,10 @@ struct felbm_ctx {
   int32_t *tile_off = nullptr, *halo_off = nullptr, *halo = nullptr;
   uint16_t* tslot = nullptr;
   void* tval = nullptr;
+  // LDS-tiled right-hand side (FP32): per-tile incident-element entries with vertex slots
+  bool use_rhs_lds = false;
+  int32_t* rhs_off = nullptr;
+  int2* rhs_ent = nullptr;
   // two-sweep (temporally blocked) solve: ring-1 rows and ring-2 lists per tile
   bool use_pair = false;
   int pair_slots = 0, pair_slots1 = 0;
@@ -269,6 +273,16 @@ template <typename real>
 int enqueue_rhs(felbm_ctx* c) {
   const int gN = grid_for(c->N);
   const int N = (int)c->N, Np = (int)c->Np, E = (int)c->E;
+  if constexpr (std::is_same<real, float>::value) {
+    if (c->use_rhs_lds) {
+      TileArgs ta{c->tile_off, c->tslot, c->halo_off, c->halo, c->ntiles, c->tile_slots};
+      const int grid = (c->ntiles + 7) / 8 * 8;
+      return launch_sm(c, K_RHS, k_rhs_lds, grid, BLOCK, RHS_LDS_BYTES, N, Np, E, ta, RhsTile{c->rhs_off, c->rhs_ent},
+                       (const double*)c->geo, (const double*)c->gC, (const float*)c->gp, (const double*)c->lapmu,
+                       (const double*)c->Cn, (const float*)c->uxn, (const float*)c->uyn, (const double*)c->mu,
+                       (const float*)c->pop, (const double*)c->mass, c->sp, (float*)c->f, c->fC);
+    }
+  }
   return launch(c, K_RHS, k_rhs<real>, gN, N, Np, E, (const int*)c->n2e_ptr, (const int*)c->n2e, (const int*)c->tri,
                 (const real*)c->geor, (const double*)c->geo, (const double*)c->gC, (const real*)c->gp,
                 (const double*)c->lapmu, (const double*)c->Cn, (const real*)c->uxn, (const real*)c->uyn,
@@ -650,6 +664,63 @@ int build_pairs(felbm_ctx* c, const MeshPrep& m, const std::vector<int32_t>& r1_
   return FELBM_OK;
 }
 
+// Per-tile incident-element entries of the LDS-staged right-hand side (FP32):
+// for node lane of tile t, entry k = (element * 4 + local vertex, LDS slots of
+// the element's three vertices), column-major per tile, padded with -1.  Every
+// vertex of an element incident to a tile node is a tile node or in the tile's
+// halo (the halo lists every node coupled by the mass matrix).
+int build_rhs_tiles(felbm_ctx* c, const MeshPrep& m, const std::vector<int32_t>& halo_off,
+                    const std::vector<int32_t>& halo) {
+  if (c->prm.precision != FELBM_FP32) return FELBM_OK;
+  const int64_t N = m.N, E = m.E, nt = (N + TILE - 1) / TILE;
+  std::vector<int32_t> off(nt + 1, 0);
+  std::vector<int2> ent;
+  int64_t true_entries = 0;
+  for (int64_t t = 0; t < nt; ++t) {
+    const int64_t lo = t * TILE, hi = std::min<int64_t>(N, lo + TILE);
+    const int32_t* hb = halo.data() + halo_off[t];
+    const int32_t* he = halo.data() + halo_off[t + 1];
+    int64_t width = 0;
+    for (int64_t i = lo; i < hi; ++i) width = std::max<int64_t>(width, m.n2e_ptr[i + 1] - m.n2e_ptr[i]);
+    const size_t base = ent.size();
+    ent.resize(base + width * TILE, int2{-1, 0});
+    for (int64_t i = lo; i < hi; ++i) {
+      const int64_t lane = i - lo;
+      for (int32_t q = m.n2e_ptr[i], k = 0; q < m.n2e_ptr[i + 1]; ++q, ++k) {
+        const int32_t packed = m.n2e[q], e = packed >> 2;
+        int32_t slots = 0;
+        for (int v = 0; v < 3; ++v) {
+          const int32_t node = m.tri[v * E + e];
+          int32_t sl;
+          if (node >= lo && node < hi) {
+            sl = (int32_t)(node - lo);
+          } else {
+            const int32_t* p = std::lower_bound(hb, he, node);
+            if (p == he || *p != node) return FELBM_OK;  // keep the global-gather kernel
+            sl = (int32_t)(TILE + (p - hb));
+          }
+          slots |= sl << (9 * v);
+        }
+        ent[base + k * TILE + lane] = int2{packed, slots};
+        ++true_entries;
+      }
+    }
+    off[t + 1] = (int32_t)ent.size();
+  }
+  TRY(dalloc(c, &c->rhs_off, off.size()));
+  TRY(dalloc(c, &c->rhs_ent, ent.size()));
+  TRY(upload(c, c->rhs_off, off));
+  TRY(upload(c, c->rhs_ent, ent));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  c->use_rhs_lds = true;
+  // algorithmic bytes: populations and nodal fields once per node (C, mu, u, mass),
+  // f and fC written, the true entries, element data (FP64 geometry, grad C, grad p, lap mu)
+  const double Nd = (double)N, Ed = (double)E;
+  c->kstat[K_RHS].bytes = 2 * 18 * Nd * 4 + Nd * (8 + 8 + 4 + 4 + 8 + 8) + (double)true_entries * 8 +
+                          Ed * (56 + 16 + 8 + 8) + (double)halo.size() * 4;
+  return FELBM_OK;
+}
+
 // Per-tile halo lists and local-slot matrix rows for the LDS-staged sweep.
 // Falls back to the global sliced-ELL sweep when a tile row is wider than
 // MAXW or the staging buffers would exceed 64 KiB of LDS.
@@ -725,6 +796,7 @@ int build_tiles(felbm_ctx* c, const MeshPrep& m) {
   c->kstat[K_SWEEP_FIRST].bytes = 2 * 18 * Nd * s + tmat + 3 * cons;
   c->kstat[K_SWEEP_MID].bytes = 3 * 18 * Nd * s + tmat + 4 * cons;
   c->kstat[K_SWEEP_LAST].bytes = 4 * 18 * Nd * s + tmat + Nd + 5 * cons;
+  TRY(build_rhs_tiles(c, m, halo_off, halo));
   TRY(build_pairs(c, m, halo_off, halo, tile_off, slot));
   return FELBM_OK;
 }

@@ -466,6 +466,202 @@ __global__ void __launch_bounds__(BLOCK) k_rhs(int N, int Np, int E, const int* 
 }
 
 // ----------------------------------------------------------------------------
+// Tiles of 256 consecutive (internal-order) nodes, their halo lists and LDS
+// slots, shared by the LDS-staged right-hand side and solve sweeps.
+// ----------------------------------------------------------------------------
+constexpr int TILE = BLOCK;
+constexpr int MAXW = 12;
+// compile-time LDS strides (so that population offsets are instruction
+// immediates): one-sweep halo <= 128; two-sweep ring 1 <= 128, rings 1+2 <= 256
+constexpr int HALO_MAX = 128;
+constexpr int SLOTS1 = TILE + HALO_MAX;     // tile + ring 1
+constexpr int SLOTS2 = TILE + 2 * HALO_MAX; // tile + ring 1 + ring 2
+constexpr int PAIR_G32 = 6;  // populations per LDS pass of the two-sweep kernel (FP32)
+constexpr int PAIR_G64 = 3;  // (FP64)
+
+struct TileArgs {
+  const int* tile_off;   // [ntiles+1] entry offsets
+  const uint16_t* slot;  // [entries]
+  const int* halo_off;   // [ntiles+1]
+  const int* halo;       // halo node ids
+  int ntiles, slots;     // slots = 256 + largest halo
+};
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// each active lane's 16 (4) bytes at src land at lds_wave_base + lane * 16 (4)
+__device__ __forceinline__ void lds_dma16(const void* src, void* lds_wave_base) {
+  __builtin_amdgcn_global_load_lds(src, (lds_void_t*)lds_wave_base, 16, 0, 0);
+}
+__device__ __forceinline__ void lds_dma4(const void* src, void* lds_wave_base) {
+  __builtin_amdgcn_global_load_lds(src, (lds_void_t*)lds_wave_base, 4, 0, 0);
+}
+
+// ----------------------------------------------------------------------------
+// The same right-hand side with the vertex data of a 256-node tile and its
+// halo staged in LDS (FP32): post-collision populations by LDS DMA, the nodal
+// fields C, mu, u by ordinary loads.  Thread = node; its incident elements are
+// listed per tile column-major (entry k of lane l at ent_off[t] + k*256 + l):
+// x = element * 4 + local vertex (-1 = padding), y = LDS slots of the
+// element's vertices 0, 1, 2 (9 bits each).  Element data (geometry, grad C,
+// grad p, lap mu) is read from global memory; geometry in FP64 and rounded
+// for the FP32 arithmetic.  The FP64 zeroth h-moment uses
+// div J = sum_a s_a, div Pi = sum_a e_a s_a with
+// s_a = sum_v (e_a . grad N_v) h_hat_{a,v}, in a vertex order that does not
+// depend on which vertex gathers, as in k_rhs.
+// ----------------------------------------------------------------------------
+constexpr unsigned RHS_LDS_BYTES = NPOP * SLOTS1 * 4 + SLOTS1 * (8 + 8 + 4 + 4);
+struct RhsTile {
+  const int* ent_off;  // [ntiles+1]
+  const int2* ent;     // [entries]
+};
+
+__global__ void __launch_bounds__(BLOCK) k_rhs_lds(int N, int Np, int E, TileArgs ta, RhsTile rt,
+                                                  const double* __restrict__ geo, const double* __restrict__ gC,
+                                                  const float* __restrict__ gp, const double* __restrict__ lapmu,
+                                                  const double* __restrict__ Cn, const float* __restrict__ uxn,
+                                                  const float* __restrict__ uyn, const double* __restrict__ mu,
+                                                  const float* __restrict__ pop, const double* __restrict__ mass,
+                                                  StepParams P, float* __restrict__ f, double* __restrict__ fC) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int S = SLOTS1;
+  float* ps = reinterpret_cast<float*>(smem);
+  double* Cs = reinterpret_cast<double*>(smem + NPOP * S * sizeof(float));
+  double* mus = Cs + S;
+  float* uxs = reinterpret_cast<float*>(mus + S);
+  float* uys = uxs + S;
+  const int t = xcd_block();
+  if (t >= ta.ntiles) return;  // block-uniform
+  const int lane = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(lane >> 6);
+  const int l64 = lane & 63;
+  const int base = t * TILE;
+  const int i = base + lane;
+  const bool valid = i < N;
+  const int h0 = ta.halo_off[t], nh = ta.halo_off[t + 1] - h0;
+  if (base + 4 * l64 < Np)
+    for (int a = wave; a < NPOP; a += 4) lds_dma16(pop + a * Np + base + 4 * l64, ps + a * S);
+  const int hid0 = l64 < nh ? ta.halo[h0 + l64] : 0;
+  const int hid1 = 64 + l64 < nh ? ta.halo[h0 + 64 + l64] : 0;
+  for (int a = wave; a < NPOP; a += 4) {
+    if (l64 < nh) lds_dma4(pop + a * Np + hid0, ps + a * S + TILE);
+    if (64 + l64 < nh) lds_dma4(pop + a * Np + hid1, ps + a * S + TILE + 64);
+  }
+  if (valid) {
+    Cs[lane] = Cn[i];
+    mus[lane] = mu[i];
+    uxs[lane] = uxn[i];
+    uys[lane] = uyn[i];
+  }
+  if (lane < nh) {
+    const int j = ta.halo[h0 + lane];
+    Cs[TILE + lane] = Cn[j];
+    mus[TILE + lane] = mu[j];
+    uxs[TILE + lane] = uxn[j];
+    uys[TILE + lane] = uyn[j];
+  }
+  const double mi = valid ? mass[i] : 1.0;
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's LDS DMA has landed
+  __syncthreads();
+  if (!valid) return;
+  float b[NPOP];
+#pragma unroll
+  for (int a = 0; a < NPOP; ++a) b[a] = 0.0f;
+  double bC = 0.0;
+  const float dt = (float)P.dt, c1 = dt / 3.0f, c2 = 0.5f * dt * dt;
+  const float drho_cs2 = (float)(CS2 * (P.rho_l - P.rho_v));
+  const int e0 = rt.ent_off[t], width = (rt.ent_off[t + 1] - e0) / TILE;
+  for (int k = 0; k < width; ++k) {
+    const int2 en = rt.ent[e0 + k * TILE + lane];
+    if (en.x < 0) continue;
+    const int e = en.x >> 2, l = en.x & 3;
+    const int s0 = en.y & 511, s1 = (en.y >> 9) & 511, s2 = (en.y >> 18) & 511;
+    // slots of the two other vertices, in the order (l + 1, l + 2) mod 3
+    const int sa = l == 0 ? s1 : (l == 1 ? s2 : s0);
+    const int sb = l == 0 ? s2 : (l == 1 ? s0 : s1);
+    const double Ad = geo[e];
+    double gxd[3], gyd[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      gxd[v] = geo[(1 + 2 * v) * E + e];
+      gyd[v] = geo[(2 + 2 * v) * E + e];
+    }
+    float gxf[3], gyf[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      gxf[v] = (float)gxd[v];
+      gyf[v] = (float)gyd[v];
+    }
+    const float A = (float)Ad;
+    // own vertex l and the two others (l + 1, l + 2) mod 3
+    const float gxl = l == 0 ? gxf[0] : (l == 1 ? gxf[1] : gxf[2]);
+    const float gyl = l == 0 ? gyf[0] : (l == 1 ? gyf[1] : gyf[2]);
+    const float gla = l == 0 ? gxf[1] : (l == 1 ? gxf[2] : gxf[0]);
+    const float hla = l == 0 ? gyf[1] : (l == 1 ? gyf[2] : gyf[0]);
+    const float glb = l == 0 ? gxf[2] : (l == 1 ? gxf[0] : gxf[1]);
+    const float hlb = l == 0 ? gyf[2] : (l == 1 ? gyf[0] : gyf[1]);
+    // barycentric values of the P1 fields and the element gradients
+    const double Cb = (Cs[s0] + Cs[s1] + Cs[s2]) * (1.0 / 3.0);
+    const double mub = (mus[s0] + mus[s1] + mus[s2]) * (1.0 / 3.0);
+    const float ux0 = uxs[s0], ux1 = uxs[s1], ux2 = uxs[s2];
+    const float uy0 = uys[s0], uy1 = uys[s1], uy2 = uys[s2];
+    const float ubx = (ux0 + ux1 + ux2) / 3.0f, uby = (uy0 + uy1 + uy2) / 3.0f;
+    const double rhobd = Cb * P.rho_l + (1.0 - Cb) * P.rho_v;
+    const float rhob = (float)rhobd;
+    const double gCx = gC[e], gCy = gC[E + e];
+    const float gpx = gp[e], gpy = gp[E + e];
+    const float ax = drho_cs2 * (float)gCx, ay = drho_cs2 * (float)gCy;  // c_s^2 grad rho
+    const float bx = (float)(mub * gCx), by = (float)(mub * gCy);        // mu grad C
+    const float coef = (float)Cb / (rhob * (float)CS2);
+    const float Xx = (float)gCx - coef * (gpx - bx), Xy = (float)gCy - coef * (gpy - by);
+    const double lm = lapmu[e];
+    const float d = (float)(P.mobility * lm);
+    const float uA = ubx * ax + uby * ay, uB = ubx * bx + uby * by, uX = ubx * Xx + uby * Xy;
+    const float uu = ubx * ubx + uby * uby;
+    double divJ = 0.0, dPx = 0.0, dPy = 0.0;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const float exa = (float)ex(a), eya = (float)ey(a);
+      const float eu = exa * ubx + eya * uby;
+      const float G = (float)wq(a) * (1.0f + 3.0f * eu + 4.5f * eu * eu - 1.5f * uu);
+      const float Phig = (exa * ax + eya * ay - uA) * (G - (float)wq(a)) + (exa * bx + eya * by - uB) * G;
+      const float Phih = (exa * Xx + eya * Xy - uX + d) * G;
+      const float enl = exa * gxl + eya * gyl;
+      const float ena = exa * gla + eya * hla, enb = exa * glb + eya * hlb;
+      const float ha = ps[(Q + a) * S + sa], hb = ps[(Q + a) * S + sb], hl = ps[(Q + a) * S + lane];
+      const float sg = ps[a * S + lane] * enl + ps[a * S + sa] * ena + ps[a * S + sb] * enb;
+      const float sh = hl * enl + ha * ena + hb * enb;
+      const float wgt = A * (c1 + c2 * enl);
+      b[a] += wgt * (Phig - sg);
+      b[Q + a] += wgt * (Phih - sh);
+      if (a != 0) {
+        // FP64, vertex order 0, 1, 2 whichever vertex gathers
+        const double h0v = ps[(Q + a) * S + s0], h1v = ps[(Q + a) * S + s1], h2v = ps[(Q + a) * S + s2];
+        const double sa_d = (ex(a) * gxd[0] + ey(a) * gyd[0]) * h0v + (ex(a) * gxd[1] + ey(a) * gyd[1]) * h1v +
+                            (ex(a) * gxd[2] + ey(a) * gyd[2]) * h2v;
+        divJ += sa_d;
+        if (ex(a)) dPx += ex(a) * sa_d;
+        if (ey(a)) dPy += ey(a) * sa_d;
+      }
+    }
+    const double uxd = ((double)ux0 + (double)ux1 + (double)ux2) * (1.0 / 3.0);
+    const double uyd = ((double)uy0 + (double)uy1 + (double)uy2) * (1.0 / 3.0);
+    const double cf = Cb / (rhobd * CS2);
+    const double Xdx = gCx - cf * ((double)gpx - mub * gCx), Xdy = gCy - cf * ((double)gpy - mub * gCy);
+    const double Ml = P.mobility * lm;
+    const double s0m = Ml - divJ;
+    const double s1x = CS2 * Xdx + Ml * uxd - dPx, s1y = CS2 * Xdy + Ml * uyd - dPy;
+    const double gxl_d = l == 0 ? gxd[0] : (l == 1 ? gxd[1] : gxd[2]);
+    const double gyl_d = l == 0 ? gyd[0] : (l == 1 ? gyd[1] : gyd[2]);
+    bC += Ad * (P.dt * (1.0 / 3.0) * s0m + 0.5 * P.dt * P.dt * (gxl_d * s1x + gyl_d * s1y));
+  }
+  const float inv_m = (float)(1.0 / mi);
+#pragma unroll
+  for (int a = 0; a < NPOP; ++a) f[a * Np + i] = b[a] * inv_m;
+  fC[i] = bC / mi;
+}
+
+// ----------------------------------------------------------------------------
 // a8: the consistent-mass solve M11 x = b, preconditioned by the lumped mass:
 // Richardson sweeps x <- x + w_j (f - A x), A = diag(m)^-1 M11, f = b/m,
 // x_0 = f.  With w_j the reciprocal Chebyshev roots on [lambda_min, lambda_max]
@@ -575,24 +771,6 @@ __global__ void __launch_bounds__(BLOCK) k_sweep(int N, int Np, const int* __res
 // in registers; padded entries point at the row's own slot with weight 0.
 // FP32 stages all 18 populations at once, FP64 nine at a time.
 // ----------------------------------------------------------------------------
-constexpr int TILE = BLOCK;
-constexpr int MAXW = 12;
-// compile-time LDS strides (so that population offsets are instruction
-// immediates): one-sweep halo <= 128; two-sweep ring 1 <= 128, rings 1+2 <= 256
-constexpr int HALO_MAX = 128;
-constexpr int SLOTS1 = TILE + HALO_MAX;     // tile + ring 1
-constexpr int SLOTS2 = TILE + 2 * HALO_MAX; // tile + ring 1 + ring 2
-constexpr int PAIR_G32 = 6;  // populations per LDS pass of the two-sweep kernel (FP32)
-constexpr int PAIR_G64 = 3;  // (FP64)
-
-struct TileArgs {
-  const int* tile_off;   // [ntiles+1] entry offsets
-  const uint16_t* slot;  // [entries]
-  const int* halo_off;   // [ntiles+1]
-  const int* halo;       // halo node ids
-  int ntiles, slots;     // slots = 256 + largest halo
-};
-
 template <typename real, int MODE>
 __global__ void __launch_bounds__(BLOCK) k_sweep_lds(int N, int Np, TileArgs ta, const real* __restrict__ tval,
                                                     const real* __restrict__ f, const real* __restrict__ xin,
@@ -719,16 +897,6 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_lds(int N, int Np, TileArgs ta,
 // slots.  Same tile rows and LDS layout as k_sweep_lds with all 18 populations
 // in one pass: [18][SLOTS1] floats, then [SLOTS1] doubles.
 // ----------------------------------------------------------------------------
-typedef __attribute__((address_space(3))) void lds_void_t;
-
-// each active lane's 16 (4) bytes at src land at lds_wave_base + lane * 16 (4)
-__device__ __forceinline__ void lds_dma16(const void* src, void* lds_wave_base) {
-  __builtin_amdgcn_global_load_lds(src, (lds_void_t*)lds_wave_base, 16, 0, 0);
-}
-__device__ __forceinline__ void lds_dma4(const void* src, void* lds_wave_base) {
-  __builtin_amdgcn_global_load_lds(src, (lds_void_t*)lds_wave_base, 4, 0, 0);
-}
-
 template <int MODE>
 __global__ void __launch_bounds__(BLOCK) k_sweep_dma(int N, int Np, TileArgs ta, const float* __restrict__ tval,
                                                     const float* __restrict__ f, const float* __restrict__ xin,
