@@ -21,11 +21,11 @@ using namespace felbm;
 namespace {
 
 enum KernelId {
-  K_MOMENTS = 0, K_REDUCE, K_GRAD, K_LAPC, K_GRADMU, K_LAPMU, K_RHS, K_SWEEP_FIRST, K_SWEEP_MID, K_SWEEP_LAST,
+  K_MOMENTS = 0, K_REDUCE, K_GRAD, K_EFLUX, K_LAPC, K_GRADMU, K_LAPMU, K_RHS, K_SWEEP_FIRST, K_SWEEP_MID, K_SWEEP_LAST,
   K_PAIR_FIRST, K_PAIR_MID, K_PAIR_LAST, K_ADJ_PREP, K_ADJ_FORCE, K_ADJ_STREAM, K_ADJ_GMU, K_ADJ_MU, K_ADJ_GC,
   K_ADJ_NODE, K_COUNT
 };
-const char* const kKernelNames[K_COUNT] = {"moments_collide", "reduce_final", "elem_grad", "lapC_mu",
+const char* const kKernelNames[K_COUNT] = {"moments_collide", "reduce_final", "elem_grad", "edge_flux", "lapC_mu",
                                            "elem_gradmu", "elem_lapmu", "rhs_gather", "sweep_first",
                                            "sweep_mid", "sweep_last", "sweep2_first", "sweep2_mid",
                                            "sweep2_last", "adj_prep", "adj_force", "adj_stream",
@@ -77,6 +77,7 @@ struct felbm_ctx {
   int32_t *tri = nullptr, *enbr = nullptr, *n2e_ptr = nullptr, *n2e = nullptr, *wall_nbr = nullptr;
   int32_t *sell_ptr = nullptr, *sell_col = nullptr;
   double *geo = nullptr, *wall_len = nullptr, *bc = nullptr, *mass = nullptr, *xy = nullptr;
+  double *pvol = nullptr, *eflux = nullptr;  // patch volume per node; edge fluxes [3][E]
   void *geor = nullptr, *sell_val = nullptr;
   uint8_t* is_wall = nullptr;
   // state and work buffers (device)
@@ -233,7 +234,8 @@ void set_kernel_bytes(felbm_ctx* c) {
   c->kstat[K_MOMENTS].bytes = 2 * pops + N * (8 + 3 * s) + N * 8 * 3;        // pop r/w, fields, mass + xy
   c->kstat[K_REDUCE].bytes = 0;
   c->kstat[K_GRAD].bytes = E * (12 + 56 + 16 + 2 * s) + N * (8 + s);
-  c->kstat[K_LAPC].bytes = N * (4 + 8 + 8 + 8 + 8 + 8 + 8 * 2 + 4 * 2) + 3 * E * 4 + E * (4 * 3 + 56 + 16);
+  c->kstat[K_EFLUX].bytes = E * (12 + 56 + 16 + 24);
+  c->kstat[K_LAPC].bytes = N * (4 + 8 + 8 + 8 + 8 + 8 + 8 * 2 + 4 * 2) + 3 * E * (4 + 8);
   c->kstat[K_GRADMU].bytes = E * (12 + 48 + 16) + N * 8;
   c->kstat[K_LAPMU].bytes = E * (12 + 48 + 16 + 8);
   c->kstat[K_RHS].bytes = 2 * pops + N * (4 + 8 + 8 + 2 * s + 8) + 3 * E * 4 + E * (12 + 7 * s + 16 + 2 * s + 8);
@@ -259,9 +261,11 @@ int enqueue_fields(felbm_ctx* c, bool collide, bool record, DiagRecord* rec_targ
                c->first_bad));
   TRY(launch(c, K_GRAD, k_elem_grad<real>, gE, E, (const int*)c->tri, (const double*)c->geo, (const double*)c->Cn,
              (const real*)c->pn, c->gC, (real*)c->gp));
-  TRY(launch(c, K_LAPC, k_lapC_mu, gN, N, E, (const int*)c->n2e_ptr, (const int*)c->n2e, (const int*)c->tri,
-             (const int*)c->enbr, (const double*)c->geo, (const double*)c->gC, (const double*)c->Cn,
-             (const double*)c->bc, (const int*)c->wall_nbr, (const double*)c->wall_len, c->sp, c->lapC, c->mu));
+  TRY(launch(c, K_EFLUX, k_edge_flux, gE, E, (const int*)c->tri, (const int*)c->enbr, (const double*)c->geo,
+             (const double*)c->gC, (const double*)c->Cn, (const double*)c->bc, c->eflux));
+  TRY(launch(c, K_LAPC, k_lapC_mu, gN, N, E, (const int*)c->n2e_ptr, (const int*)c->n2e, (const double*)c->eflux,
+             (const double*)c->pvol, (const double*)c->Cn, (const double*)c->bc, (const int*)c->wall_nbr,
+             (const double*)c->wall_len, c->sp, c->lapC, c->mu));
   TRY(launch(c, K_GRADMU, k_elem_gradmu, gE, E, (const int*)c->tri, (const double*)c->geo, (const double*)c->mu,
              c->gmu));
   TRY(launch(c, K_LAPMU, k_elem_lapmu, gE, E, (const int*)c->enbr, (const double*)c->geo, (const double*)c->gmu,
@@ -891,6 +895,8 @@ int felbm_upload_mesh(felbm_ctx* c, int64_t n_nodes, const double* xy, int64_t n
   TRY(dalloc(c, &c->is_wall, N));
   TRY(dalloc(c, &c->bc, N));
   TRY(dalloc(c, &c->mass, N));
+  TRY(dalloc(c, &c->pvol, N));
+  TRY(dalloc(c, &c->eflux, 3 * E));
   TRY(dalloc(c, &c->xy, 2 * N));
   TRY(dalloc(c, &c->sell_ptr, m.sell_ptr.size()));
   TRY(dalloc(c, &c->sell_col, m.sell_col.size()));
@@ -929,6 +935,14 @@ int felbm_upload_mesh(felbm_ctx* c, int64_t n_nodes, const double* xy, int64_t n
   TRY(upload(c, c->wall_len, m.wall_len));
   TRY(upload(c, c->is_wall, m.is_wall));
   TRY(upload(c, c->mass, m.mass));
+  {
+    // patch volume sum_T A_T in the node's element-list order (the order the gather sums its fluxes)
+    std::vector<double> pvol(N, 0.0);
+    for (int64_t k = 0; k < N; ++k)
+      for (int32_t q = m.n2e_ptr[k]; q < m.n2e_ptr[k + 1]; ++q) pvol[k] += m.geo[m.n2e[q] >> 2];
+    TRY(upload(c, c->pvol, pvol));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+  }
   TRY(upload(c, c->xy, m.xy));
   TRY(upload(c, c->sell_ptr, m.sell_ptr));
   TRY(upload(c, c->sell_col, m.sell_col));

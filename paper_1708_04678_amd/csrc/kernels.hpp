@@ -257,33 +257,47 @@ __device__ __forceinline__ double wall_flux(double Ca, double Cb, double ra, dou
 // The outer edge of patch element T opposite node k has |e| n_out =
 // -2 A_T grad N_k; its gradient is the mean of the two adjacent element
 // gradients; wall edges (opposite k, or incident to k) carry the wetting flux.
+// Two passes: each element writes the flux through its three edges as seen
+// from the opposite vertex (F[l][e]); each node sums the entries of its patch
+// in its element-list order and adds the wall edges incident to it.
 // ----------------------------------------------------------------------------
+__global__ void __launch_bounds__(BLOCK) k_edge_flux(int E, const int* __restrict__ tri, const int* __restrict__ enbr,
+                                                    const double* __restrict__ geo, const double* __restrict__ gC,
+                                                    const double* __restrict__ Cn, const double* __restrict__ bc,
+                                                    double* __restrict__ F) {
+  const int e = xcd_block() * BLOCK + threadIdx.x;
+  if (e >= E) return;
+  const double A = geo[e], gCx = gC[e], gCy = gC[E + e];
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    const double gx = geo[(1 + 2 * l) * E + e], gy = geo[(2 + 2 * l) * E + e];
+    const int nb = enbr[l * E + e];
+    double fl;
+    if (nb >= 0) {
+      const double Gx = 0.5 * (gCx + gC[nb]), Gy = 0.5 * (gCy + gC[E + nb]);
+      fl = -2.0 * A * (gx * Gx + gy * Gy);
+    } else {
+      const int a = tri[((l + 1) % 3) * E + e], b = tri[((l + 2) % 3) * E + e];
+      const double len = 2.0 * A * sqrt(gx * gx + gy * gy);
+      fl = wall_flux(Cn[a], Cn[b], bc[a], bc[b], len);
+    }
+    F[l * E + e] = fl;
+  }
+}
+
 __global__ void __launch_bounds__(BLOCK) k_lapC_mu(int N, int E, const int* __restrict__ n2e_ptr,
-                                                  const int* __restrict__ n2e, const int* __restrict__ tri,
-                                                  const int* __restrict__ enbr, const double* __restrict__ geo,
-                                                  const double* __restrict__ gC, const double* __restrict__ Cn,
+                                                  const int* __restrict__ n2e, const double* __restrict__ F,
+                                                  const double* __restrict__ pvol, const double* __restrict__ Cn,
                                                   const double* __restrict__ bc, const int* __restrict__ wall_nbr,
                                                   const double* __restrict__ wall_len, StepParams P,
                                                   double* __restrict__ lapC, double* __restrict__ mu) {
   const int k = xcd_block() * BLOCK + threadIdx.x;
   if (k >= N) return;
-  double flux = 0.0, vol = 0.0;
+  double flux = 0.0;
   const int beg = n2e_ptr[k], end = n2e_ptr[k + 1];
   for (int q = beg; q < end; ++q) {
     const int packed = n2e[q];
-    const int e = packed >> 2, l = packed & 3;
-    const double A = geo[e];
-    const double gx = geo[(1 + 2 * l) * E + e], gy = geo[(2 + 2 * l) * E + e];
-    vol += A;
-    const int nb = enbr[l * E + e];
-    if (nb >= 0) {
-      const double Gx = 0.5 * (gC[e] + gC[nb]), Gy = 0.5 * (gC[E + e] + gC[E + nb]);
-      flux += -2.0 * A * (gx * Gx + gy * Gy);
-    } else {
-      const int a = tri[((l + 1) % 3) * E + e], b = tri[((l + 2) % 3) * E + e];
-      const double len = 2.0 * A * sqrt(gx * gx + gy * gy);
-      flux += wall_flux(Cn[a], Cn[b], bc[a], bc[b], len);
-    }
+    flux += F[(packed & 3) * E + (packed >> 2)];
   }
   const double Ck = Cn[k];
 #pragma unroll
@@ -291,7 +305,7 @@ __global__ void __launch_bounds__(BLOCK) k_lapC_mu(int N, int E, const int* __re
     const int j = wall_nbr[w * N + k];
     if (j >= 0) flux += wall_flux(Ck, Cn[j], bc[k], bc[j], wall_len[w * N + k]);
   }
-  const double L = flux / vol;
+  const double L = flux / pvol[k];
   lapC[k] = L;
   mu[k] = 2.0 * P.beta * Ck * (Ck - 1.0) * (2.0 * Ck - 1.0) - P.kappa * L;
 }
