@@ -302,8 +302,8 @@ int sweep(felbm_ctx* c, int kid, const real* xin, real* xout, real w, const Cons
     TileArgs ta{c->tile_off, c->tslot, c->halo_off, c->halo, c->ntiles, c->tile_slots};
     const int grid = (c->ntiles + 7) / 8 * 8;
     if constexpr (std::is_same<real, float>::value)
-      return launch_sm(c, kid, k_sweep_dma<MODE>, grid, BLOCK, c->lds_bytes, N, Np, ta, (const float*)c->tval, f, xin,
-                       xout, pop, (const uint8_t*)c->is_wall, w, cs);
+      return launch_sm(c, kid, k_sweep_dma<MODE>, (2 * c->ntiles + 7) / 8 * 8, BLOCK, SWEEP_DMA_LDS_BYTES, N, Np, ta,
+                       (const float*)c->tval, f, xin, xout, pop, (const uint8_t*)c->is_wall, w, cs);
     return launch_sm(c, kid, k_sweep_lds<real, MODE>, grid, BLOCK, c->lds_bytes, N, Np, ta, (const real*)c->tval, f, xin,
                      xout, pop, (const uint8_t*)c->is_wall, w, cs);
   }
@@ -1481,16 +1481,17 @@ int felbm_validate_mesh(int64_t n_nodes, const double* xy, int64_t n_tris, const
 
 void felbm_destroy(felbm_ctx* c) {
   if (!c) return;
-  if (c->stream) hipStreamSynchronize(c->stream);
+  // teardown: errors are not reportable past this point
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (auto& p : c->pending) {
-    hipEventDestroy(p.start);
-    hipEventDestroy(p.stop);
+    (void)hipEventDestroy(p.start);
+    (void)hipEventDestroy(p.stop);
   }
-  for (auto e : c->event_pool) hipEventDestroy(e);
-  for (void* p : c->allocations) hipFree(p);
-  if (c->ck_buf) hipFree(c->ck_buf);
-  if (c->seg_buf) hipFree(c->seg_buf);
-  if (c->own_stream) hipStreamDestroy(c->own_stream);
+  for (auto e : c->event_pool) (void)hipEventDestroy(e);
+  for (void* p : c->allocations) (void)hipFree(p);
+  if (c->ck_buf) (void)hipFree(c->ck_buf);
+  if (c->seg_buf) (void)hipFree(c->seg_buf);
+  if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
   delete c;
 }
 

@@ -905,12 +905,17 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_lds(int N, int Np, TileArgs ta,
 // FP32 sweep staged by LDS DMA (global_load_lds): the loads write LDS
 // directly, so nothing is held in VGPRs while they are in flight and a
 // workgroup issues all of its staging (tile, halo, FP64 composition iterate,
-// the f values it needs later) before one wait.  Tile values move 16 bytes per
+// the f values it needs later) before one wait.  Two workgroups per tile, one
+// per population set (g: 0..8, h: 9..17), which keeps the LDS of a workgroup
+// at 9 populations and lets more tiles be in flight per CU; the h workgroup
+// also carries the FP64 composition sweep.  Tile values move 16 bytes per
 // lane (one instruction per population covers the 256-node tile); halo values
 // are 4-byte gathers of 64 entries per instruction, written to consecutive
-// slots.  Same tile rows and LDS layout as k_sweep_lds with all 18 populations
-// in one pass: [18][SLOTS1] floats, then [SLOTS1] doubles.
+// slots.  Same tile rows and slots as k_sweep_lds; LDS: [9][SLOTS1] floats,
+// then [SLOTS1] doubles.
 // ----------------------------------------------------------------------------
+constexpr unsigned SWEEP_DMA_LDS_BYTES = Q * SLOTS1 * 4 + SLOTS1 * 8;
+
 template <int MODE>
 __global__ void __launch_bounds__(BLOCK) k_sweep_dma(int N, int Np, TileArgs ta, const float* __restrict__ tval,
                                                     const float* __restrict__ f, const float* __restrict__ xin,
@@ -921,9 +926,12 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_dma(int N, int Np, TileArgs ta,
   constexpr bool FIRST = MODE == 0 || MODE == 3;   // iterate = f
   constexpr bool STAGE = MODE != 4;
   float* xs = reinterpret_cast<float*>(smem);
-  double* cxs = reinterpret_cast<double*>(smem + NPOP * S * sizeof(float));
-  const int t = xcd_block();
-  if (t >= ta.ntiles) return;  // block-uniform
+  double* cxs = reinterpret_cast<double*>(smem + Q * S * sizeof(float));
+  const int vb = xcd_block();
+  const int t = vb >> 1;
+  const bool hset = (vb & 1) != 0;  // block-uniform: this workgroup sweeps h (and the composition)
+  if (t >= ta.ntiles) return;       // block-uniform
+  const int p0 = hset ? Q : 0;
   const int lane = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(lane >> 6);
   const int l = lane & 63;
@@ -932,24 +940,26 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_dma(int N, int Np, TileArgs ta,
   const bool valid = i < N;
   const int h0 = ta.halo_off[t], nh = ta.halo_off[t + 1] - h0;
   const int e0 = ta.tile_off[t], width = (ta.tile_off[t + 1] - e0) / TILE;
-  const float* __restrict__ x = FIRST ? f : xin;
+  const float* __restrict__ x = (FIRST ? f : xin) + p0 * Np;
   const double* __restrict__ xC = FIRST ? cs.fC : cs.xCin;
   if (STAGE) {
     // Np is a multiple of 64, so a 16-byte chunk that starts below Np ends inside the array
     if (base + 4 * l < Np)
-      for (int a = wave; a < NPOP; a += 4) lds_dma16(x + a * Np + base + 4 * l, xs + a * S);
+      for (int a = wave; a < Q; a += 4) lds_dma16(x + a * Np + base + 4 * l, xs + a * S);
     const int hid0 = l < nh ? ta.halo[h0 + l] : 0;
     const int hid1 = 64 + l < nh ? ta.halo[h0 + 64 + l] : 0;
-    for (int a = wave; a < NPOP; a += 4) {
+    for (int a = wave; a < Q; a += 4) {
       if (l < nh) lds_dma4(x + a * Np + hid0, xs + a * S + TILE);
       if (64 + l < nh) lds_dma4(x + a * Np + hid1, xs + a * S + TILE + 64);
     }
-    if (wave < 2) {
-      // two doubles per lane; waves 0 and 1 cover tile nodes [0,128) and [128,256)
-      if (base + wave * 128 + 2 * l < Np) lds_dma16(xC + base + wave * 128 + 2 * l, cxs + wave * 128);
-    } else {
-      const int hh = (wave - 2) * 64 + l;
-      if (hh < nh) cxs[TILE + hh] = xC[wave == 2 ? hid0 : hid1];
+    if (hset) {
+      if (wave < 2) {
+        // two doubles per lane; waves 0 and 1 cover tile nodes [0,128) and [128,256)
+        if (base + wave * 128 + 2 * l < Np) lds_dma16(xC + base + wave * 128 + 2 * l, cxs + wave * 128);
+      } else {
+        const int hh = (wave - 2) * 64 + l;
+        if (hh < nh) cxs[TILE + hh] = xC[wave == 2 ? hid0 : hid1];
+      }
     }
   }
   int sl[MAXW];
@@ -965,66 +975,71 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_dma(int N, int Np, TileArgs ta,
     }
   }
   // the f values of the own node, in flight together with the staging
-  float fr[NPOP];
+  float fr[Q];
   double fCi = 0.0, dlti = 0.0;
   if (!FIRST && valid) {
 #pragma unroll
-    for (int a = 0; a < NPOP; ++a) fr[a] = f[a * Np + i];
-    fCi = cs.fC[i];
+    for (int a = 0; a < Q; ++a) fr[a] = f[(p0 + a) * Np + i];
+    if (hset) fCi = cs.fC[i];
   }
-  if (STAGE && valid) dlti = cs.dlt[i];
+  if (STAGE && hset && valid) dlti = cs.dlt[i];
   if (STAGE) {
     __builtin_amdgcn_s_waitcnt(0);  // this wave's LDS DMA has landed
     __syncthreads();
   }
   if (!valid) return;
-  float r[NPOP];
-  double rc;
+  float r[Q];
+  double rc = 0.0;
   if (STAGE) {
 #pragma unroll
-    for (int a = 0; a < NPOP; ++a) {
+    for (int a = 0; a < Q; ++a) {
       const float xi = xs[a * S + lane];
       float acc = 0.5f * xi;
 #pragma unroll
       for (int k = 0; k < MAXW; ++k)
         if (k < width) acc += va[k] * xs[a * S + sl[k]];
       r[a] = xi + w * ((FIRST ? xi : fr[a]) - acc);
-      if (MODE == 0 || MODE == 1) xout[a * Np + i] = r[a];
+      if (MODE == 0 || MODE == 1) xout[(p0 + a) * Np + i] = r[a];
     }
-    const double xco = cxs[lane];
-    double acc = dlti * xco;
+    if (hset) {
+      const double xco = cxs[lane];
+      double acc = dlti * xco;
 #pragma unroll
-    for (int k = 0; k < MAXW; ++k)
-      if (k < width) acc += (double)va[k] * cxs[sl[k]];
-    rc = xco + cs.w * ((FIRST ? xco : fCi) - acc);
+      for (int k = 0; k < MAXW; ++k)
+        if (k < width) acc += (double)va[k] * cxs[sl[k]];
+      rc = xco + cs.w * ((FIRST ? xco : fCi) - acc);
+    }
   } else {
 #pragma unroll
-    for (int a = 0; a < NPOP; ++a) r[a] = fr[a];
+    for (int a = 0; a < Q; ++a) r[a] = fr[a];
     rc = fCi;
   }
   if (MODE == 0 || MODE == 1) {
-    cs.xCout[i] = rc;
+    if (hset) cs.xCout[i] = rc;
     return;
   }
-  float s[NPOP];
+  float s[Q];
 #pragma unroll
-  for (int a = 0; a < NPOP; ++a) s[a] = pop[a * Np + i] + r[a];
+  for (int a = 0; a < Q; ++a) s[a] = pop[(p0 + a) * Np + i] + r[a];
   if (is_wall[i]) {
+    // wall operator: every opposite pair of this population set replaced by its mean
 #pragma unroll
     for (int a = 1; a < Q; ++a) {
       const int b = opp(a);
       if (b > a) {
-        const float mg = 0.5f * (s[a] + s[b]), mh = 0.5f * (s[Q + a] + s[Q + b]);
-        s[a] = mg; s[b] = mg; s[Q + a] = mh; s[Q + b] = mh;
+        const float m = 0.5f * (s[a] + s[b]);
+        s[a] = m; s[b] = m;
       }
     }
   }
 #pragma unroll
-  for (int a = 0; a < NPOP; ++a) pop[a * Np + i] = s[a];
-  double sh = 0.0;
+  for (int a = 0; a < Q; ++a) pop[(p0 + a) * Np + i] = s[a];
+  if (hset) {
+    double sh = 0.0;
 #pragma unroll
-  for (int a = 0; a < Q; ++a) sh += (double)s[Q + a];
-  cs.rC[i] = (cs.Cn[i] + rc) - sh;
+    for (int a = 0; a < Q; ++a) sh += (double)s[a];
+    cs.rC[i] = (cs.Cn[i] + rc) - sh;
+  }
 }
 
 // ----------------------------------------------------------------------------
