@@ -649,8 +649,11 @@ __global__ void __launch_bounds__(BLOCK) k_rhs_lds(int N, int Np, int E, TileArg
       b[a] += wgt * (Phig - sg);
       b[Q + a] += wgt * (Phih - sh);
       if (a != 0) {
-        // FP64, vertex order 0, 1, 2 whichever vertex gathers
-        const double h0v = ps[(Q + a) * S + s0], h1v = ps[(Q + a) * S + s1], h2v = ps[(Q + a) * S + s2];
+        // FP64, vertex order 0, 1, 2 whichever vertex gathers (vertex l holds hl,
+        // vertex l + 1 holds ha, vertex l + 2 holds hb)
+        const double h0v = l == 0 ? hl : (l == 1 ? hb : ha);
+        const double h1v = l == 1 ? hl : (l == 2 ? hb : ha);
+        const double h2v = l == 2 ? hl : (l == 0 ? hb : ha);
         const double sa_d = (ex(a) * gxd[0] + ey(a) * gyd[0]) * h0v + (ex(a) * gxd[1] + ey(a) * gyd[1]) * h1v +
                             (ex(a) * gxd[2] + ey(a) * gyd[2]) * h2v;
         divJ += sa_d;
