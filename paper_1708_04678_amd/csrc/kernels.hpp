@@ -511,6 +511,19 @@ __device__ __forceinline__ void lds_dma4(const void* src, void* lds_wave_base) {
   __builtin_amdgcn_global_load_lds(src, (lds_void_t*)lds_wave_base, 4, 0, 0);
 }
 
+// streamed accesses (read or written once per launch, no reuse inside it):
+// nontemporal when NT, ordinary otherwise
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st_stream(T v, T* p) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
 // ----------------------------------------------------------------------------
 // The same right-hand side with the vertex data of a 256-node tile and its
 // halo staged in LDS (FP32): post-collision populations by LDS DMA, the nodal
@@ -928,6 +941,9 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_dma(int N, int Np, TileArgs ta,
   constexpr int S = SLOTS1;
   constexpr bool FIRST = MODE == 0 || MODE == 3;   // iterate = f
   constexpr bool STAGE = MODE != 4;
+  // f, the rows and the new iterate are streamed with nontemporal accesses
+  // (measured 1.5 % faster over the sweeps of a step than ordinary ones)
+  constexpr bool NT = true;
   float* xs = reinterpret_cast<float*>(smem);
   double* cxs = reinterpret_cast<double*>(smem + Q * S * sizeof(float));
   const int vb = xcd_block();
@@ -970,8 +986,8 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_dma(int N, int Np, TileArgs ta,
 #pragma unroll
   for (int k = 0; k < MAXW; ++k) {
     if (k < width) {
-      sl[k] = ta.slot[e0 + k * TILE + lane];
-      va[k] = tval[e0 + k * TILE + lane];
+      sl[k] = ld_stream<NT>(&ta.slot[e0 + k * TILE + lane]);
+      va[k] = ld_stream<NT>(&tval[e0 + k * TILE + lane]);
     } else {
       sl[k] = lane;
       va[k] = 0.0f;
@@ -982,7 +998,7 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_dma(int N, int Np, TileArgs ta,
   double fCi = 0.0, dlti = 0.0;
   if (!FIRST && valid) {
 #pragma unroll
-    for (int a = 0; a < Q; ++a) fr[a] = f[(p0 + a) * Np + i];
+    for (int a = 0; a < Q; ++a) fr[a] = ld_stream<NT>(&f[(p0 + a) * Np + i]);
     if (hset) fCi = cs.fC[i];
   }
   if (STAGE && hset && valid) dlti = cs.dlt[i];
@@ -1002,7 +1018,7 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_dma(int N, int Np, TileArgs ta,
       for (int k = 0; k < MAXW; ++k)
         if (k < width) acc += va[k] * xs[a * S + sl[k]];
       r[a] = xi + w * ((FIRST ? xi : fr[a]) - acc);
-      if (MODE == 0 || MODE == 1) xout[(p0 + a) * Np + i] = r[a];
+      if (MODE == 0 || MODE == 1) st_stream<NT>(r[a], &xout[(p0 + a) * Np + i]);
     }
     if (hset) {
       const double xco = cxs[lane];
@@ -1018,7 +1034,7 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_dma(int N, int Np, TileArgs ta,
     rc = fCi;
   }
   if (MODE == 0 || MODE == 1) {
-    if (hset) cs.xCout[i] = rc;
+    if (hset) st_stream<NT>(rc, &cs.xCout[i]);
     return;
   }
   float s[Q];
