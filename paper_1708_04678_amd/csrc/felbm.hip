@@ -95,6 +95,7 @@ struct felbm_ctx {
   bool use_rhs_lds = false;
   int32_t* rhs_off = nullptr;
   int2* rhs_ent = nullptr;
+  double* gaos = nullptr;  // element geometry records [E][8]
   // two-sweep (temporally blocked) solve: ring-1 rows and ring-2 lists per tile
   bool use_pair = false;
   int pair_slots = 0, pair_slots1 = 0;
@@ -281,8 +282,8 @@ int enqueue_rhs(felbm_ctx* c) {
     if (c->use_rhs_lds) {
       TileArgs ta{c->tile_off, c->tslot, c->halo_off, c->halo, c->ntiles, c->tile_slots};
       const int grid = (c->ntiles + 7) / 8 * 8;
-      return launch_sm(c, K_RHS, k_rhs_lds, grid, BLOCK, RHS_LDS_BYTES, N, Np, E, ta, RhsTile{c->rhs_off, c->rhs_ent},
-                       (const double*)c->geo, (const double*)c->gC, (const float*)c->gp, (const double*)c->lapmu,
+      return launch_sm(c, K_RHS, k_rhs_lds, grid, BLOCK, RHS_LDS_BYTES, N, Np, E, ta,
+                       RhsTile{c->rhs_off, c->rhs_ent, c->gaos, c->gC, (const float*)c->gp, c->lapmu},
                        (const double*)c->Cn, (const float*)c->uxn, (const float*)c->uyn, (const double*)c->mu,
                        (const float*)c->pop, (const double*)c->mass, c->sp, (float*)c->f, c->fC);
     }
@@ -711,10 +712,15 @@ int build_rhs_tiles(felbm_ctx* c, const MeshPrep& m, const std::vector<int32_t>&
     }
     off[t + 1] = (int32_t)ent.size();
   }
+  std::vector<double> gaos(8 * (size_t)E, 0.0);
+  for (int64_t e = 0; e < E; ++e)
+    for (int q = 0; q < 7; ++q) gaos[8 * e + q] = m.geo[q * E + e];
   TRY(dalloc(c, &c->rhs_off, off.size()));
   TRY(dalloc(c, &c->rhs_ent, ent.size()));
+  TRY(dalloc(c, &c->gaos, gaos.size()));
   TRY(upload(c, c->rhs_off, off));
   TRY(upload(c, c->rhs_ent, ent));
+  TRY(upload(c, c->gaos, gaos));
   HIP_OK(c, hipStreamSynchronize(c->stream));
   c->use_rhs_lds = true;
   // algorithmic bytes: populations and nodal fields once per node (C, mu, u, mass),

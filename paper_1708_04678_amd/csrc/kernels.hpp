@@ -541,11 +541,13 @@ constexpr unsigned RHS_LDS_BYTES = NPOP * SLOTS1 * 4 + SLOTS1 * (8 + 8 + 4 + 4);
 struct RhsTile {
   const int* ent_off;  // [ntiles+1]
   const int2* ent;     // [entries]
+  const double* gaos;  // [E][8] FP64 element geometry {A, dN0/dx, dN0/dy, dN1/dx, dN1/dy, dN2/dx, dN2/dy, 0}
+  const double* gC;    // [2][E]
+  const float* gp;     // [2][E]
+  const double* lapmu; // [E]
 };
 
 __global__ void __launch_bounds__(BLOCK) k_rhs_lds(int N, int Np, int E, TileArgs ta, RhsTile rt,
-                                                  const double* __restrict__ geo, const double* __restrict__ gC,
-                                                  const float* __restrict__ gp, const double* __restrict__ lapmu,
                                                   const double* __restrict__ Cn, const float* __restrict__ uxn,
                                                   const float* __restrict__ uyn, const double* __restrict__ mu,
                                                   const float* __restrict__ pop, const double* __restrict__ mass,
@@ -606,13 +608,12 @@ __global__ void __launch_bounds__(BLOCK) k_rhs_lds(int N, int Np, int E, TileArg
     // slots of the two other vertices, in the order (l + 1, l + 2) mod 3
     const int sa = l == 0 ? s1 : (l == 1 ? s2 : s0);
     const int sb = l == 0 ? s2 : (l == 1 ? s0 : s1);
-    const double Ad = geo[e];
-    double gxd[3], gyd[3];
-#pragma unroll
-    for (int v = 0; v < 3; ++v) {
-      gxd[v] = geo[(1 + 2 * v) * E + e];
-      gyd[v] = geo[(2 + 2 * v) * E + e];
-    }
+    // the element's geometry as one 64-byte record (a straddling element costs
+    // one cache line instead of seven)
+    const double2* g2 = reinterpret_cast<const double2*>(rt.gaos) + 4 * (size_t)e;
+    const double2 ga = g2[0], gb = g2[1], gc = g2[2], gd = g2[3];
+    const double Ad = ga.x;
+    const double gxd[3] = {ga.y, gb.y, gc.y}, gyd[3] = {gb.x, gc.x, gd.x};
     float gxf[3], gyf[3];
 #pragma unroll
     for (int v = 0; v < 3; ++v) {
@@ -635,13 +636,13 @@ __global__ void __launch_bounds__(BLOCK) k_rhs_lds(int N, int Np, int E, TileArg
     const float ubx = (ux0 + ux1 + ux2) / 3.0f, uby = (uy0 + uy1 + uy2) / 3.0f;
     const double rhobd = Cb * P.rho_l + (1.0 - Cb) * P.rho_v;
     const float rhob = (float)rhobd;
-    const double gCx = gC[e], gCy = gC[E + e];
-    const float gpx = gp[e], gpy = gp[E + e];
+    const double gCx = rt.gC[e], gCy = rt.gC[E + e];
+    const float gpx = rt.gp[e], gpy = rt.gp[E + e];
     const float ax = drho_cs2 * (float)gCx, ay = drho_cs2 * (float)gCy;  // c_s^2 grad rho
     const float bx = (float)(mub * gCx), by = (float)(mub * gCy);        // mu grad C
     const float coef = (float)Cb / (rhob * (float)CS2);
     const float Xx = (float)gCx - coef * (gpx - bx), Xy = (float)gCy - coef * (gpy - by);
-    const double lm = lapmu[e];
+    const double lm = rt.lapmu[e];
     const float d = (float)(P.mobility * lm);
     const float uA = ubx * ax + uby * ay, uB = ubx * bx + uby * by, uX = ubx * Xx + uby * Xy;
     const float uu = ubx * ubx + uby * uby;
