@@ -22,13 +22,11 @@ namespace {
 
 enum KernelId {
   K_MOMENTS = 0, K_REDUCE, K_GRAD, K_EFLUX, K_LAPC, K_GRADMU, K_LAPMU, K_RHS, K_SWEEP_FIRST, K_SWEEP_MID, K_SWEEP_LAST,
-  K_PAIR_FIRST, K_PAIR_MID, K_PAIR_LAST, K_ADJ_PREP, K_ADJ_FORCE, K_ADJ_STREAM, K_ADJ_GMU, K_ADJ_MU, K_ADJ_GC,
-  K_ADJ_NODE, K_COUNT
+  K_ADJ_PREP, K_ADJ_FORCE, K_ADJ_STREAM, K_ADJ_GMU, K_ADJ_MU, K_ADJ_GC, K_ADJ_NODE, K_COUNT
 };
 const char* const kKernelNames[K_COUNT] = {"moments_collide", "reduce_final", "elem_grad", "edge_flux", "lapC_mu",
                                            "elem_gradmu", "elem_lapmu", "rhs_gather", "sweep_first",
-                                           "sweep_mid", "sweep_last", "sweep2_first", "sweep2_mid",
-                                           "sweep2_last", "adj_prep", "adj_force", "adj_stream",
+                                           "sweep_mid", "sweep_last", "adj_prep", "adj_force", "adj_stream",
                                            "adj_gmu", "adj_mu", "adj_gC", "adj_node"};
 
 struct KStat {
@@ -87,7 +85,6 @@ struct felbm_ctx {
   // LDS-tiled solve: per-tile halo lists and matrix rows with local slots
   bool use_lds = false;
   int ntiles = 0, tile_slots = 0;
-  uint32_t lds_bytes = 0;
   int32_t *tile_off = nullptr, *halo_off = nullptr, *halo = nullptr;
   uint16_t* tslot = nullptr;
   void* tval = nullptr;
@@ -96,13 +93,6 @@ struct felbm_ctx {
   int32_t* rhs_off = nullptr;
   int2* rhs_ent = nullptr;
   double* gaos = nullptr;  // element geometry records [E][8]
-  // two-sweep (temporally blocked) solve: ring-1 rows and ring-2 lists per tile
-  bool use_pair = false;
-  int pair_slots = 0, pair_slots1 = 0;
-  uint32_t pair_lds = 0;
-  int32_t *ring_off = nullptr, *ring_w = nullptr, *r2_off = nullptr, *r2 = nullptr;
-  uint16_t* rslot = nullptr;
-  void* rval = nullptr;
   // adjoint: element reverse adjacency, caller<->internal maps, reverse buffers, checkpoints
   int32_t *erev = nullptr, *d_node_perm = nullptr;
   void *lam = nullptr, *lhat = nullptr;
@@ -301,12 +291,8 @@ int sweep(felbm_ctx* c, int kid, const real* xin, real* xout, real w, const Cons
   const real* f = (const real*)c->f;
   if (c->use_lds) {
     TileArgs ta{c->tile_off, c->tslot, c->halo_off, c->halo, c->ntiles, c->tile_slots};
-    const int grid = (c->ntiles + 7) / 8 * 8;
-    if constexpr (std::is_same<real, float>::value)
-      return launch_sm(c, kid, k_sweep_dma<MODE>, (2 * c->ntiles + 7) / 8 * 8, BLOCK, SWEEP_DMA_LDS_BYTES, N, Np, ta,
-                       (const float*)c->tval, f, xin, xout, pop, (const uint8_t*)c->is_wall, w, cs);
-    return launch_sm(c, kid, k_sweep_lds<real, MODE>, grid, BLOCK, c->lds_bytes, N, Np, ta, (const real*)c->tval, f, xin,
-                     xout, pop, (const uint8_t*)c->is_wall, w, cs);
+    return launch_sm(c, kid, k_sweep_dma<real, MODE>, (2 * c->ntiles + 7) / 8 * 8, BLOCK, sweep_dma_lds_bytes<real>(),
+                     N, Np, ta, (const real*)c->tval, f, xin, xout, pop, (const uint8_t*)c->is_wall, w, cs);
   }
   return launch(c, kid, k_sweep<real, MODE>, grid_for(c->N), N, Np, (const int*)c->sell_ptr, (const int*)c->sell_col,
                 (const real*)c->sell_val, f, xin, xout, pop, (const uint8_t*)c->is_wall, w, cs);
@@ -314,56 +300,9 @@ int sweep(felbm_ctx* c, int kid, const real* xin, real* xout, real w, const Cons
 
 // K Chebyshev-step Richardson sweeps on f, then psi_bar^{n+1} = psi_hat + x_K
 // and the wall operator (fused into the last sweep)
-template <typename real, int PMODE>
-int sweep2(felbm_ctx* c, int kid, const real* xin, real* xout, double w0, double w1, const ConsArgs& cs) {
-  PairArgs pa{c->tile_off, c->tslot, c->ring_off, c->ring_w, c->rslot, c->halo_off, c->halo,
-              c->r2_off, c->r2, c->ntiles, c->pair_slots, c->pair_slots1};
-  const int grid = (c->ntiles + 7) / 8 * 8;
-  return launch_sm(c, kid, k_sweep2<real, PMODE>, grid, BLOCK, c->pair_lds, (int)c->N, (int)c->Np, pa,
-                   (const real*)c->tval, (const real*)c->rval, (const real*)c->f, xin, xout, (real*)c->pop,
-                   (const uint8_t*)c->is_wall, (real)w0, (real)w1, cs, w0, w1);
-}
-
-// The same K sweeps, two per launch (a single first sweep when K is odd).
-template <typename real>
-int enqueue_solve_pairs(felbm_ctx* c) {
-  const int K = c->prm.solver_sweeps;
-  const std::vector<double>& w = c->cheb_w;
-  real *cur = (real*)c->xa, *nxt = (real*)c->xb;
-  double *ccur = c->xCa, *cnxt = c->xCb;
-  ConsArgs cs{c->fC, nullptr, nullptr, c->dlt, c->Cn, c->rC, 0.0};
-  int j = 0;
-  if (K % 2 == 1) {
-    cs.w = w[0];
-    cs.xCout = ccur;
-    TRY((sweep<real, 0>(c, K_SWEEP_FIRST, nullptr, cur, (real)w[0], cs)));
-    j = 1;
-  }
-  while (j < K) {
-    const bool first = (j == 0), last = (j + 2 == K);
-    cs.xCin = ccur;
-    cs.xCout = last ? nullptr : cnxt;
-    if (first && last)
-      TRY((sweep2<real, 3>(c, K_PAIR_LAST, nullptr, nullptr, w[j], w[j + 1], cs)));
-    else if (first)
-      TRY((sweep2<real, 0>(c, K_PAIR_FIRST, nullptr, nxt, w[j], w[j + 1], cs)));
-    else if (last)
-      TRY((sweep2<real, 2>(c, K_PAIR_LAST, cur, nullptr, w[j], w[j + 1], cs)));
-    else
-      TRY((sweep2<real, 1>(c, K_PAIR_MID, cur, nxt, w[j], w[j + 1], cs)));
-    if (!last) {
-      std::swap(cur, nxt);
-      std::swap(ccur, cnxt);
-    }
-    j += 2;
-  }
-  return FELBM_OK;
-}
-
 template <typename real>
 int enqueue_solve(felbm_ctx* c) {
   const int K = c->prm.solver_sweeps;
-  if (c->use_pair && K >= 2) return enqueue_solve_pairs<real>(c);
   real *xa = (real*)c->xa, *xb = (real*)c->xb;
   ConsArgs cs{c->fC, nullptr, nullptr, c->dlt, c->Cn, c->rC, 0.0};
   if (K == 0) return sweep<real, 4>(c, K_SWEEP_LAST, nullptr, nullptr, (real)0, cs);
@@ -510,32 +449,14 @@ int enqueue_adjoint_solve(felbm_ctx* c, real** result) {
   const std::vector<double>& w = c->cheb_w;
   real *cur = xa, *nxt = xb;
   double *ccur = c->xCa, *cnxt = c->xCb;
-  int j = 0;
-  if (!(c->use_pair && K >= 2) || K % 2 == 1) {
-    TRY((sweep<real, 0>(c, K_SWEEP_FIRST, nullptr, cur, (real)w[0], cs)));
-    j = 1;
-  }
-  if (c->use_pair && K >= 2) {
-    while (j < K) {
-      cs.xCin = ccur;
-      cs.xCout = cnxt;
-      if (j == 0)
-        TRY((sweep2<real, 0>(c, K_PAIR_FIRST, nullptr, nxt, w[0], w[1], cs)));
-      else
-        TRY((sweep2<real, 1>(c, K_PAIR_MID, cur, nxt, w[j], w[j + 1], cs)));
-      std::swap(cur, nxt);
-      std::swap(ccur, cnxt);
-      j += 2;
-    }
-  } else {
-    for (; j < K; ++j) {
-      cs.w = w[j];
-      cs.xCin = ccur;
-      cs.xCout = cnxt;
-      TRY((sweep<real, 1>(c, K_SWEEP_MID, cur, nxt, (real)w[j], cs)));
-      std::swap(cur, nxt);
-      std::swap(ccur, cnxt);
-    }
+  TRY((sweep<real, 0>(c, K_SWEEP_FIRST, nullptr, cur, (real)w[0], cs)));
+  for (int j = 1; j < K; ++j) {
+    cs.w = w[j];
+    cs.xCin = ccur;
+    cs.xCout = cnxt;
+    TRY((sweep<real, 1>(c, K_SWEEP_MID, cur, nxt, (real)w[j], cs)));
+    std::swap(cur, nxt);
+    std::swap(ccur, cnxt);
   }
   *result = cur;
   return FELBM_OK;
@@ -568,105 +489,6 @@ int enqueue_adjoint_step(felbm_ctx* c) {
 
 int enqueue_adjoint_step_any(felbm_ctx* c) {
   return c->prm.precision == FELBM_FP64 ? enqueue_adjoint_step<double>(c) : enqueue_adjoint_step<float>(c);
-}
-
-// Ring-1 rows (the rows of the tile's halo nodes, in slots of tile + ring 1 +
-// ring 2) and ring-2 node lists for the two-sweep kernel.
-int build_pairs(felbm_ctx* c, const MeshPrep& m, const std::vector<int32_t>& r1_off, const std::vector<int32_t>& r1,
-                const std::vector<int32_t>& tile_off, const std::vector<uint16_t>& tslot) {
-  const int64_t N = m.N, nt = (N + TILE - 1) / TILE;
-  std::vector<int32_t> ring_off(nt + 1, 0), ring_w(nt, 0), r2_off(nt + 1, 0), r2;
-  std::vector<uint16_t> rslot;
-  std::vector<double> rval;
-  int64_t max12 = 0, max1 = 0;
-  for (int64_t t = 0; t < nt; ++t) {
-    const int64_t lo = t * TILE, hi = std::min<int64_t>(N, lo + TILE);
-    const int32_t* ring = r1.data() + r1_off[t];
-    const int64_t n1 = r1_off[t + 1] - r1_off[t];
-    auto in_ring1 = [&](int32_t j) { return std::binary_search(ring, ring + n1, j); };
-    std::vector<int32_t> l2;
-    int64_t rw = 0;
-    for (int64_t h = 0; h < n1; ++h) {
-      const int32_t j = ring[h];
-      rw = std::max<int64_t>(rw, m.csr_ptr[j + 1] - m.csr_ptr[j]);
-      for (int32_t q = m.csr_ptr[j]; q < m.csr_ptr[j + 1]; ++q) {
-        const int32_t k = m.csr_col[q];
-        if ((k < lo || k >= hi) && !in_ring1(k)) l2.push_back(k);
-      }
-    }
-    std::sort(l2.begin(), l2.end());
-    l2.erase(std::unique(l2.begin(), l2.end()), l2.end());
-    if (rw > MAXW) return FELBM_OK;  // keep one sweep per launch
-    max12 = std::max<int64_t>(max12, n1 + (int64_t)l2.size());
-    max1 = std::max<int64_t>(max1, n1);
-    const size_t base = rslot.size();
-    rslot.resize(base + rw * n1);
-    rval.resize(base + rw * n1);
-    for (int64_t k = 0; k < rw; ++k)
-      for (int64_t h = 0; h < n1; ++h) {
-        const int32_t j = ring[h];
-        const size_t idx = base + k * n1 + h;
-        rslot[idx] = (uint16_t)(TILE + h);
-        rval[idx] = 0.0;
-        if (k < m.csr_ptr[j + 1] - m.csr_ptr[j]) {
-          const int32_t q = m.csr_col[m.csr_ptr[j] + k];
-          int64_t s;
-          if (q >= lo && q < hi)
-            s = q - lo;
-          else if (in_ring1(q))
-            s = TILE + (std::lower_bound(ring, ring + n1, q) - ring);
-          else
-            s = TILE + n1 + (std::lower_bound(l2.begin(), l2.end(), q) - l2.begin());
-          rslot[idx] = (uint16_t)s;
-          rval[idx] = m.csr_val[m.csr_ptr[j] + k];
-        }
-      }
-    ring_w[t] = (int32_t)rw;
-    ring_off[t + 1] = (int32_t)rslot.size();
-    r2.insert(r2.end(), l2.begin(), l2.end());
-    r2_off[t + 1] = (int32_t)r2.size();
-  }
-  (void)tile_off;
-  (void)tslot;
-  if (max1 > HALO_MAX || max12 > 2 * HALO_MAX) return FELBM_OK;  // keep one sweep per launch
-  // FP32 keeps one sweep per launch: the staging of its 18 populations in a
-  // single LDS pass is faster than two-sweep blocking in several passes
-  if (c->prm.precision == FELBM_FP32) return FELBM_OK;
-  const int64_t S = SLOTS2, S1 = SLOTS1;
-  const int G = c->prm.precision == FELBM_FP32 ? PAIR_G32 : PAIR_G64;
-  const size_t lds = (((size_t)G * (S + 2 * S1 - TILE) * c->rs + 15) & ~(size_t)15) +
-                     (c->prm.precision == FELBM_FP32 ? (size_t)(S + 2 * S1 - TILE) * 8 : 0);
-  if (lds > 65536) return FELBM_OK;
-  TRY(dalloc(c, &c->ring_off, ring_off.size()));
-  TRY(dalloc(c, &c->ring_w, ring_w.size()));
-  TRY(dalloc(c, &c->r2_off, r2_off.size()));
-  TRY(dalloc(c, &c->r2, r2.size()));
-  TRY(dalloc(c, &c->rslot, rslot.size()));
-  TRY(dalloc_bytes(c, &c->rval, rval.size() * c->rs));
-  TRY(upload(c, c->ring_off, ring_off));
-  TRY(upload(c, c->ring_w, ring_w));
-  TRY(upload(c, c->r2_off, r2_off));
-  TRY(upload(c, c->r2, r2));
-  TRY(upload(c, c->rslot, rslot));
-  if (c->prm.precision == FELBM_FP64) {
-    TRY(upload(c, (double*)c->rval, rval));
-  } else {
-    std::vector<float> v32(rval.begin(), rval.end());
-    TRY(upload(c, (float*)c->rval, v32));
-    HIP_OK(c, hipStreamSynchronize(c->stream));
-  }
-  HIP_OK(c, hipStreamSynchronize(c->stream));
-  c->pair_slots = (int)S;
-  c->pair_slots1 = (int)S1;
-  c->pair_lds = (uint32_t)lds;
-  c->use_pair = true;
-  const double s = (double)c->rs, Nd = (double)N;
-  const double tmat = (double)m.offdiag_nnz * (2.0 + s) + (double)r1.size() * 4.0;
-  const double cons = c->prm.precision == FELBM_FP32 ? 8.0 * Nd : 0.0;
-  c->kstat[K_PAIR_FIRST].bytes = 2 * 18 * Nd * s + tmat + 4 * cons;
-  c->kstat[K_PAIR_MID].bytes = 3 * 18 * Nd * s + tmat + 4 * cons;
-  c->kstat[K_PAIR_LAST].bytes = 5 * 18 * Nd * s + tmat + Nd + 6 * cons;
-  return FELBM_OK;
 }
 
 // Per-tile incident-element entries of the LDS-staged right-hand side (FP32):
@@ -733,7 +555,7 @@ int build_rhs_tiles(felbm_ctx* c, const MeshPrep& m, const std::vector<int32_t>&
 
 // Per-tile halo lists and local-slot matrix rows for the LDS-staged sweep.
 // Falls back to the global sliced-ELL sweep when a tile row is wider than
-// MAXW or the staging buffers would exceed 64 KiB of LDS.
+// MAXW or a tile's halo has more than HALO_MAX nodes.
 int build_tiles(felbm_ctx* c, const MeshPrep& m) {
   const int64_t N = m.N, nt = (N + TILE - 1) / TILE;
   std::vector<int32_t> tile_off(nt + 1, 0), halo_off(nt + 1, 0), halo;
@@ -774,10 +596,7 @@ int build_tiles(felbm_ctx* c, const MeshPrep& m) {
     halo_off[t + 1] = (int32_t)halo.size();
   }
   if (maxh > HALO_MAX) return FELBM_OK;  // keep the sliced-ELL sweep
-  const int64_t slots = SLOTS1;
-  const int G = c->prm.precision == FELBM_FP32 ? 18 : 9;
-  const size_t lds = (((size_t)G * slots * c->rs + 15) & ~(size_t)15) + (c->prm.precision == FELBM_FP32 ? slots * 8 : 0);
-  if (lds > 65536) return FELBM_OK;
+  const int64_t slots = TILE + maxh;
   TRY(dalloc(c, &c->tile_off, tile_off.size()));
   TRY(dalloc(c, &c->halo_off, halo_off.size()));
   TRY(dalloc(c, &c->halo, halo.size()));
@@ -797,7 +616,6 @@ int build_tiles(felbm_ctx* c, const MeshPrep& m) {
   HIP_OK(c, hipStreamSynchronize(c->stream));
   c->ntiles = (int)nt;
   c->tile_slots = (int)slots;
-  c->lds_bytes = (uint32_t)lds;
   c->use_lds = true;
   // algorithmic bytes: true nonzeros only (padding entries are not counted)
   const double s = (double)c->rs, Nd = (double)N;
@@ -807,7 +625,6 @@ int build_tiles(felbm_ctx* c, const MeshPrep& m) {
   c->kstat[K_SWEEP_MID].bytes = 3 * 18 * Nd * s + tmat + 4 * cons;
   c->kstat[K_SWEEP_LAST].bytes = 4 * 18 * Nd * s + tmat + Nd + 5 * cons;
   TRY(build_rhs_tiles(c, m, halo_off, halo));
-  TRY(build_pairs(c, m, halo_off, halo, tile_off, slot));
   return FELBM_OK;
 }
 

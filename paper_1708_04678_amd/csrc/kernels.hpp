@@ -486,12 +486,9 @@ __global__ void __launch_bounds__(BLOCK) k_rhs(int N, int Np, int E, const int* 
 constexpr int TILE = BLOCK;
 constexpr int MAXW = 12;
 // compile-time LDS strides (so that population offsets are instruction
-// immediates): one-sweep halo <= 128; two-sweep ring 1 <= 128, rings 1+2 <= 256
+// immediates): halo of a tile <= 128 nodes
 constexpr int HALO_MAX = 128;
-constexpr int SLOTS1 = TILE + HALO_MAX;     // tile + ring 1
-constexpr int SLOTS2 = TILE + 2 * HALO_MAX; // tile + ring 1 + ring 2
-constexpr int PAIR_G32 = 6;  // populations per LDS pass of the two-sweep kernel (FP32)
-constexpr int PAIR_G64 = 3;  // (FP64)
+constexpr int SLOTS1 = TILE + HALO_MAX;  // tile + halo
 
 struct TileArgs {
   const int* tile_off;   // [ntiles+1] entry offsets
@@ -793,163 +790,44 @@ __global__ void __launch_bounds__(BLOCK) k_sweep(int N, int Np, const int* __res
 }
 
 // ----------------------------------------------------------------------------
-// The same sweep staged through LDS, one workgroup per tile of 256 consecutive
-// (internal-order) nodes.  The tile's own iterate values are loaded coalesced,
-// the values of its halo (outside neighbours, listed per tile) are gathered
-// once, and the matrix rows address LDS slots with 16-bit indices: slot < 256
-// is the tile node, slot >= 256 the halo entry.  Row entries are stored
-// column-major per tile (entry k of lane l at tile_off + k*256 + l) and held
-// in registers; padded entries point at the row's own slot with weight 0.
-// FP32 stages all 18 populations at once, FP64 nine at a time.
+// The sweep on 256-node tiles staged in LDS.  Slots: [0, 256) are the tile's
+// own nodes, [256, 256 + halo) its halo (outside neighbours, listed per
+// tile).  Matrix rows use 16-bit slots, stored column-major per tile (entry k
+// of lane l at tile_off + k*256 + l); padded entries point at the row's own
+// slot with weight 0.  Staging by LDS DMA (global_load_lds): the loads write
+// LDS directly, so nothing is held in VGPRs while they are in flight and a
+// workgroup issues all of its staging (tile, halo, FP64 composition iterate,
+// the f values it needs later) before one wait.  Two workgroups per tile, one
+// per population set (g: 0..8, h: 9..17), which keeps the LDS of a workgroup
+// at 9 populations and lets more tiles be in flight per CU; in FP32 the h
+// workgroup also carries the FP64 composition sweep.  Tile values move 16
+// bytes per lane; FP32 halo values are 4-byte DMA gathers of 64 entries per
+// instruction, FP64 halo values go through registers.  LDS: [9][SLOTS1]
+// values, then (FP32) [SLOTS1] doubles.
 // ----------------------------------------------------------------------------
+template <typename real>
+constexpr unsigned sweep_dma_lds_bytes() {
+  return Q * SLOTS1 * sizeof(real) + (Conserve<real>::on ? SLOTS1 * 8 : 0);
+}
+
 template <typename real, int MODE>
-__global__ void __launch_bounds__(BLOCK) k_sweep_lds(int N, int Np, TileArgs ta, const real* __restrict__ tval,
+__global__ void __launch_bounds__(BLOCK) k_sweep_dma(int N, int Np, TileArgs ta, const real* __restrict__ tval,
                                                     const real* __restrict__ f, const real* __restrict__ xin,
                                                     real* __restrict__ xout, real* __restrict__ pop,
                                                     const uint8_t* __restrict__ is_wall, real w, ConsArgs cs) {
   extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int S = SLOTS1;
   constexpr bool CONS = Conserve<real>::on;
-  constexpr int G = sizeof(real) == 4 ? NPOP : Q;  // populations per LDS pass
-  constexpr int S = SLOTS1;
-  real* xs = reinterpret_cast<real*>(smem);
-  double* cxs = reinterpret_cast<double*>(smem + (((size_t)G * S * sizeof(real) + 15) & ~(size_t)15));
-  const int t = xcd_block();
-  if (t >= ta.ntiles) return;  // block-uniform: no barrier is skipped by part of a block
-  const int lane = threadIdx.x;
-  const int i = t * TILE + lane;
-  const bool valid = i < N;
-  const int h0 = ta.halo_off[t], nh = ta.halo_off[t + 1] - h0;
-  const int e0 = ta.tile_off[t], width = (ta.tile_off[t + 1] - e0) / TILE;
-  int sl[MAXW];
-  real va[MAXW];
-#pragma unroll
-  for (int k = 0; k < MAXW; ++k) {
-    if (k < width) {
-      sl[k] = ta.slot[e0 + k * TILE + lane];
-      va[k] = tval[e0 + k * TILE + lane];
-    } else {
-      sl[k] = lane;
-      va[k] = 0;
-    }
-  }
-  const real* __restrict__ x = (MODE == 0 || MODE == 3) ? f : xin;
-  const double* __restrict__ xC = (MODE == 0 || MODE == 3) ? cs.fC : cs.xCin;
-  real r[NPOP], xo[NPOP];
-  double rc = 0.0, xco = 0.0;
-#pragma unroll
-  for (int g0 = 0; g0 < NPOP; g0 += G) {
-    if (MODE != 4) {
-#pragma unroll
-      for (int a = 0; a < G; ++a) {
-        xo[g0 + a] = valid ? x[(g0 + a) * Np + i] : (real)0;
-        xs[a * S + lane] = xo[g0 + a];
-      }
-      for (int h = lane; h < nh; h += TILE) {
-        const int j = ta.halo[h0 + h];
-#pragma unroll
-        for (int a = 0; a < G; ++a) xs[a * S + TILE + h] = x[(g0 + a) * Np + j];
-      }
-      if (CONS && g0 == 0) {
-        xco = valid ? xC[i] : 0.0;
-        cxs[lane] = xco;
-        for (int h = lane; h < nh; h += TILE) cxs[TILE + h] = xC[ta.halo[h0 + h]];
-      }
-      __syncthreads();
-#pragma unroll
-      for (int a = 0; a < G; ++a) {
-        real acc = (real)0.5 * xo[g0 + a];
-#pragma unroll
-        for (int k = 0; k < MAXW; ++k)
-          if (k < width) acc += va[k] * xs[a * S + sl[k]];
-        r[g0 + a] = acc;
-      }
-      if (CONS && g0 == 0) {
-        double acc = valid ? cs.dlt[i] * xco : 0.0;
-#pragma unroll
-        for (int k = 0; k < MAXW; ++k)
-          if (k < width) acc += (double)va[k] * cxs[sl[k]];
-        rc = acc;
-      }
-      __syncthreads();
-    }
-  }
-  if (!valid) return;
-  if (MODE != 4) {
-#pragma unroll
-    for (int a = 0; a < NPOP; ++a) {
-      const real fi = (MODE == 0 || MODE == 3) ? xo[a] : f[a * Np + i];
-      r[a] = xo[a] + w * (fi - r[a]);
-    }
-    if (CONS) {
-      const double fi = (MODE == 0 || MODE == 3) ? xco : cs.fC[i];
-      rc = xco + cs.w * (fi - rc);
-    }
-  } else {
-#pragma unroll
-    for (int a = 0; a < NPOP; ++a) r[a] = f[a * Np + i];
-    if (CONS) rc = cs.fC[i];
-  }
-  if (MODE == 0 || MODE == 1) {
-#pragma unroll
-    for (int a = 0; a < NPOP; ++a) xout[a * Np + i] = r[a];
-    if (CONS) cs.xCout[i] = rc;
-    return;
-  }
-  real s[NPOP];
-#pragma unroll
-  for (int a = 0; a < NPOP; ++a) s[a] = pop[a * Np + i] + r[a];
-  if (is_wall[i]) {
-#pragma unroll
-    for (int a = 1; a < Q; ++a) {
-      const int b = opp(a);
-      if (b > a) {
-        const real mg = (real)0.5 * (s[a] + s[b]), mh = (real)0.5 * (s[Q + a] + s[Q + b]);
-        s[a] = mg; s[b] = mg; s[Q + a] = mh; s[Q + b] = mh;
-      }
-    }
-  }
-#pragma unroll
-  for (int a = 0; a < NPOP; ++a) pop[a * Np + i] = s[a];
-  if (CONS) {
-    double sh = 0.0;
-#pragma unroll
-    for (int a = 0; a < Q; ++a) sh += (double)s[Q + a];
-    cs.rC[i] = (cs.Cn[i] + rc) - sh;
-  }
-}
-
-// ----------------------------------------------------------------------------
-// FP32 sweep staged by LDS DMA (global_load_lds): the loads write LDS
-// directly, so nothing is held in VGPRs while they are in flight and a
-// workgroup issues all of its staging (tile, halo, FP64 composition iterate,
-// the f values it needs later) before one wait.  Two workgroups per tile, one
-// per population set (g: 0..8, h: 9..17), which keeps the LDS of a workgroup
-// at 9 populations and lets more tiles be in flight per CU; the h workgroup
-// also carries the FP64 composition sweep.  Tile values move 16 bytes per
-// lane (one instruction per population covers the 256-node tile); halo values
-// are 4-byte gathers of 64 entries per instruction, written to consecutive
-// slots.  Same tile rows and slots as k_sweep_lds; LDS: [9][SLOTS1] floats,
-// then [SLOTS1] doubles.
-// ----------------------------------------------------------------------------
-constexpr unsigned SWEEP_DMA_LDS_BYTES = Q * SLOTS1 * 4 + SLOTS1 * 8;
-
-template <int MODE>
-__global__ void __launch_bounds__(BLOCK) k_sweep_dma(int N, int Np, TileArgs ta, const float* __restrict__ tval,
-                                                    const float* __restrict__ f, const float* __restrict__ xin,
-                                                    float* __restrict__ xout, float* __restrict__ pop,
-                                                    const uint8_t* __restrict__ is_wall, float w, ConsArgs cs) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int S = SLOTS1;
   constexpr bool FIRST = MODE == 0 || MODE == 3;   // iterate = f
   constexpr bool STAGE = MODE != 4;
   // f, the rows and the new iterate are streamed with nontemporal accesses
   // (measured 1.5 % faster over the sweeps of a step than ordinary ones)
   constexpr bool NT = true;
-  float* xs = reinterpret_cast<float*>(smem);
-  double* cxs = reinterpret_cast<double*>(smem + Q * S * sizeof(float));
+  real* xs = reinterpret_cast<real*>(smem);
+  double* cxs = reinterpret_cast<double*>(smem + Q * S * sizeof(real));
   const int vb = xcd_block();
   const int t = vb >> 1;
-  const bool hset = (vb & 1) != 0;  // block-uniform: this workgroup sweeps h (and the composition)
+  const bool hset = (vb & 1) != 0;  // block-uniform: this workgroup sweeps h (and, FP32, the composition)
   if (t >= ta.ntiles) return;       // block-uniform
   const int p0 = hset ? Q : 0;
   const int lane = threadIdx.x;
@@ -960,19 +838,28 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_dma(int N, int Np, TileArgs ta,
   const bool valid = i < N;
   const int h0 = ta.halo_off[t], nh = ta.halo_off[t + 1] - h0;
   const int e0 = ta.tile_off[t], width = (ta.tile_off[t + 1] - e0) / TILE;
-  const float* __restrict__ x = (FIRST ? f : xin) + p0 * Np;
+  const real* __restrict__ x = (FIRST ? f : xin) + p0 * Np;
   const double* __restrict__ xC = FIRST ? cs.fC : cs.xCin;
   if (STAGE) {
     // Np is a multiple of 64, so a 16-byte chunk that starts below Np ends inside the array
-    if (base + 4 * l < Np)
-      for (int a = wave; a < Q; a += 4) lds_dma16(x + a * Np + base + 4 * l, xs + a * S);
+    constexpr int PER = 16 / sizeof(real);  // values per lane and 16-byte load
+#pragma unroll
+    for (int c = 0; c < TILE / (64 * PER); ++c)
+      if (base + c * 64 * PER + PER * l < Np)
+        for (int a = wave; a < Q; a += 4) lds_dma16(x + a * Np + base + c * 64 * PER + PER * l, xs + a * S + c * 64 * PER);
     const int hid0 = l < nh ? ta.halo[h0 + l] : 0;
     const int hid1 = 64 + l < nh ? ta.halo[h0 + 64 + l] : 0;
     for (int a = wave; a < Q; a += 4) {
-      if (l < nh) lds_dma4(x + a * Np + hid0, xs + a * S + TILE);
-      if (64 + l < nh) lds_dma4(x + a * Np + hid1, xs + a * S + TILE + 64);
+      if constexpr (sizeof(real) == 4) {
+        if (l < nh) lds_dma4(x + a * Np + hid0, xs + a * S + TILE);
+        if (64 + l < nh) lds_dma4(x + a * Np + hid1, xs + a * S + TILE + 64);
+      } else {
+        // 8-byte halo values go through registers (LDS DMA moves at most 4 bytes per gathered lane)
+        if (l < nh) xs[a * S + TILE + l] = x[a * Np + hid0];
+        if (64 + l < nh) xs[a * S + TILE + 64 + l] = x[a * Np + hid1];
+      }
     }
-    if (hset) {
+    if (CONS && hset) {
       if (wave < 2) {
         // two doubles per lane; waves 0 and 1 cover tile nodes [0,128) and [128,256)
         if (base + wave * 128 + 2 * l < Np) lds_dma16(xC + base + wave * 128 + 2 * l, cxs + wave * 128);
@@ -983,7 +870,7 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_dma(int N, int Np, TileArgs ta,
     }
   }
   int sl[MAXW];
-  float va[MAXW];
+  real va[MAXW];
 #pragma unroll
   for (int k = 0; k < MAXW; ++k) {
     if (k < width) {
@@ -991,37 +878,37 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_dma(int N, int Np, TileArgs ta,
       va[k] = ld_stream<NT>(&tval[e0 + k * TILE + lane]);
     } else {
       sl[k] = lane;
-      va[k] = 0.0f;
+      va[k] = (real)0;
     }
   }
   // the f values of the own node, in flight together with the staging
-  float fr[Q];
+  real fr[Q];
   double fCi = 0.0, dlti = 0.0;
   if (!FIRST && valid) {
 #pragma unroll
     for (int a = 0; a < Q; ++a) fr[a] = ld_stream<NT>(&f[(p0 + a) * Np + i]);
-    if (hset) fCi = cs.fC[i];
+    if (CONS && hset) fCi = cs.fC[i];
   }
-  if (STAGE && hset && valid) dlti = cs.dlt[i];
+  if (CONS && STAGE && hset && valid) dlti = cs.dlt[i];
   if (STAGE) {
     __builtin_amdgcn_s_waitcnt(0);  // this wave's LDS DMA has landed
     __syncthreads();
   }
   if (!valid) return;
-  float r[Q];
+  real r[Q];
   double rc = 0.0;
   if (STAGE) {
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
-      const float xi = xs[a * S + lane];
-      float acc = 0.5f * xi;
+      const real xi = xs[a * S + lane];
+      real acc = (real)0.5 * xi;
 #pragma unroll
       for (int k = 0; k < MAXW; ++k)
         if (k < width) acc += va[k] * xs[a * S + sl[k]];
       r[a] = xi + w * ((FIRST ? xi : fr[a]) - acc);
       if (MODE == 0 || MODE == 1) st_stream<NT>(r[a], &xout[(p0 + a) * Np + i]);
     }
-    if (hset) {
+    if (CONS && hset) {
       const double xco = cxs[lane];
       double acc = dlti * xco;
 #pragma unroll
@@ -1035,10 +922,10 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_dma(int N, int Np, TileArgs ta,
     rc = fCi;
   }
   if (MODE == 0 || MODE == 1) {
-    if (hset) st_stream<NT>(rc, &cs.xCout[i]);
+    if (CONS && hset) st_stream<NT>(rc, &cs.xCout[i]);
     return;
   }
-  float s[Q];
+  real s[Q];
 #pragma unroll
   for (int a = 0; a < Q; ++a) s[a] = pop[(p0 + a) * Np + i] + r[a];
   if (is_wall[i]) {
@@ -1047,232 +934,19 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_dma(int N, int Np, TileArgs ta,
     for (int a = 1; a < Q; ++a) {
       const int b = opp(a);
       if (b > a) {
-        const float m = 0.5f * (s[a] + s[b]);
+        const real m = (real)0.5 * (s[a] + s[b]);
         s[a] = m; s[b] = m;
       }
     }
   }
 #pragma unroll
   for (int a = 0; a < Q; ++a) pop[(p0 + a) * Np + i] = s[a];
-  if (hset) {
+  if (CONS && hset) {
     double sh = 0.0;
 #pragma unroll
     for (int a = 0; a < Q; ++a) sh += (double)s[a];
     cs.rC[i] = (cs.Cn[i] + rc) - sh;
   }
-}
-
-// ----------------------------------------------------------------------------
-// Two sweeps per launch (temporal blocking).  Each tile stages its iterate on
-// the tile, its first halo ring (outside neighbours) and second ring
-// (neighbours of the first ring), runs the first sweep on tile + ring 1 into
-// a second LDS buffer and the second sweep on the tile rows.  Because the
-// Chebyshev-step Richardson recurrence is first order, x_{j+2} follows from
-// x_j and f alone, so one launch reads the iterate and f once and writes once.
-// Slots: [0, 256) tile, [256, 256 + R1) ring 1, then ring 2.  Ring-1 rows are
-// stored per tile column-major with stride R1 (entry k of ring row h at
-// ring_off + k*R1 + h).
-// PMODE 0: x_j = f (first pair); 1: middle pair; 2: last pair, writes
-// psi_bar^{n+1} = psi_hat + x_{j+2} with the wall operator; 3: first and last.
-// ----------------------------------------------------------------------------
-struct PairArgs {
-  const int* tile_off;    // tile rows (as TileArgs)
-  const uint16_t* slot;
-  const int* ring_off;    // [ntiles+1] offsets of the ring-1 row entries
-  const int* ring_w;      // [ntiles] width of the ring-1 rows
-  const uint16_t* rslot;  // ring-1 row slots
-  const int* r1_off;      // [ntiles+1] ring-1 node lists
-  const int* r1;
-  const int* r2_off;      // [ntiles+1] ring-2 node lists
-  const int* r2;
-  int ntiles, slots, slots1;  // slots = 256 + max(R1 + R2), slots1 = 256 + max R1
-};
-
-template <typename real, int PMODE>
-__global__ void __launch_bounds__(BLOCK, 4) k_sweep2(int N, int Np, PairArgs pa, const real* __restrict__ tval,
-                                                 const real* __restrict__ rval, const real* __restrict__ f,
-                                                 const real* __restrict__ xin, real* __restrict__ xout,
-                                                 real* __restrict__ pop, const uint8_t* __restrict__ is_wall,
-                                                 real w0, real w1, ConsArgs cs, double cw0, double cw1) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  constexpr bool CONS = Conserve<real>::on;
-  constexpr int G = sizeof(real) == 4 ? PAIR_G32 : PAIR_G64;  // populations per LDS pass
-  constexpr bool FIRST = (PMODE == 0 || PMODE == 3), LAST = (PMODE == 2 || PMODE == 3);
-  constexpr int S = SLOTS2, S1 = SLOTS1;
-  // LDS: x [G][S], y [G][S1], f on ring 1 [G][S1 - 256]; FP64 composition: cx [S], cy [S1], cf [S1 - 256]
-  real* xs = reinterpret_cast<real*>(smem);
-  real* ys = xs + G * S;
-  real* fr = ys + G * S1;
-  double* cx = reinterpret_cast<double*>(smem + (((size_t)G * (S + 2 * S1 - TILE) * sizeof(real) + 15) & ~(size_t)15));
-  double* cy = cx + S;
-  double* cf = cy + S1;
-  const int t = xcd_block();
-  if (t >= pa.ntiles) return;  // block-uniform
-  const int lane = threadIdx.x;
-  const int i = t * TILE + lane;
-  const bool valid = i < N;
-  const int a0 = pa.r1_off[t], n1 = pa.r1_off[t + 1] - a0;
-  const int b0 = pa.r2_off[t], n2 = pa.r2_off[t + 1] - b0;
-  const int e0 = pa.tile_off[t], width = (pa.tile_off[t + 1] - e0) / TILE;
-  const int q0 = pa.ring_off[t], rw = pa.ring_w[t];
-  int sl[MAXW];
-  real va[MAXW];
-#pragma unroll
-  for (int k = 0; k < MAXW; ++k) {
-    if (k < width) {
-      sl[k] = pa.slot[e0 + k * TILE + lane];
-      va[k] = tval[e0 + k * TILE + lane];
-    } else {
-      sl[k] = lane;
-      va[k] = 0;
-    }
-  }
-  const real* __restrict__ x = FIRST ? f : xin;
-  const double* __restrict__ xC = FIRST ? cs.fC : cs.xCin;
-  double sh = 0.0;  // sum of the new h populations (LAST, FP32)
-#pragma unroll 1
-  for (int g0 = 0; g0 < NPOP; g0 += G) {
-    // stage x on tile, ring 1, ring 2 and f on ring 1
-    real fo[G];
-#pragma unroll
-    for (int a = 0; a < G; ++a) {
-      const real xv = valid ? x[(g0 + a) * Np + i] : (real)0;
-      xs[a * S + lane] = xv;
-      fo[a] = FIRST ? xv : (valid ? f[(g0 + a) * Np + i] : (real)0);
-    }
-    for (int h = lane; h < n1; h += TILE) {
-      const int j = pa.r1[a0 + h];
-#pragma unroll
-      for (int a = 0; a < G; ++a) {
-        const real xv = x[(g0 + a) * Np + j];
-        xs[a * S + TILE + h] = xv;
-        fr[a * (S1 - TILE) + h] = FIRST ? xv : f[(g0 + a) * Np + j];
-      }
-    }
-    for (int h = lane; h < n2; h += TILE) {
-      const int j = pa.r2[b0 + h];
-#pragma unroll
-      for (int a = 0; a < G; ++a) xs[a * S + TILE + n1 + h] = x[(g0 + a) * Np + j];
-    }
-    const bool cpass = CONS && g0 == 0;
-    double cfo = 0.0;
-    if (cpass) {
-      const double xv = valid ? xC[i] : 0.0;
-      cx[lane] = xv;
-      cfo = FIRST ? xv : (valid ? cs.fC[i] : 0.0);
-      for (int h = lane; h < n1; h += TILE) {
-        const int j = pa.r1[a0 + h];
-        const double v = xC[j];
-        cx[TILE + h] = v;
-        cf[h] = FIRST ? v : cs.fC[j];
-      }
-      for (int h = lane; h < n2; h += TILE) cx[TILE + n1 + h] = xC[pa.r2[b0 + h]];
-    }
-    __syncthreads();
-    // first sweep on the tile rows ...
-#pragma unroll
-    for (int a = 0; a < G; ++a) {
-      const real xv = xs[a * S + lane];
-      real acc = (real)0.5 * xv;
-#pragma unroll
-      for (int k = 0; k < MAXW; ++k)
-        if (k < width) acc += va[k] * xs[a * S + sl[k]];
-      ys[a * S1 + lane] = xv + w0 * (fo[a] - acc);
-    }
-    if (cpass) {
-      const double xv = cx[lane];
-      double acc = valid ? cs.dlt[i] * xv : 0.0;
-#pragma unroll
-      for (int k = 0; k < MAXW; ++k)
-        if (k < width) acc += (double)va[k] * cx[sl[k]];
-      cy[lane] = xv + cw0 * (cfo - acc);
-    }
-    // ... and on the ring-1 rows (entries loaded once per row)
-    for (int h = lane; h < n1; h += TILE) {
-      int rs[MAXW];
-      real rv[MAXW];
-#pragma unroll
-      for (int k = 0; k < MAXW; ++k) {
-        rs[k] = k < rw ? pa.rslot[q0 + k * n1 + h] : TILE + h;
-        rv[k] = k < rw ? rval[q0 + k * n1 + h] : (real)0;
-      }
-#pragma unroll
-      for (int a = 0; a < G; ++a) {
-        const real xv = xs[a * S + TILE + h];
-        real acc = (real)0.5 * xv;
-#pragma unroll
-        for (int k = 0; k < MAXW; ++k)
-          if (k < rw) acc += rv[k] * xs[a * S + rs[k]];
-        ys[a * S1 + TILE + h] = xv + w0 * (fr[a * (S1 - TILE) + h] - acc);
-      }
-      if (cpass) {
-        const double xr = cx[TILE + h];
-        double ar = cs.dlt[pa.r1[a0 + h]] * xr;
-#pragma unroll
-        for (int k = 0; k < MAXW; ++k)
-          if (k < rw) ar += (double)rv[k] * cx[rs[k]];
-        cy[TILE + h] = xr + cw0 * (cf[h] - ar);
-      }
-    }
-    __syncthreads();
-    // second sweep on the tile rows, written out directly
-#pragma unroll
-    for (int a = 0; a < G; ++a) {
-      const real yv = ys[a * S1 + lane];
-      real acc = (real)0.5 * yv;
-#pragma unroll
-      for (int k = 0; k < MAXW; ++k)
-        if (k < width) acc += va[k] * ys[a * S1 + sl[k]];
-      const real z = yv + w1 * (fo[a] - acc);
-      if (valid) {
-        const int p = g0 + a;
-        if (!LAST) {
-          xout[p * Np + i] = z;
-        } else {
-          const real s = pop[p * Np + i] + z;
-          pop[p * Np + i] = s;
-          if (p >= Q) sh += (double)s;
-        }
-      }
-    }
-    if (cpass) {
-      const double yv = cy[lane];
-      double acc = valid ? cs.dlt[i] * yv : 0.0;
-#pragma unroll
-      for (int k = 0; k < MAXW; ++k)
-        if (k < width) acc += (double)va[k] * cy[sl[k]];
-      const double z = yv + cw1 * (cfo - acc);
-      if (valid) {
-        if (!LAST)
-          cs.xCout[i] = z;
-        else
-          cs.rC[i] = cs.Cn[i] + z;  // the h sum is subtracted below
-      }
-    }
-    __syncthreads();
-  }
-  if (!LAST || !valid) return;
-  if (is_wall[i]) {
-    // wall operator on the values this thread just wrote
-    real s[NPOP];
-#pragma unroll
-    for (int a = 0; a < NPOP; ++a) s[a] = pop[a * Np + i];
-#pragma unroll
-    for (int a = 1; a < Q; ++a) {
-      const int b = opp(a);
-      if (b > a) {
-        const real mg = (real)0.5 * (s[a] + s[b]), mh = (real)0.5 * (s[Q + a] + s[Q + b]);
-        s[a] = mg; s[b] = mg; s[Q + a] = mh; s[Q + b] = mh;
-      }
-    }
-    sh = 0.0;
-#pragma unroll
-    for (int a = 0; a < NPOP; ++a) {
-      pop[a * Np + i] = s[a];
-      if (a >= Q) sh += (double)s[a];
-    }
-  }
-  if (CONS) cs.rC[i] -= sh;
 }
 
 // ----------------------------------------------------------------------------
