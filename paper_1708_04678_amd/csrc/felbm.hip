@@ -268,15 +268,13 @@ template <typename real>
 int enqueue_rhs(felbm_ctx* c) {
   const int gN = grid_for(c->N);
   const int N = (int)c->N, Np = (int)c->Np, E = (int)c->E;
-  if constexpr (std::is_same<real, float>::value) {
-    if (c->use_rhs_lds) {
-      TileArgs ta{c->tile_off, c->tslot, c->halo_off, c->halo, c->ntiles, c->tile_slots};
-      const int grid = (c->ntiles + 7) / 8 * 8;
-      return launch_sm(c, K_RHS, k_rhs_lds, grid, BLOCK, RHS_LDS_BYTES, N, Np, E, ta,
-                       RhsTile{c->rhs_off, c->rhs_ent, c->gaos, c->gC, (const float*)c->gp, c->lapmu},
-                       (const double*)c->Cn, (const float*)c->uxn, (const float*)c->uyn, (const double*)c->mu,
-                       (const float*)c->pop, (const double*)c->mass, c->sp, (float*)c->f, c->fC);
-    }
+  if (c->use_rhs_lds) {
+    TileArgs ta{c->tile_off, c->tslot, c->halo_off, c->halo, c->ntiles, c->tile_slots};
+    const int grid = (c->ntiles + 7) / 8 * 8;
+    return launch_sm(c, K_RHS, k_rhs_lds<real>, grid, BLOCK, rhs_lds_bytes<real>(), N, Np, E, ta,
+                     RhsTile{c->rhs_off, c->rhs_ent, c->gaos, c->gC, c->gp, c->lapmu}, (const double*)c->Cn,
+                     (const real*)c->uxn, (const real*)c->uyn, (const double*)c->mu, (const real*)c->pop,
+                     (const double*)c->mass, c->sp, (real*)c->f, c->fC);
   }
   return launch(c, K_RHS, k_rhs<real>, gN, N, Np, E, (const int*)c->n2e_ptr, (const int*)c->n2e, (const int*)c->tri,
                 (const real*)c->geor, (const double*)c->geo, (const double*)c->gC, (const real*)c->gp,
@@ -491,14 +489,13 @@ int enqueue_adjoint_step_any(felbm_ctx* c) {
   return c->prm.precision == FELBM_FP64 ? enqueue_adjoint_step<double>(c) : enqueue_adjoint_step<float>(c);
 }
 
-// Per-tile incident-element entries of the LDS-staged right-hand side (FP32):
+// Per-tile incident-element entries of the LDS-staged right-hand side:
 // for node lane of tile t, entry k = (element * 4 + local vertex, LDS slots of
 // the element's three vertices), column-major per tile, padded with -1.  Every
 // vertex of an element incident to a tile node is a tile node or in the tile's
 // halo (the halo lists every node coupled by the mass matrix).
 int build_rhs_tiles(felbm_ctx* c, const MeshPrep& m, const std::vector<int32_t>& halo_off,
                     const std::vector<int32_t>& halo) {
-  if (c->prm.precision != FELBM_FP32) return FELBM_OK;
   const int64_t N = m.N, E = m.E, nt = (N + TILE - 1) / TILE;
   std::vector<int32_t> off(nt + 1, 0);
   std::vector<int2> ent;
@@ -546,10 +543,12 @@ int build_rhs_tiles(felbm_ctx* c, const MeshPrep& m, const std::vector<int32_t>&
   HIP_OK(c, hipStreamSynchronize(c->stream));
   c->use_rhs_lds = true;
   // algorithmic bytes: populations and nodal fields once per node (C, mu, u, mass),
-  // f and fC written, the true entries, element data (FP64 geometry, grad C, grad p, lap mu)
+  // f (and, FP32, fC) written, the true entries, element data (FP64 geometry,
+  // grad C, grad p, lap mu)
   const double Nd = (double)N, Ed = (double)E;
-  c->kstat[K_RHS].bytes = 2 * 18 * Nd * 4 + Nd * (8 + 8 + 4 + 4 + 8 + 8) + (double)true_entries * 8 +
-                          Ed * (56 + 16 + 8 + 8) + (double)halo.size() * 4;
+  const double s = (double)c->rs, cons = c->prm.precision == FELBM_FP32 ? 8.0 : 0.0;
+  c->kstat[K_RHS].bytes = 2 * 18 * Nd * s + Nd * (8 + 8 + 2 * s + 8 + cons) + (double)true_entries * 8 +
+                          Ed * (56 + 16 + 2 * s + 8) + (double)halo.size() * 4;
   return FELBM_OK;
 }
 

@@ -523,39 +523,46 @@ __device__ __forceinline__ void st_stream(T v, T* p) {
 
 // ----------------------------------------------------------------------------
 // The same right-hand side with the vertex data of a 256-node tile and its
-// halo staged in LDS (FP32): post-collision populations by LDS DMA, the nodal
-// fields C, mu, u by ordinary loads.  Thread = node; its incident elements are
+// halo staged in LDS: post-collision populations (tile by 16-byte LDS DMA; FP32
+// halo by 4-byte DMA gathers, FP64 halo through registers), the nodal fields
+// C, mu, u by ordinary loads.  Thread = node; its incident elements are
 // listed per tile column-major (entry k of lane l at ent_off[t] + k*256 + l):
 // x = element * 4 + local vertex (-1 = padding), y = LDS slots of the
 // element's vertices 0, 1, 2 (9 bits each).  Element data (geometry, grad C,
 // grad p, lap mu) is read from global memory; geometry in FP64 and rounded
-// for the FP32 arithmetic.  The FP64 zeroth h-moment uses
+// to the working precision.  FP32 only: the FP64 zeroth h-moment uses
 // div J = sum_a s_a, div Pi = sum_a e_a s_a with
 // s_a = sum_v (e_a . grad N_v) h_hat_{a,v}, in a vertex order that does not
 // depend on which vertex gathers, as in k_rhs.
 // ----------------------------------------------------------------------------
-constexpr unsigned RHS_LDS_BYTES = NPOP * SLOTS1 * 4 + SLOTS1 * (8 + 8 + 4 + 4);
+template <typename real>
+constexpr unsigned rhs_lds_bytes() {
+  return NPOP * SLOTS1 * sizeof(real) + SLOTS1 * (8 + 8 + 2 * sizeof(real));
+}
 struct RhsTile {
-  const int* ent_off;  // [ntiles+1]
-  const int2* ent;     // [entries]
-  const double* gaos;  // [E][8] FP64 element geometry {A, dN0/dx, dN0/dy, dN1/dx, dN1/dy, dN2/dx, dN2/dy, 0}
-  const double* gC;    // [2][E]
-  const float* gp;     // [2][E]
-  const double* lapmu; // [E]
+  const int* ent_off;   // [ntiles+1]
+  const int2* ent;      // [entries]
+  const double* gaos;   // [E][8] FP64 element geometry {A, dN0/dx, dN0/dy, dN1/dx, dN1/dy, dN2/dx, dN2/dy, 0}
+  const double* gC;     // [2][E]
+  const void* gp;       // [2][E] in the working precision
+  const double* lapmu;  // [E]
 };
 
+template <typename real>
 __global__ void __launch_bounds__(BLOCK) k_rhs_lds(int N, int Np, int E, TileArgs ta, RhsTile rt,
-                                                  const double* __restrict__ Cn, const float* __restrict__ uxn,
-                                                  const float* __restrict__ uyn, const double* __restrict__ mu,
-                                                  const float* __restrict__ pop, const double* __restrict__ mass,
-                                                  StepParams P, float* __restrict__ f, double* __restrict__ fC) {
+                                                  const double* __restrict__ Cn, const real* __restrict__ uxn,
+                                                  const real* __restrict__ uyn, const double* __restrict__ mu,
+                                                  const real* __restrict__ pop, const double* __restrict__ mass,
+                                                  StepParams P, real* __restrict__ f, double* __restrict__ fC) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int S = SLOTS1;
-  float* ps = reinterpret_cast<float*>(smem);
-  double* Cs = reinterpret_cast<double*>(smem + NPOP * S * sizeof(float));
+  constexpr bool CONS = Conserve<real>::on;
+  real* ps = reinterpret_cast<real*>(smem);
+  double* Cs = reinterpret_cast<double*>(smem + NPOP * S * sizeof(real));
   double* mus = Cs + S;
-  float* uxs = reinterpret_cast<float*>(mus + S);
-  float* uys = uxs + S;
+  real* uxs = reinterpret_cast<real*>(mus + S);
+  real* uys = uxs + S;
+  const real* __restrict__ gp = static_cast<const real*>(rt.gp);
   const int t = xcd_block();
   if (t >= ta.ntiles) return;  // block-uniform
   const int lane = threadIdx.x;
@@ -565,13 +572,23 @@ __global__ void __launch_bounds__(BLOCK) k_rhs_lds(int N, int Np, int E, TileArg
   const int i = base + lane;
   const bool valid = i < N;
   const int h0 = ta.halo_off[t], nh = ta.halo_off[t + 1] - h0;
-  if (base + 4 * l64 < Np)
-    for (int a = wave; a < NPOP; a += 4) lds_dma16(pop + a * Np + base + 4 * l64, ps + a * S);
+  constexpr int PER = 16 / sizeof(real);  // values per lane and 16-byte load
+#pragma unroll
+  for (int c = 0; c < TILE / (64 * PER); ++c)
+    if (base + c * 64 * PER + PER * l64 < Np)
+      for (int a = wave; a < NPOP; a += 4)
+        lds_dma16(pop + a * Np + base + c * 64 * PER + PER * l64, ps + a * S + c * 64 * PER);
   const int hid0 = l64 < nh ? ta.halo[h0 + l64] : 0;
   const int hid1 = 64 + l64 < nh ? ta.halo[h0 + 64 + l64] : 0;
   for (int a = wave; a < NPOP; a += 4) {
-    if (l64 < nh) lds_dma4(pop + a * Np + hid0, ps + a * S + TILE);
-    if (64 + l64 < nh) lds_dma4(pop + a * Np + hid1, ps + a * S + TILE + 64);
+    if constexpr (sizeof(real) == 4) {
+      if (l64 < nh) lds_dma4(pop + a * Np + hid0, ps + a * S + TILE);
+      if (64 + l64 < nh) lds_dma4(pop + a * Np + hid1, ps + a * S + TILE + 64);
+    } else {
+      // 8-byte halo values go through registers (LDS DMA moves at most 4 bytes per gathered lane)
+      if (l64 < nh) ps[a * S + TILE + l64] = pop[a * Np + hid0];
+      if (64 + l64 < nh) ps[a * S + TILE + 64 + l64] = pop[a * Np + hid1];
+    }
   }
   if (valid) {
     Cs[lane] = Cn[i];
@@ -590,12 +607,12 @@ __global__ void __launch_bounds__(BLOCK) k_rhs_lds(int N, int Np, int E, TileArg
   __builtin_amdgcn_s_waitcnt(0);  // this wave's LDS DMA has landed
   __syncthreads();
   if (!valid) return;
-  float b[NPOP];
+  real b[NPOP];
 #pragma unroll
-  for (int a = 0; a < NPOP; ++a) b[a] = 0.0f;
+  for (int a = 0; a < NPOP; ++a) b[a] = (real)0;
   double bC = 0.0;
-  const float dt = (float)P.dt, c1 = dt / 3.0f, c2 = 0.5f * dt * dt;
-  const float drho_cs2 = (float)(CS2 * (P.rho_l - P.rho_v));
+  const real dt = (real)P.dt, c1 = dt / (real)3, c2 = (real)0.5 * dt * dt;
+  const real drho_cs2 = (real)(CS2 * (P.rho_l - P.rho_v));
   const int e0 = rt.ent_off[t], width = (rt.ent_off[t + 1] - e0) / TILE;
   for (int k = 0; k < width; ++k) {
     const int2 en = rt.ent[e0 + k * TILE + lane];
@@ -611,55 +628,55 @@ __global__ void __launch_bounds__(BLOCK) k_rhs_lds(int N, int Np, int E, TileArg
     const double2 ga = g2[0], gb = g2[1], gc = g2[2], gd = g2[3];
     const double Ad = ga.x;
     const double gxd[3] = {ga.y, gb.y, gc.y}, gyd[3] = {gb.x, gc.x, gd.x};
-    float gxf[3], gyf[3];
+    real gxf[3], gyf[3];
 #pragma unroll
     for (int v = 0; v < 3; ++v) {
-      gxf[v] = (float)gxd[v];
-      gyf[v] = (float)gyd[v];
+      gxf[v] = (real)gxd[v];
+      gyf[v] = (real)gyd[v];
     }
-    const float A = (float)Ad;
+    const real A = (real)Ad;
     // own vertex l and the two others (l + 1, l + 2) mod 3
-    const float gxl = l == 0 ? gxf[0] : (l == 1 ? gxf[1] : gxf[2]);
-    const float gyl = l == 0 ? gyf[0] : (l == 1 ? gyf[1] : gyf[2]);
-    const float gla = l == 0 ? gxf[1] : (l == 1 ? gxf[2] : gxf[0]);
-    const float hla = l == 0 ? gyf[1] : (l == 1 ? gyf[2] : gyf[0]);
-    const float glb = l == 0 ? gxf[2] : (l == 1 ? gxf[0] : gxf[1]);
-    const float hlb = l == 0 ? gyf[2] : (l == 1 ? gyf[0] : gyf[1]);
+    const real gxl = l == 0 ? gxf[0] : (l == 1 ? gxf[1] : gxf[2]);
+    const real gyl = l == 0 ? gyf[0] : (l == 1 ? gyf[1] : gyf[2]);
+    const real gla = l == 0 ? gxf[1] : (l == 1 ? gxf[2] : gxf[0]);
+    const real hla = l == 0 ? gyf[1] : (l == 1 ? gyf[2] : gyf[0]);
+    const real glb = l == 0 ? gxf[2] : (l == 1 ? gxf[0] : gxf[1]);
+    const real hlb = l == 0 ? gyf[2] : (l == 1 ? gyf[0] : gyf[1]);
     // barycentric values of the P1 fields and the element gradients
     const double Cb = (Cs[s0] + Cs[s1] + Cs[s2]) * (1.0 / 3.0);
     const double mub = (mus[s0] + mus[s1] + mus[s2]) * (1.0 / 3.0);
-    const float ux0 = uxs[s0], ux1 = uxs[s1], ux2 = uxs[s2];
-    const float uy0 = uys[s0], uy1 = uys[s1], uy2 = uys[s2];
-    const float ubx = (ux0 + ux1 + ux2) / 3.0f, uby = (uy0 + uy1 + uy2) / 3.0f;
+    const real ux0 = uxs[s0], ux1 = uxs[s1], ux2 = uxs[s2];
+    const real uy0 = uys[s0], uy1 = uys[s1], uy2 = uys[s2];
+    const real ubx = (ux0 + ux1 + ux2) / (real)3, uby = (uy0 + uy1 + uy2) / (real)3;
     const double rhobd = Cb * P.rho_l + (1.0 - Cb) * P.rho_v;
-    const float rhob = (float)rhobd;
+    const real rhob = (real)rhobd;
     const double gCx = rt.gC[e], gCy = rt.gC[E + e];
-    const float gpx = rt.gp[e], gpy = rt.gp[E + e];
-    const float ax = drho_cs2 * (float)gCx, ay = drho_cs2 * (float)gCy;  // c_s^2 grad rho
-    const float bx = (float)(mub * gCx), by = (float)(mub * gCy);        // mu grad C
-    const float coef = (float)Cb / (rhob * (float)CS2);
-    const float Xx = (float)gCx - coef * (gpx - bx), Xy = (float)gCy - coef * (gpy - by);
+    const real gpx = gp[e], gpy = gp[E + e];
+    const real ax = drho_cs2 * (real)gCx, ay = drho_cs2 * (real)gCy;  // c_s^2 grad rho
+    const real bx = (real)(mub * gCx), by = (real)(mub * gCy);        // mu grad C
+    const real coef = (real)Cb / (rhob * (real)CS2);
+    const real Xx = (real)gCx - coef * (gpx - bx), Xy = (real)gCy - coef * (gpy - by);
     const double lm = rt.lapmu[e];
-    const float d = (float)(P.mobility * lm);
-    const float uA = ubx * ax + uby * ay, uB = ubx * bx + uby * by, uX = ubx * Xx + uby * Xy;
-    const float uu = ubx * ubx + uby * uby;
+    const real d = (real)(P.mobility * lm);
+    const real uA = ubx * ax + uby * ay, uB = ubx * bx + uby * by, uX = ubx * Xx + uby * Xy;
+    const real uu = ubx * ubx + uby * uby;
     double divJ = 0.0, dPx = 0.0, dPy = 0.0;
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
-      const float exa = (float)ex(a), eya = (float)ey(a);
-      const float eu = exa * ubx + eya * uby;
-      const float G = (float)wq(a) * (1.0f + 3.0f * eu + 4.5f * eu * eu - 1.5f * uu);
-      const float Phig = (exa * ax + eya * ay - uA) * (G - (float)wq(a)) + (exa * bx + eya * by - uB) * G;
-      const float Phih = (exa * Xx + eya * Xy - uX + d) * G;
-      const float enl = exa * gxl + eya * gyl;
-      const float ena = exa * gla + eya * hla, enb = exa * glb + eya * hlb;
-      const float ha = ps[(Q + a) * S + sa], hb = ps[(Q + a) * S + sb], hl = ps[(Q + a) * S + lane];
-      const float sg = ps[a * S + lane] * enl + ps[a * S + sa] * ena + ps[a * S + sb] * enb;
-      const float sh = hl * enl + ha * ena + hb * enb;
-      const float wgt = A * (c1 + c2 * enl);
+      const real exa = (real)ex(a), eya = (real)ey(a);
+      const real eu = exa * ubx + eya * uby;
+      const real G = (real)wq(a) * ((real)1 + (real)3 * eu + (real)4.5 * eu * eu - (real)1.5 * uu);
+      const real Phig = (exa * ax + eya * ay - uA) * (G - (real)wq(a)) + (exa * bx + eya * by - uB) * G;
+      const real Phih = (exa * Xx + eya * Xy - uX + d) * G;
+      const real enl = exa * gxl + eya * gyl;
+      const real ena = exa * gla + eya * hla, enb = exa * glb + eya * hlb;
+      const real ha = ps[(Q + a) * S + sa], hb = ps[(Q + a) * S + sb], hl = ps[(Q + a) * S + lane];
+      const real sg = ps[a * S + lane] * enl + ps[a * S + sa] * ena + ps[a * S + sb] * enb;
+      const real sh = hl * enl + ha * ena + hb * enb;
+      const real wgt = A * (c1 + c2 * enl);
       b[a] += wgt * (Phig - sg);
       b[Q + a] += wgt * (Phih - sh);
-      if (a != 0) {
+      if (CONS && a != 0) {
         // FP64, vertex order 0, 1, 2 whichever vertex gathers (vertex l holds hl,
         // vertex l + 1 holds ha, vertex l + 2 holds hb)
         const double h0v = l == 0 ? hl : (l == 1 ? hb : ha);
@@ -672,21 +689,23 @@ __global__ void __launch_bounds__(BLOCK) k_rhs_lds(int N, int Np, int E, TileArg
         if (ey(a)) dPy += ey(a) * sa_d;
       }
     }
-    const double uxd = ((double)ux0 + (double)ux1 + (double)ux2) * (1.0 / 3.0);
-    const double uyd = ((double)uy0 + (double)uy1 + (double)uy2) * (1.0 / 3.0);
-    const double cf = Cb / (rhobd * CS2);
-    const double Xdx = gCx - cf * ((double)gpx - mub * gCx), Xdy = gCy - cf * ((double)gpy - mub * gCy);
-    const double Ml = P.mobility * lm;
-    const double s0m = Ml - divJ;
-    const double s1x = CS2 * Xdx + Ml * uxd - dPx, s1y = CS2 * Xdy + Ml * uyd - dPy;
-    const double gxl_d = l == 0 ? gxd[0] : (l == 1 ? gxd[1] : gxd[2]);
-    const double gyl_d = l == 0 ? gyd[0] : (l == 1 ? gyd[1] : gyd[2]);
-    bC += Ad * (P.dt * (1.0 / 3.0) * s0m + 0.5 * P.dt * P.dt * (gxl_d * s1x + gyl_d * s1y));
+    if (CONS) {
+      const double uxd = ((double)ux0 + (double)ux1 + (double)ux2) * (1.0 / 3.0);
+      const double uyd = ((double)uy0 + (double)uy1 + (double)uy2) * (1.0 / 3.0);
+      const double cf = Cb / (rhobd * CS2);
+      const double Xdx = gCx - cf * ((double)gpx - mub * gCx), Xdy = gCy - cf * ((double)gpy - mub * gCy);
+      const double Ml = P.mobility * lm;
+      const double s0m = Ml - divJ;
+      const double s1x = CS2 * Xdx + Ml * uxd - dPx, s1y = CS2 * Xdy + Ml * uyd - dPy;
+      const double gxl_d = l == 0 ? gxd[0] : (l == 1 ? gxd[1] : gxd[2]);
+      const double gyl_d = l == 0 ? gyd[0] : (l == 1 ? gyd[1] : gyd[2]);
+      bC += Ad * (P.dt * (1.0 / 3.0) * s0m + 0.5 * P.dt * P.dt * (gxl_d * s1x + gyl_d * s1y));
+    }
   }
-  const float inv_m = (float)(1.0 / mi);
+  const real inv_m = (real)(1.0 / mi);
 #pragma unroll
   for (int a = 0; a < NPOP; ++a) f[a * Np + i] = b[a] * inv_m;
-  fC[i] = bC / mi;
+  if (CONS) fC[i] = bC / mi;
 }
 
 // ----------------------------------------------------------------------------
