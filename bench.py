@@ -151,10 +151,16 @@ def main():
         import torch
         x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
+        y.copy_(x)
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
         for _ in range(10):
             y.copy_(x)
+        stop.record()
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30, "copies": 10}))
+        ms = start.elapsed_time(stop) / 10
+        print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30, "copies": 10,
+                          "ms_per_copy": round(ms, 4), "copy_GBps": round(2 * (1 << 30) / (ms * 1e-3) / 1e9, 1)}))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding of this path is "
