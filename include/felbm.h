@@ -74,13 +74,24 @@ enum { FELBM_FP64 = 0, FELBM_FP32 = 1 };
  *                  K = 0 is the lumped-mass solve.  Every sweep preserves
  *                  sum_i m_i x_i = sum_i b_i, hence mass.
  *   lambda_min/max bounds of the spectrum of diag(m)^-1 M11; 0/0 selects the
- *                  bounds [1/4, 1] that hold for every P1 triangle mesh.     */
+ *                  bounds [1/4, 1] that hold for every P1 triangle mesh.
+ *   kernels        FELBM_KERNELS_AUTO: the right-hand side and the sweeps run
+ *                  on LDS-staged 256-node tiles whenever every tile's halo
+ *                  has at most 128 nodes and every mass-matrix row at most 12
+ *                  off-diagonal entries (otherwise the global-gather kernels);
+ *                  FELBM_KERNELS_GLOBAL: always the global-gather kernels
+ *                  (same arithmetic, for meshes and tests that need them).
+ *   reserved_      set to 0.                                                 */
+enum { FELBM_KERNELS_AUTO = 0, FELBM_KERNELS_GLOBAL = 1 };
+
 typedef struct {
   double sigma, xi, mobility;
   double rho_l, rho_v, nu_l, nu_v, dt;
   int32_t precision;
   int32_t solver_sweeps;
   double lambda_min, lambda_max;
+  int32_t kernels;
+  int32_t reserved_;
 } felbm_params;
 
 /* Global FP64 reductions of the current state (Sec. III).

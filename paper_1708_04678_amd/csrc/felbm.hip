@@ -651,6 +651,10 @@ int felbm_create(const felbm_params* p, felbm_ctx** out) {
     g_create_error = "create: precision must be FELBM_FP64 or FELBM_FP32";
     return FELBM_EINVAL;
   }
+  if (p->kernels != FELBM_KERNELS_AUTO && p->kernels != FELBM_KERNELS_GLOBAL) {
+    g_create_error = "create: kernels must be FELBM_KERNELS_AUTO or FELBM_KERNELS_GLOBAL";
+    return FELBM_EINVAL;
+  }
   if (p->solver_sweeps < 0 || p->solver_sweeps > 256) {
     g_create_error = "create: solver_sweeps must be in [0, 256]";
     return FELBM_EINVAL;
@@ -810,7 +814,7 @@ int felbm_upload_mesh(felbm_ctx* c, int64_t n_nodes, const double* xy, int64_t n
     HIP_OK(c, hipStreamSynchronize(c->stream));
   }
   set_kernel_bytes(c);
-  TRY(build_tiles(c, m));
+  if (c->prm.kernels == FELBM_KERNELS_AUTO) TRY(build_tiles(c, m));
   std::vector<double> zeros(N, 0.0);
   TRY(upload(c, c->bc, zeros));
   HIP_OK(c, hipMemsetAsync(c->pop, 0, 18 * Np * rs, c->stream));

@@ -26,7 +26,8 @@ class Params(ct.Structure):
     _fields_ = [("sigma", ct.c_double), ("xi", ct.c_double), ("mobility", ct.c_double),
                 ("rho_l", ct.c_double), ("rho_v", ct.c_double), ("nu_l", ct.c_double), ("nu_v", ct.c_double),
                 ("dt", ct.c_double), ("precision", ct.c_int32), ("solver_sweeps", ct.c_int32),
-                ("lambda_min", ct.c_double), ("lambda_max", ct.c_double)]
+                ("lambda_min", ct.c_double), ("lambda_max", ct.c_double), ("kernels", ct.c_int32),
+                ("reserved_", ct.c_int32)]
 
 
 class Diag(ct.Structure):
@@ -135,11 +136,12 @@ class Context:
     """One FE-LBM simulation on the current HIP device (see include/felbm.h)."""
 
     def __init__(self, *, sigma, xi, mobility, rho_l, rho_v, nu_l, nu_v, dt, precision="fp64",
-                 solver_sweeps=28, lambda_min=0.0, lambda_max=0.0):
+                 solver_sweeps=28, lambda_min=0.0, lambda_max=0.0, kernels="auto"):
         lib = load_library()
         prec = {"fp64": FP64, "fp32": FP32}[precision] if isinstance(precision, str) else int(precision)
+        kern = {"auto": 0, "global": 1}[kernels] if isinstance(kernels, str) else int(kernels)
         self.params = Params(sigma, xi, mobility, rho_l, rho_v, nu_l, nu_v, dt, prec, int(solver_sweeps),
-                             lambda_min, lambda_max)
+                             lambda_min, lambda_max, kern, 0)
         h = _P()
         rc = lib.felbm_create(ct.byref(self.params), ct.byref(h))
         if rc != 0:
