@@ -42,6 +42,18 @@ sides of every parity test):
   R6  velocity is the literal first moment over c_s^2 rho (no half-force
       shift); the initial populations are the equilibria of (C, u, p).
   R7  solver: initial guess = lumped solve b/m; stop at ||r||_2 <= tol ||b||_2.
+
+The nodal-force scheme (the comparison column of the parasitic-current table,
+Sec. III.A; force_scheme="nodal") is not specified in the paper beyond
+"the same discretization scheme for the force terms" as for the populations:
+  N1  the forces are P1 fields, F_a(x) = N1(x)^T F_a, in the same streaming
+      step: the weak form becomes +(dt M11 + dt^2 K1_a) F_a with
+      K1_a = 1/2 int (e_a . grad N1) N1^T;
+  N2  nodal grad C, grad p, grad rho: area-weighted means of the element
+      gradients over the vertex patch (the lumped L2 projection of P0 onto P1);
+  N3  nodal lap mu: the vertex-patch operator of eqn:lapl_int_mp applied to
+      mu, with zero flux through wall edges (eqn:bc1);
+  N4  F at node i: eq:G and eq:H with the nodal values of the fields.
 """
 from __future__ import annotations
 
@@ -186,6 +198,22 @@ class Matrices:
         self.Ca = [E[a, 0] * self.C[0] + E[a, 1] * self.C[1] for a in range(Q)]
         self.Da = [sum(E[a, s] * E[a, r] * self.D[s][r] for s in (0, 1) for r in (0, 1)) for a in range(Q)]
         self.Ka = [E[a, 0] * self.K[0] + E[a, 1] * self.K[1] for a in range(Q)]
+        self._geo = geo
+        self.K1a = None
+
+    def nodal_force_matrices(self):
+        """K1_r = 1/2 int d_r N1 N1^T (reading N1), built on first use:
+        1/2 int_T d_r phi_i phi_j = (A/6) d_r N_i."""
+        if self.K1a is None:
+            geo = self._geo
+            tri, A, G = geo.tri, geo.area, geo.gradN
+            I = np.repeat(tri, 3, axis=1).ravel()
+            J = np.tile(tri, (1, 3)).ravel()
+            li = np.repeat(np.arange(3), 3)
+            self.K1 = [sp.csr_matrix((((A[:, None] / 6.0) * G[:, li, r]).ravel(), (I, J)), shape=(geo.N, geo.N))
+                       for r in (0, 1)]
+            self.K1a = [E[a, 0] * self.K1[0] + E[a, 1] * self.K1[1] for a in range(Q)]
+        return self.K1a
 
 
 # ---------------------------------------------------------------------------
@@ -307,22 +335,48 @@ def laplacian_mu(geo: Geometry, gradmu):
 # ---------------------------------------------------------------------------
 # Element (P0) forces, eq:G and eq:H at barycentric values (eq:intF, reading R5)
 # ---------------------------------------------------------------------------
-def element_forces(geo: Geometry, prm: Params, C, rho, u, mu, gradC, gradp, gradrho, lapmu):
-    Cb = C[geo.tri].mean(1)
-    rhob = rho[geo.tri].mean(1)
-    ub = u[geo.tri].mean(1)
-    mub = mu[geo.tri].mean(1)
-    Gu = gamma(ub)                                       # (NT, 9)
+def point_forces(prm: Params, C, rho, u, mu, gradC, gradp, gradrho, lapmu):
+    """eq:G and eq:H at a set of points given the values of C, rho, u, mu,
+    grad C, grad p, grad rho and lap mu there; (n, 9) each."""
+    Gu = gamma(u)                                        # (n, 9)
     G0 = W[None, :]
-    # (e_a - u) . X for a vector X per element
+    # (e_a - u) . X for a vector X per point
     def edot(X):
-        return (E[:, 0][None, :] - ub[:, 0, None]) * X[:, 0, None] + (E[:, 1][None, :] - ub[:, 1, None]) * X[:, 1, None]
+        return (E[:, 0][None, :] - u[:, 0, None]) * X[:, 0, None] + (E[:, 1][None, :] - u[:, 1, None]) * X[:, 1, None]
     # eq:G: (e - u) . [grad rho c_s^2 (Gamma(u) - Gamma(0)) + mu grad C Gamma(u)]
-    Phi_g = edot(gradrho) * CS2 * (Gu - G0) + edot(mub[:, None] * gradC) * Gu
+    Phi_g = edot(gradrho) * CS2 * (Gu - G0) + edot(mu[:, None] * gradC) * Gu
     # eq:H: (e - u) . [grad C - C/(rho c_s^2)(grad p - mu grad C)] Gamma(u) + M lap mu Gamma(u)
-    X = gradC - (Cb / (rhob * CS2))[:, None] * (gradp - mub[:, None] * gradC)
+    X = gradC - (C / (rho * CS2))[:, None] * (gradp - mu[:, None] * gradC)
     Phi_h = edot(X) * Gu + prm.mobility * lapmu[:, None] * Gu
     return Phi_g, Phi_h
+
+
+def element_forces(geo: Geometry, prm: Params, C, rho, u, mu, gradC, gradp, gradrho, lapmu):
+    """P0 forces: eq:G and eq:H at the barycentric values of the P1 fields with
+    the element gradients (reading R5), (NT, 9) each."""
+    return point_forces(prm, C[geo.tri].mean(1), rho[geo.tri].mean(1), u[geo.tri].mean(1), mu[geo.tri].mean(1),
+                        gradC, gradp, gradrho, lapmu)
+
+
+# ---------------------------------------------------------------------------
+# Nodal (P1) forces, the comparison scheme of the parasitic-current table
+# (readings N1-N4)
+# ---------------------------------------------------------------------------
+def nodal_average(geo: Geometry, elem_vec):
+    """Area-weighted mean over each vertex patch of an element (P0) field
+    (reading N2), (N, ...)."""
+    shape = (-1,) + (1,) * (elem_vec.ndim - 1)
+    acc = np.zeros((geo.N,) + elem_vec.shape[1:], dtype=elem_vec.dtype)
+    weighted = geo.area.reshape(shape) * elem_vec
+    for l in range(3):
+        np.add.at(acc, geo.tri[:, l], weighted)
+    return acc / geo.patch_volume.reshape(shape)
+
+
+def nodal_laplacian_mu(geo: Geometry, mu, gradmu):
+    """Vertex-patch Laplacian of mu (eqn:lapl_int_mp) with zero flux through
+    wall edges (eqn:bc1) (reading N3), (N,)."""
+    return laplacian_C(geo, mu, gradmu, np.zeros(geo.N))
 
 
 # ---------------------------------------------------------------------------
@@ -334,6 +388,18 @@ def rhs(mat: Matrices, dt, psi_hat, Phi):
     for a in range(Q):
         b = -dt * (mat.Ca[a] @ psi_hat[:, a]) - dt * dt * (mat.Da[a] @ psi_hat[:, a])
         b = b + dt * (mat.M10 @ Phi[:, a]) + dt * dt * (mat.Ka[a] @ Phi[:, a])
+        cols.append(b)
+    return np.stack(cols, axis=1)
+
+
+def rhs_nodal(mat: Matrices, dt, psi_hat, F):
+    """b_a = (-dt C_a - dt^2 D_a) psi_hat_a + (dt M11 + dt^2 K1_a) F_a with the
+    force a P1 field (reading N1), (N, 9)."""
+    K1a = mat.nodal_force_matrices()
+    cols = []
+    for a in range(Q):
+        b = -dt * (mat.Ca[a] @ psi_hat[:, a]) - dt * dt * (mat.Da[a] @ psi_hat[:, a])
+        b = b + dt * (mat.M11 @ F[:, a]) + dt * dt * (K1a[a] @ F[:, a])
         cols.append(b)
     return np.stack(cols, axis=1)
 
@@ -374,7 +440,10 @@ def pcg(M, m, b, tol=1e-13, max_it=100):
 # The model: state = (g, h), each (N, 9), in the "bar" variables of eqn::new_variable
 # ---------------------------------------------------------------------------
 class Oracle:
-    def __init__(self, mesh, phys, omega_c, tol=1e-13):
+    def __init__(self, mesh, phys, omega_c, tol=1e-13, force_scheme="mixed"):
+        if force_scheme not in ("mixed", "nodal"):
+            raise ValueError("force_scheme is 'mixed' (P0 element forces) or 'nodal' (P1 nodal forces)")
+        self.force_scheme = force_scheme
         self.geo = Geometry(mesh)
         self.mat = Matrices(self.geo)
         self.prm = Params.from_physics(phys.sigma, phys.xi, phys.mobility, phys.rho_l, phys.rho_v,
@@ -415,21 +484,33 @@ class Oracle:
         lapmu = laplacian_mu(geo, gradmu)
         gradp = element_gradient(geo, p)
         gradrho = element_gradient(geo, rho)
-        Phi_g, Phi_h = element_forces(geo, prm, C, rho, u, mu, gradC, gradp, gradrho, lapmu)
-        return dict(C=C, p=p, rho=rho, u=u, gradC=gradC, lapC=lapC, mu=mu, gradmu=gradmu, lapmu=lapmu,
-                    gradp=gradp, gradrho=gradrho, Phi_g=Phi_g, Phi_h=Phi_h, tau=relaxation_time(C, prm))
+        out = dict(C=C, p=p, rho=rho, u=u, gradC=gradC, lapC=lapC, mu=mu, gradmu=gradmu, lapmu=lapmu,
+                   gradp=gradp, gradrho=gradrho, tau=relaxation_time(C, prm))
+        if self.force_scheme == "mixed":
+            out["Phi_g"], out["Phi_h"] = element_forces(geo, prm, C, rho, u, mu, gradC, gradp, gradrho, lapmu)
+        else:
+            gradC_n, gradp_n, gradrho_n = (nodal_average(geo, x) for x in (gradC, gradp, gradrho))
+            lapmu_n = nodal_laplacian_mu(geo, mu, gradmu)
+            out.update(gradC_n=gradC_n, gradp_n=gradp_n, gradrho_n=gradrho_n, lapmu_n=lapmu_n)
+            out["F_g"], out["F_h"] = point_forces(prm, C, rho, u, mu, gradC_n, gradp_n, gradrho_n, lapmu_n)
+        return out
 
     def step(self, g, h, return_fields=False):
         """One time step: collision (eqn::collide) then Galerkin streaming
-        with the element force (eqn::stream, eq:galerkin_lbm), the mass
-        matrix solve and the wall operator."""
+        with the element force (eqn::stream, eq:galerkin_lbm; the nodal force
+        of readings N1-N4 for force_scheme="nodal"), the mass matrix solve and
+        the wall operator."""
         f = self.fields(g, h)
         g_eq, h_eq = equilibria(f["C"], f["p"], f["rho"], f["u"])
         g_hat = collide(g, g_eq, f["tau"])
         h_hat = collide(h, h_eq, f["tau"])
         dt = self.prm.dt
-        b_g = rhs(self.mat, dt, g_hat, f["Phi_g"])
-        b_h = rhs(self.mat, dt, h_hat, f["Phi_h"])
+        if self.force_scheme == "mixed":
+            b_g = rhs(self.mat, dt, g_hat, f["Phi_g"])
+            b_h = rhs(self.mat, dt, h_hat, f["Phi_h"])
+        else:
+            b_g = rhs_nodal(self.mat, dt, g_hat, f["F_g"])
+            b_h = rhs_nodal(self.mat, dt, h_hat, f["F_h"])
         d_g = np.empty_like(b_g)
         d_h = np.empty_like(b_h)
         its = 0

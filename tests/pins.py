@@ -484,3 +484,111 @@ def shear_wave_viscosity_ratio(tau=2.0, n_steps=600) -> float:
     a2 = amp(g, h)
     rate = np.log(a1 / a2) / (n_steps * dt)
     return float(rate / (phys.nu_l * k * k))
+
+
+# ---------------------------------------------------------------------------
+# Nodal-force comparison scheme (readings N1-N4 of the oracle)
+# ---------------------------------------------------------------------------
+def nodal_force_matrix_error() -> float:
+    """K1_r = 1/2 int d_r phi_i phi_j against midpoint quadrature with the
+    shape functions from a barycentric solve (the brute force of
+    bruteforce_matrices), on the four-element mesh and a jittered periodic mesh."""
+    errs = []
+    for mesh in (four_element_mesh(), small_mesh(nx=6, ny=4)):
+        N = mesh.n_nodes
+        K1 = np.zeros((2, N, N))
+        for vs in mesh.tri:
+            P = mesh.xy[vs].copy()
+            if mesh.period_x > 0:
+                P[:, 0] -= mesh.period_x * np.round((P[:, 0] - P[0, 0]) / mesh.period_x)
+            area = 0.5 * abs(np.linalg.det(np.vstack([P.T, np.ones(3)])))
+            eps = 1e-6
+            grads = np.zeros((3, 2))
+            c = P.mean(0)
+            for r in range(2):
+                dx = np.zeros(2); dx[r] = eps
+                grads[:, r] = (_bary(P, c + dx) - _bary(P, c - dx)) / (2 * eps)
+            for q in ((P[0] + P[1]) / 2, (P[1] + P[2]) / 2, (P[2] + P[0]) / 2):
+                lam = _bary(P, q)
+                for a in range(3):
+                    for b in range(3):
+                        for r in range(2):
+                            K1[r, vs[a], vs[b]] += 0.5 * (area / 3.0) * grads[a, r] * lam[b]
+        mat = fo.Matrices(fo.Geometry(mesh))
+        K1a = mat.nodal_force_matrices()
+        errs += [abs(mat.K1[r].toarray() - K1[r]).max() for r in range(2)]
+        errs += [abs(K1a[a].toarray() - (fo.E[a, 0] * K1[0] + fo.E[a, 1] * K1[1])).max() for a in range(9)]
+    return float(max(errs))
+
+
+def nodal_average_error() -> float:
+    """The area-weighted patch mean of the element centroids' coordinates is
+    the centroid of the vertex patch, int_patch x / |patch|, integrated here by
+    midpoint quadrature triangle by triangle (exact for linear integrands)."""
+    mesh = small_mesh()
+    geo = fo.Geometry(mesh)
+    got = fo.nodal_average(geo, geo.centroid)
+    num = np.zeros((geo.N, 2)); den = np.zeros(geo.N)
+    for t, vs in enumerate(mesh.tri):
+        P = geo.p[t]
+        area = 0.5 * abs(np.linalg.det(np.vstack([P.T, np.ones(3)])))
+        mids = ((P[0] + P[1]) / 2, (P[1] + P[2]) / 2, (P[2] + P[0]) / 2)
+        integral = sum(m for m in mids) * area / 3.0
+        for v in vs:
+            num[v] += integral; den[v] += area
+    # compare in the frame of each node (the unwrapped triangle coordinates of
+    # a periodic patch can differ by one period from node to node)
+    diff = got - num / den[:, None]
+    diff[:, 0] -= mesh.period_x * np.round(diff[:, 0] / mesh.period_x)
+    return float(abs(diff).max())
+
+
+def nodal_static_drift(seed=3) -> float:
+    """The static interface of Sec. II.C with nodal (P1) forces: the paper's
+    argument is that only the piecewise-constant force balances the streaming
+    of a static profile, so the nodal scheme moves the populations.  Returns
+    the relative one-step change (compare static_balance_drift)."""
+    mesh = small_mesh(seed=seed)
+    phys = make_physics(sigma=0.0, m_rho=10, m_nu=1, dt=0.1, mobility=0.0)
+    o = fo.Oracle(mesh, phys, np.zeros(mesh.n_nodes), force_scheme="nodal")
+    rng = np.random.default_rng(seed)
+    C = rng.uniform(0.0, 1.0, mesh.n_nodes)
+    g, h = o.init_state(C)
+    g1, h1 = o.step(g, h)
+    return float(max(abs(h1 - h).max(), abs(g1 - g).max()) / abs(h).max())
+
+
+def nodal_force_moments_error() -> float:
+    """Moments of the nodal forces from sum Gamma = 1, sum (e - u) Gamma = 0:
+    sum_a F_h = M lap mu_n, sum_a F_g = c_s^2 u . grad rho_n, and at u = 0
+    sum_a e F_g = c_s^2 mu grad C_n (nodal values, reading N4)."""
+    mesh = small_mesh()
+    phys = make_physics(sigma=0.01, m_rho=10, m_nu=1, dt=0.1)
+    from workloads import droplet_field
+    o = fo.Oracle(mesh, phys, np.zeros(mesh.n_nodes), force_scheme="nodal")
+    rng = np.random.default_rng(9)
+    C = droplet_field(mesh, [(8.0, 2.0, 4.0)], phys.xi)
+    u = rng.normal(0, 0.02, (mesh.n_nodes, 2))
+    g, h = o.init_state(C, u=u, p=rng.normal(0, 1e-3, mesh.n_nodes))
+    f = o.fields(g, h)
+    e1 = abs(f["F_h"].sum(1) - o.prm.mobility * f["lapmu_n"]).max()
+    e2 = abs(f["F_g"].sum(1) - fo.CS2 * (f["u"] * f["gradrho_n"]).sum(1)).max()
+    g0, h0 = o.init_state(C)
+    f0 = o.fields(g0, h0)
+    first = np.stack([f0["F_g"] @ fo.E[:, 0], f0["F_g"] @ fo.E[:, 1]], 1)
+    e3 = abs(first - fo.CS2 * f0["mu"][:, None] * f0["gradC_n"]).max()
+    return float(max(e1, e2, e3))
+
+
+def nodal_mass_drift(steps=20) -> float:
+    """Total composition with nodal forces and a wetting wall: the P1 force
+    enters through int phi_i F and its weighted sum over nodes telescopes like
+    the P0 one, so mass is conserved to the solver tolerance."""
+    mesh = small_mesh()
+    phys = make_physics(sigma=0.01, m_rho=10, m_nu=1, dt=0.1)
+    from workloads import droplet_field, wetting_from_angles
+    o = fo.Oracle(mesh, phys, wetting_from_angles(mesh, 60.0, 110.0), force_scheme="nodal")
+    g, h = o.init_state(droplet_field(mesh, [(8.0, 0.0, 4.0)], phys.xi))
+    m0 = o.mass(h)
+    g, h = o.run(g, h, steps)
+    return float(abs(o.mass(h) - m0) / m0)

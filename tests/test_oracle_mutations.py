@@ -94,6 +94,36 @@ def equilibria_wrong_weight(C, p, rho, u):
     return g, h * (1.0 + 0.01 * (np.arange(fo.Q) == 5))
 
 
+def nodal_matrices_factor(self):
+    # 1/2 int d_r phi_i phi_j taken as (A/3) d_r N_i instead of (A/6) d_r N_i
+    geo = self._geo
+    tri, A, G = geo.tri, geo.area, geo.gradN
+    I = np.repeat(tri, 3, axis=1).ravel()
+    J = np.tile(tri, (1, 3)).ravel()
+    li = np.repeat(np.arange(3), 3)
+    import scipy.sparse as sp
+    self.K1 = [sp.csr_matrix((((A[:, None] / 3.0) * G[:, li, r]).ravel(), (I, J)), shape=(geo.N, geo.N))
+               for r in (0, 1)]
+    self.K1a = [fo.E[a, 0] * self.K1[0] + fo.E[a, 1] * self.K1[1] for a in range(fo.Q)]
+    return self.K1a
+
+
+def nodal_average_unweighted(geo, elem_vec):
+    acc = np.zeros((geo.N,) + elem_vec.shape[1:])
+    cnt = np.zeros(geo.N)
+    for l in range(3):
+        np.add.at(acc, geo.tri[:, l], elem_vec)
+        np.add.at(cnt, geo.tri[:, l], 1.0)
+    return acc / cnt.reshape((-1,) + (1,) * (elem_vec.ndim - 1))
+
+
+_point = fo.point_forces
+
+
+def point_forces_no_mobility(prm, C, rho, u, mu, gradC, gradp, gradrho, lapmu):
+    return _point(prm, C, rho, u, mu, gradC, gradp, gradrho, 0 * lapmu)
+
+
 MUTATIONS = [
     ("printed M10 sign", "rhs", rhs_printed_sign, lambda: pins.static_balance_drift() > 1e-8),
     ("dropped D term", "rhs", rhs_no_D, lambda: pins.advection_error() > 0.05),
@@ -111,12 +141,18 @@ MUTATIONS = [
      lambda: not (0.98 < pins.shear_wave_viscosity_ratio(n_steps=300) < 1.08)),
     ("no wall operator", "wall_operator", no_wall_operator, lambda: pins.wall_velocity_after_step() > 1e-6),
     ("wrong equilibrium weight", "equilibria", equilibria_wrong_weight, lambda: pins.lattice_identities_error() > 1e-6),
+    ("nodal force matrix factor", "Matrices.nodal_force_matrices", nodal_matrices_factor,
+     lambda: pins.nodal_force_matrix_error() > 1e-3),
+    ("unweighted nodal average", "nodal_average", nodal_average_unweighted, lambda: pins.nodal_average_error() > 1e-6),
+    ("nodal forces without mobility", "point_forces", point_forces_no_mobility,
+     lambda: pins.nodal_force_moments_error() > 1e-8),
 ]
 
 
 @pytest.mark.parametrize("name,attr,fn,caught", MUTATIONS, ids=[m[0] for m in MUTATIONS])
 def test_pin_catches_planted_mistake(monkeypatch, name, attr, fn, caught):
-    monkeypatch.setattr(fo, attr, fn)
+    owner, _, leaf = attr.rpartition(".")
+    monkeypatch.setattr(getattr(fo, owner) if owner else fo, leaf, fn)
     assert caught(), f"no pin caught the planted mistake: {name}"
 
 

@@ -109,3 +109,25 @@ def test_viscosity_from_relaxation_time():
 
 def test_complex_step_tangent_matches_fd():
     assert pins.complex_step_vs_fd() < 1e-6
+
+
+def test_nodal_force_matrix_matches_bruteforce():
+    assert pins.nodal_force_matrix_error() < 1e-8
+
+
+def test_nodal_average_is_patch_centroid():
+    assert pins.nodal_average_error() < 1e-12
+
+
+def test_nodal_forces_do_not_balance_static_interface():
+    # the mixed scheme keeps this state to rounding (test_static_interface_balance);
+    # the nodal one moves it, which is the mechanism behind the parasitic-current table
+    assert pins.nodal_static_drift() > 1e-4
+
+
+def test_nodal_force_moments():
+    assert pins.nodal_force_moments_error() < 1e-14
+
+
+def test_nodal_scheme_conserves_mass():
+    assert pins.nodal_mass_drift() < 1e-12
