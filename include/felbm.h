@@ -81,8 +81,15 @@ enum { FELBM_FP64 = 0, FELBM_FP32 = 1 };
  *                  off-diagonal entries (otherwise the global-gather kernels);
  *                  FELBM_KERNELS_GLOBAL: always the global-gather kernels
  *                  (same arithmetic, for meshes and tests that need them).
- *   reserved_      set to 0.                                                 */
+ *   force_scheme   FELBM_FORCES_MIXED: the paper's scheme, forces constant per
+ *                  element at the barycentric field values (Sec. II.C,
+ *                  eq:intF).  FELBM_FORCES_NODAL: the comparison scheme of the
+ *                  parasitic-current table (Sec. III.A), forces as P1 fields
+ *                  from nodal values and area-weighted nodal gradients, nodal
+ *                  lap mu by the vertex-patch operator with zero wall flux;
+ *                  FP64 only, no adjoint.                                    */
 enum { FELBM_KERNELS_AUTO = 0, FELBM_KERNELS_GLOBAL = 1 };
+enum { FELBM_FORCES_MIXED = 0, FELBM_FORCES_NODAL = 1 };
 
 typedef struct {
   double sigma, xi, mobility;
@@ -91,7 +98,7 @@ typedef struct {
   int32_t solver_sweeps;
   double lambda_min, lambda_max;
   int32_t kernels;
-  int32_t reserved_;
+  int32_t force_scheme;
 } felbm_params;
 
 /* Global FP64 reductions of the current state (Sec. III).

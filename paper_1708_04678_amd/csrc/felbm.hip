@@ -21,11 +21,11 @@ using namespace felbm;
 namespace {
 
 enum KernelId {
-  K_MOMENTS = 0, K_REDUCE, K_GRAD, K_EFLUX, K_LAPC, K_GRADMU, K_LAPMU, K_RHS, K_SWEEP_FIRST, K_SWEEP_MID, K_SWEEP_LAST,
-  K_ADJ_PREP, K_ADJ_FORCE, K_ADJ_STREAM, K_ADJ_GMU, K_ADJ_MU, K_ADJ_GC, K_ADJ_NODE, K_COUNT
+  K_MOMENTS = 0, K_REDUCE, K_GRAD, K_EFLUX, K_LAPC, K_GRADMU, K_LAPMU, K_NODEF, K_RHS, K_SWEEP_FIRST, K_SWEEP_MID,
+  K_SWEEP_LAST, K_ADJ_PREP, K_ADJ_FORCE, K_ADJ_STREAM, K_ADJ_GMU, K_ADJ_MU, K_ADJ_GC, K_ADJ_NODE, K_COUNT
 };
 const char* const kKernelNames[K_COUNT] = {"moments_collide", "reduce_final", "elem_grad", "edge_flux", "lapC_mu",
-                                           "elem_gradmu", "elem_lapmu", "rhs_gather", "sweep_first",
+                                           "elem_gradmu", "elem_lapmu", "node_forces", "rhs_gather", "sweep_first",
                                            "sweep_mid", "sweep_last", "adj_prep", "adj_force", "adj_stream",
                                            "adj_gmu", "adj_mu", "adj_gC", "adj_node"};
 
@@ -76,6 +76,7 @@ struct felbm_ctx {
   int32_t *sell_ptr = nullptr, *sell_col = nullptr;
   double *geo = nullptr, *wall_len = nullptr, *bc = nullptr, *mass = nullptr, *xy = nullptr;
   double *pvol = nullptr, *eflux = nullptr;  // patch volume per node; edge fluxes [3][E]
+  void* Fn = nullptr;                         // nodal forces [18][Np] (nodal force scheme)
   void *geor = nullptr, *sell_val = nullptr;
   uint8_t* is_wall = nullptr;
   // state and work buffers (device)
@@ -259,6 +260,11 @@ int enqueue_fields(felbm_ctx* c, bool collide, bool record, DiagRecord* rec_targ
              (const double*)c->wall_len, c->sp, c->lapC, c->mu));
   TRY(launch(c, K_GRADMU, k_elem_gradmu, gE, E, (const int*)c->tri, (const double*)c->geo, (const double*)c->mu,
              c->gmu));
+  if (c->prm.force_scheme == FELBM_FORCES_NODAL)
+    return launch(c, K_NODEF, k_node_forces<real>, gN, N, Np, E, (const int*)c->n2e_ptr, (const int*)c->n2e,
+                  (const int*)c->enbr, (const double*)c->geo, (const double*)c->pvol, (const double*)c->gC,
+                  (const real*)c->gp, (const double*)c->gmu, (const double*)c->Cn, (const real*)c->uxn,
+                  (const real*)c->uyn, (const double*)c->mu, c->sp, (real*)c->Fn);
   TRY(launch(c, K_LAPMU, k_elem_lapmu, gE, E, (const int*)c->enbr, (const double*)c->geo, (const double*)c->gmu,
              c->lapmu));
   return FELBM_OK;
@@ -268,6 +274,10 @@ template <typename real>
 int enqueue_rhs(felbm_ctx* c) {
   const int gN = grid_for(c->N);
   const int N = (int)c->N, Np = (int)c->Np, E = (int)c->E;
+  if (c->prm.force_scheme == FELBM_FORCES_NODAL)
+    return launch(c, K_RHS, k_rhs_nodal<real>, gN, N, Np, E, (const int*)c->n2e_ptr, (const int*)c->n2e,
+                  (const int*)c->tri, (const double*)c->geo, (const real*)c->Fn, (const real*)c->pop,
+                  (const double*)c->mass, c->sp, (real*)c->f);
   if (c->use_rhs_lds) {
     TileArgs ta{c->tile_off, c->tslot, c->halo_off, c->halo, c->ntiles, c->tile_slots};
     const int grid = (c->ntiles + 7) / 8 * 8;
@@ -655,6 +665,14 @@ int felbm_create(const felbm_params* p, felbm_ctx** out) {
     g_create_error = "create: kernels must be FELBM_KERNELS_AUTO or FELBM_KERNELS_GLOBAL";
     return FELBM_EINVAL;
   }
+  if (p->force_scheme != FELBM_FORCES_MIXED && p->force_scheme != FELBM_FORCES_NODAL) {
+    g_create_error = "create: force_scheme must be FELBM_FORCES_MIXED or FELBM_FORCES_NODAL";
+    return FELBM_EINVAL;
+  }
+  if (p->force_scheme == FELBM_FORCES_NODAL && p->precision != FELBM_FP64) {
+    g_create_error = "create: the nodal force scheme is available in FP64 only";
+    return FELBM_EINVAL;
+  }
   if (p->solver_sweeps < 0 || p->solver_sweeps > 256) {
     g_create_error = "create: solver_sweeps must be in [0, 256]";
     return FELBM_EINVAL;
@@ -741,6 +759,7 @@ int felbm_upload_mesh(felbm_ctx* c, int64_t n_nodes, const double* xy, int64_t n
   TRY(dalloc(c, &c->gmu, 2 * E));
   TRY(dalloc(c, &c->lapmu, E));
   TRY(dalloc_bytes(c, &c->gp, 2 * E * rs));
+  if (c->prm.force_scheme == FELBM_FORCES_NODAL) TRY(dalloc_bytes(c, &c->Fn, 18 * Np * rs));
   if (c->prm.precision == FELBM_FP32) {
     TRY(dalloc(c, &c->rC, Np));
     TRY(dalloc(c, &c->fC, Np));
@@ -1135,6 +1154,8 @@ int felbm_forward_ckpt(felbm_ctx* c, int64_t n_steps, int64_t every) {
   if (!c) return FELBM_EINVAL;
   if (!c->has_state) return fail(c, FELBM_ESTATE, "forward_ckpt: not initialised");
   if (n_steps < 1 || every < 1) return fail(c, FELBM_EINVAL, "forward_ckpt: n_steps and every must be >= 1");
+  if (c->prm.force_scheme != FELBM_FORCES_MIXED)
+    return fail(c, FELBM_EINVAL, "forward_ckpt: the adjoint covers the mixed force scheme only");
   TRY(ensure_adjoint_buffers(c));
   const size_t sb = dev_state_bytes(c);
   const int64_t nck = (n_steps + every - 1) / every;

@@ -480,6 +480,112 @@ __global__ void __launch_bounds__(BLOCK) k_rhs(int N, int Np, int E, const int* 
 }
 
 // ----------------------------------------------------------------------------
+// Nodal (P1) forces, the comparison scheme of the parasitic-current table
+// (Sec. III.A), which the paper names but does not spell out.  Reading: the
+// same eq:G / eq:H, evaluated at the nodes with nodal values of the fields
+// and with nodal gradients (area-weighted means of the element gradients over
+// the vertex patch), nodal lap mu from the vertex-patch operator of
+// eqn:lapl_int_mp with zero flux through wall edges (eqn:bc1); the force then
+// enters the streaming step as a P1 field: + dt int phi_i F
+// + dt^2/2 int (e . grad phi_i) F.  FP64.
+// ----------------------------------------------------------------------------
+template <typename real>
+__global__ void __launch_bounds__(BLOCK) k_node_forces(int N, int Np, int E, const int* __restrict__ n2e_ptr,
+                                                      const int* __restrict__ n2e, const int* __restrict__ enbr,
+                                                      const double* __restrict__ geo, const double* __restrict__ pvol,
+                                                      const double* __restrict__ gC, const real* __restrict__ gp,
+                                                      const double* __restrict__ gmu, const double* __restrict__ Cn,
+                                                      const real* __restrict__ uxn, const real* __restrict__ uyn,
+                                                      const double* __restrict__ mu, StepParams P,
+                                                      real* __restrict__ Fn) {
+  const int i = xcd_block() * BLOCK + threadIdx.x;
+  if (i >= N) return;
+  double sCx = 0.0, sCy = 0.0, spx = 0.0, spy = 0.0, flux = 0.0;
+  for (int q = n2e_ptr[i]; q < n2e_ptr[i + 1]; ++q) {
+    const int packed = n2e[q];
+    const int e = packed >> 2, l = packed & 3;
+    const double A = geo[e];
+    sCx += A * gC[e];
+    sCy += A * gC[E + e];
+    spx += A * (double)gp[e];
+    spy += A * (double)gp[E + e];
+    const int nb = enbr[l * E + e];
+    if (nb >= 0) {
+      const double Gx = 0.5 * (gmu[e] + gmu[nb]), Gy = 0.5 * (gmu[E + e] + gmu[E + nb]);
+      flux += -2.0 * A * (geo[(1 + 2 * l) * E + e] * Gx + geo[(2 + 2 * l) * E + e] * Gy);
+    }
+  }
+  const double vol = pvol[i];
+  const double gCx = sCx / vol, gCy = sCy / vol, gpx = spx / vol, gpy = spy / vol, lm = flux / vol;
+  const double C = Cn[i], m = mu[i];
+  const double rho = C * P.rho_l + (1.0 - C) * P.rho_v;
+  const double ux = (double)uxn[i], uy = (double)uyn[i];
+  const double drho = P.rho_l - P.rho_v;
+  const double ax = CS2 * drho * gCx, ay = CS2 * drho * gCy;  // c_s^2 grad rho
+  const double bx = m * gCx, by = m * gCy;                    // mu grad C
+  const double cf = C / (rho * CS2);
+  const double Xx = gCx - cf * (gpx - bx), Xy = gCy - cf * (gpy - by);
+  const double d = P.mobility * lm;
+  const double uu = ux * ux + uy * uy;
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const double eu = ex(a) * ux + ey(a) * uy;
+    const double G = wq(a) * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+    const double Fg = ((ex(a) - ux) * ax + (ey(a) - uy) * ay) * (G - wq(a)) + ((ex(a) - ux) * bx + (ey(a) - uy) * by) * G;
+    const double Fh = ((ex(a) - ux) * Xx + (ey(a) - uy) * Xy + d) * G;
+    Fn[a * Np + i] = (real)Fg;
+    Fn[(Q + a) * Np + i] = (real)Fh;
+  }
+}
+
+// Galerkin right-hand side with the P1 force: per incident element,
+//   b_{a,i} += -A (dt/3 + dt^2/2 e_a . grad N_i) e_a . sum_v psi_hat_{a,v} grad N_v
+//            + dt A/12 (F_{a,i} + sum_v F_{a,v}) + dt^2/2 (e_a . grad N_i) A/3 sum_v F_{a,v}
+// (the consistent P1 mass and 1/2 int (e . grad phi_i) phi_j); f = b / m.
+template <typename real>
+__global__ void __launch_bounds__(BLOCK) k_rhs_nodal(int N, int Np, int E, const int* __restrict__ n2e_ptr,
+                                                    const int* __restrict__ n2e, const int* __restrict__ tri,
+                                                    const double* __restrict__ geo, const real* __restrict__ Fn,
+                                                    const real* __restrict__ pop, const double* __restrict__ mass,
+                                                    StepParams P, real* __restrict__ f) {
+  const int i = xcd_block() * BLOCK + threadIdx.x;
+  if (i >= N) return;
+  real b[NPOP];
+#pragma unroll
+  for (int a = 0; a < NPOP; ++a) b[a] = (real)0;
+  const real dt = (real)P.dt, c1 = dt / (real)3, c2 = (real)0.5 * dt * dt;
+  for (int q = n2e_ptr[i]; q < n2e_ptr[i + 1]; ++q) {
+    const int packed = n2e[q];
+    const int e = packed >> 2, l = packed & 3;
+    const int v0 = tri[e], v1 = tri[E + e], v2 = tri[2 * E + e];
+    const real A = (real)geo[e];
+    real gx[3], gy[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      gx[t] = (real)geo[(1 + 2 * t) * E + e];
+      gy[t] = (real)geo[(2 + 2 * t) * E + e];
+    }
+    const real gxl = l == 0 ? gx[0] : (l == 1 ? gx[1] : gx[2]);
+    const real gyl = l == 0 ? gy[0] : (l == 1 ? gy[1] : gy[2]);
+#pragma unroll
+    for (int a = 0; a < NPOP; ++a) {
+      const int d = a < Q ? a : a - Q;
+      const real exa = (real)ex(d), eya = (real)ey(d);
+      const real s = pop[a * Np + v0] * (exa * gx[0] + eya * gy[0]) + pop[a * Np + v1] * (exa * gx[1] + eya * gy[1]) +
+                     pop[a * Np + v2] * (exa * gx[2] + eya * gy[2]);
+      const real enl = exa * gxl + eya * gyl;
+      const real F0 = Fn[a * Np + v0], F1 = Fn[a * Np + v1], F2 = Fn[a * Np + v2];
+      const real Fi = Fn[a * Np + i];
+      const real fsum = F0 + F1 + F2;
+      b[a] += -A * (c1 + c2 * enl) * s + dt * (A / (real)12) * (Fi + fsum) + c2 * enl * (A / (real)3) * fsum;
+    }
+  }
+  const real inv_m = (real)(1.0 / mass[i]);
+#pragma unroll
+  for (int a = 0; a < NPOP; ++a) f[a * Np + i] = b[a] * inv_m;
+}
+
+// ----------------------------------------------------------------------------
 // Tiles of 256 consecutive (internal-order) nodes, their halo lists and LDS
 // slots, shared by the LDS-staged right-hand side and solve sweeps.
 // ----------------------------------------------------------------------------

@@ -27,7 +27,7 @@ class Params(ct.Structure):
                 ("rho_l", ct.c_double), ("rho_v", ct.c_double), ("nu_l", ct.c_double), ("nu_v", ct.c_double),
                 ("dt", ct.c_double), ("precision", ct.c_int32), ("solver_sweeps", ct.c_int32),
                 ("lambda_min", ct.c_double), ("lambda_max", ct.c_double), ("kernels", ct.c_int32),
-                ("reserved_", ct.c_int32)]
+                ("force_scheme", ct.c_int32)]
 
 
 class Diag(ct.Structure):
@@ -136,12 +136,13 @@ class Context:
     """One FE-LBM simulation on the current HIP device (see include/felbm.h)."""
 
     def __init__(self, *, sigma, xi, mobility, rho_l, rho_v, nu_l, nu_v, dt, precision="fp64",
-                 solver_sweeps=28, lambda_min=0.0, lambda_max=0.0, kernels="auto"):
+                 solver_sweeps=28, lambda_min=0.0, lambda_max=0.0, kernels="auto", force_scheme="mixed"):
         lib = load_library()
         prec = {"fp64": FP64, "fp32": FP32}[precision] if isinstance(precision, str) else int(precision)
         kern = {"auto": 0, "global": 1}[kernels] if isinstance(kernels, str) else int(kernels)
+        forces = {"mixed": 0, "nodal": 1}[force_scheme] if isinstance(force_scheme, str) else int(force_scheme)
         self.params = Params(sigma, xi, mobility, rho_l, rho_v, nu_l, nu_v, dt, prec, int(solver_sweeps),
-                             lambda_min, lambda_max, kern, 0)
+                             lambda_min, lambda_max, kern, forces)
         h = _P()
         rc = lib.felbm_create(ct.byref(self.params), ct.byref(h))
         if rc != 0:

@@ -73,7 +73,8 @@ def test_validate_rejects_bad_meshes(case):
 
 @pytest.mark.parametrize("bad", [dict(xi=0.0), dict(dt=-1.0), dict(rho_v=0.0), dict(sigma=-1.0),
                                  dict(precision=7), dict(solver_sweeps=-1), dict(solver_sweeps=1000),
-                                 dict(lambda_min=1.0, lambda_max=0.5), dict(nu_l=float("nan")), dict(kernels=5)])
+                                 dict(lambda_min=1.0, lambda_max=0.5), dict(nu_l=float("nan")), dict(kernels=5),
+                                 dict(force_scheme=3), dict(force_scheme="nodal", precision="fp32")])
 def test_create_rejects_bad_parameters(bad):
     kw = dict(sigma=0.01, xi=4.0, mobility=0.02, rho_l=1.0, rho_v=0.1, nu_l=0.1 / 3, nu_v=0.1 / 3, dt=0.1)
     kw.update(bad)
