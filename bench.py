@@ -40,10 +40,10 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def make_ctx(felbm, w, precision, sweeps, stream):
+def make_ctx(felbm, w, precision, sweeps, stream, force_scheme="mixed"):
     p = w.phys
     ctx = felbm.Context(sigma=p.sigma, xi=p.xi, mobility=p.mobility, rho_l=p.rho_l, rho_v=p.rho_v, nu_l=p.nu_l,
-                        nu_v=p.nu_v, dt=p.dt, precision=precision, solver_sweeps=sweeps)
+                        nu_v=p.nu_v, dt=p.dt, precision=precision, solver_sweeps=sweeps, force_scheme=force_scheme)
     ctx.bind_stream(stream)
     ctx.upload_mesh(w.mesh.xy, w.mesh.tri, w.mesh.wall_edges, w.mesh.period_x)
     ctx.set_wetting(w.omega_c)
@@ -109,6 +109,39 @@ def adjoint_run(felbm, stream, sweeps):
             "adjoint_MNUPS": round(w.mesh.n_nodes * n / t_bwd / 1e6, 2)}
 
 
+def spurious_table(felbm, stream, t_end, sweeps32, sweeps64, samples=16):
+    """Parasitic kinetic energy <rho u.u> in the band R +- xi of a static
+    droplet (density ratio 2, equal viscosities) at three mesh resolutions,
+    mixed (P0) against nodal (P1) forces: the 2-D analogue of the table of
+    Sec. III.A.  Sampled `samples` times up to the physical time t_end and
+    averaged over the samples of the second half (after the initial
+    relaxation of the tanh profile).  FP64 with 26 sweeps for both schemes,
+    plus the FP32 precision form of the mixed scheme."""
+    from workloads import free_droplet
+    rows = []
+    for level in range(3):
+        w = free_droplet(level, t_end)
+        chunk = max(1, w.steps // samples)
+        xc, yc, R = w.droplets[0]
+        for scheme, prec, k in (("nodal", "fp64", sweeps64), ("mixed", "fp64", sweeps64), ("mixed", "fp32", sweeps32)):
+            log(f"spurious-current table: level {level} ({w.mesh.n_nodes} nodes, {w.steps} steps), {scheme} {prec}")
+            ctx, d0 = make_ctx(felbm, w, prec, k, stream, force_scheme=scheme)
+            trace = []
+            for s in range(samples):
+                ctx.step(chunk)
+                d = ctx.diagnostics()
+                trace.append((round((s + 1) * chunk * w.phys.dt, 3), d["band_ke"], d["max_u"]))
+                log(f"  t {trace[-1][0]:.0f}  band <rho u.u> {d['band_ke']:.3e}  max|u| {d['max_u']:.3e}")
+            late = [x[1] for x in trace[samples // 2:]]
+            rows.append({"level": level, "nodes": w.mesh.n_nodes, "elements": w.mesh.n_tris, "scheme": scheme,
+                         "precision": prec, "dt": w.phys.dt, "steps": chunk * samples, "t_end": trace[-1][0],
+                         "band_ke_mean_second_half": float(sum(late) / len(late)),
+                         "band_ke_final": trace[-1][1], "max_u_final": trace[-1][2],
+                         "mass_drift": abs(d["mass"] - d0["mass"]) / d0["mass"], "trace": trace})
+            ctx.close()
+    return rows
+
+
 def cpu_baseline(cfg, rows):
     """The FP64 CPU oracle, as it stands, on the bottom `rows` node rows of the
     same mesh (one step after one warm-up step)."""
@@ -144,6 +177,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=349)
+    ap.add_argument("--spurious-table", type=float, default=0.0, metavar="T",
+                    help="only run the parasitic-current comparison (mixed vs nodal forces, three resolutions) "
+                         "up to physical time T and print it")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB ten times (HBM counter calibration)")
     args = ap.parse_args()
@@ -164,7 +200,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding of this path is "
-              "described in DESIGN.md and not built", file=sys.stderr)
+              "a design, not built", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -173,6 +209,13 @@ def main():
     from workloads import config
 
     torch.cuda.set_device(0)
+    if args.spurious_table:
+        tstream = torch.cuda.Stream()
+        torch.cuda.set_stream(tstream)
+        rows = spurious_table(felbm, tstream.cuda_stream, args.spurious_table, args.sweeps32, args.sweeps64)
+        print(json.dumps({"spurious_current_table": rows}))
+        return
+
     # a dedicated (default-priority) torch stream: the library and the timing events share it
     tstream = torch.cuda.Stream()
     torch.cuda.set_stream(tstream)

@@ -151,3 +151,22 @@ def _config(cfg: int) -> Workload:
         return Workload("adjoint-1024x512-graded", mesh, phys, droplet_field(mesh, drops, phys.xi), om, 2000, drops,
                         extra={"ckpt_every": 100, "C_target": target})
     raise ValueError(f"no workload {cfg}")
+
+
+def free_droplet(level: int, t_end: float = 8000.0) -> Workload:
+    """Static droplet for the parasitic-current comparison (the 2-D analogue of
+    the table of Sec. III.A): density ratio 2, equal kinematic viscosities
+    (1/30 in both phases), radius 16 centred in a 64 x 64 box (x-periodic,
+    neutral walls 16 units from the interface), jittered split mesh with
+    spacing h = 2^-level (level 0, 1, 2: 4,160 / 16,512 / 65,792 nodes).
+    Space and time are refined together, dt = 0.1 h, and the run covers the
+    same physical time t_end at every level."""
+    n = 64 * 2 ** level
+    mesh = split_grid_mesh(64.0, uniform_rows(64.0, n + 1), n, seed=[10 + level])
+    dt = 0.1 / 2 ** level
+    nu = 0.1 / 3.0
+    phys = Physics(sigma=0.01, xi=4.0, mobility=0.02, rho_l=1.0, rho_v=0.5, nu_l=nu, nu_v=nu, dt=dt)
+    drops = [(32.0, 32.0, 16.0)]
+    om = wetting_from_angles(mesh, 90.0)
+    return Workload(f"free-droplet-64x64-level{level}", mesh, phys, droplet_field(mesh, drops, phys.xi),
+                    om, int(round(t_end / dt)), drops)
