@@ -173,6 +173,99 @@ def spurious_table(felbm, stream, t_end, sweeps32, sweeps64, samples=16):
     return rows
 
 
+def angle_run(felbm, stream, w, sweeps32, samples):
+    """One sessile droplet in FP32 up to w.steps, the contact angle measured
+    on the C = 0.5 contour `samples` times."""
+    from paper_1708_04678_amd.analysis import contact_angle
+    ctx, d0 = make_ctx(felbm, w, "fp32", sweeps32, stream)
+    chunk = max(1, w.steps // samples)
+    trace = []
+    for s in range(samples):
+        try:
+            ctx.step(chunk)
+        except felbm.FelbmError as e:
+            log(f"  diverged: {e}")
+            ctx.close()
+            return {"nodes": w.mesh.n_nodes, "xi": w.phys.xi, "dt": w.phys.dt, "mobility": w.phys.mobility,
+                    "diverged": str(e), "trace": trace}
+        d = ctx.diagnostics()
+        th, hgt, base = contact_angle(w.mesh.xy, w.mesh.tri, w.mesh.wall_nodes(0), ctx.read("C"), w.mesh.period_x)
+        trace.append((round((s + 1) * chunk * w.phys.dt, 3), round(th, 3), d["max_u"]))
+        log(f"  t {trace[-1][0]:.0f}  theta {th:.2f} deg (h {hgt:.2f}, b {base:.2f})  max|u| {d['max_u']:.3e}")
+    ctx.close()
+    return {"nodes": w.mesh.n_nodes, "h": round(float(w.mesh.xy[1, 0] - w.mesh.xy[0, 0]), 6), "xi": w.phys.xi,
+            "dt": w.phys.dt, "mobility": w.phys.mobility, "steps": chunk * samples, "t_end": trace[-1][0],
+            "theta_measured": trace[-1][1], "height": round(hgt, 3), "base": round(base, 3),
+            "theta_change_last_quarter": round(trace[-1][1] - trace[(3 * samples) // 4 - 1][1], 3),
+            "max_u_final": trace[-1][2], "mass_drift": abs(d["mass"] - d0["mass"]) / d0["mass"], "trace": trace}
+
+
+def contact_angle_sweep(felbm, stream, t_end, sweeps32, samples=8):
+    """Equilibrium contact angle against the imposed wetting potential
+    Omega_c = -cos(theta) (the 2-D analogue of the angle sweep of Sec. III.B):
+    a R = 20 droplet on a wall meshed with h = xi / 8, for two density /
+    viscosity contrasts, in the FP32 precision form.  Then the resolution
+    study: theta = 60 and 120 deg at h / xi = 1/2, 1/4, 1/8, 1/16."""
+    import numpy as np
+    from workloads import wetting_drop
+    sweep = []
+    for m_rho, m_nu in ((10.0, 1.0), (100.0, 40.0)):
+        for theta in (30.0, 45.0, 60.0, 75.0, 90.0, 105.0, 120.0, 135.0, 150.0):
+            w = wetting_drop(theta, m_rho, m_nu, refine=2, t_end=t_end)
+            log(f"contact-angle sweep: M_rho {m_rho:g} M_nu {m_nu:g} theta {theta:g} ({w.mesh.n_nodes} nodes, "
+                f"{w.steps} steps)")
+            row = {"theta_imposed": theta, "omega_c": -float(np.cos(np.radians(theta))), "m_rho": m_rho,
+                   "m_nu": m_nu}
+            row.update(angle_run(felbm, stream, w, sweeps32, samples))
+            sweep.append(row)
+    resolution = []
+    for refine, xi, mobility, dt in ((1, 2.0, 0.2, None), (1, 4.0, 0.2, None), (2, 4.0, 0.2, None),
+                                     (4, 4.0, 0.1, 0.0125)):
+        for theta in (60.0, 120.0):
+            w = wetting_drop(theta, refine=refine, xi=xi, mobility=mobility, dt=dt, t_end=t_end)
+            log(f"contact-angle resolution: h {1.0 / refine:g} xi {xi:g} theta {theta:g} ({w.mesh.n_nodes} nodes, "
+                f"{w.steps} steps)")
+            row = {"theta_imposed": theta, "h_over_xi": 1.0 / (refine * xi), "m_rho": 10.0, "m_nu": 1.0}
+            row.update(angle_run(felbm, stream, w, sweeps32, samples))
+            resolution.append(row)
+    return sweep, resolution
+
+
+def mobility_study(felbm, stream, t_over_t0, sweeps32, samples=60):
+    """Decay of the mean kinetic energy <T> = 0.5 sum(rho u.u) / N of a
+    sessile droplet (theta = 120 deg, density ratio 100, viscosity ratio 40,
+    R = 20, h = xi / 8) for four mobilities, with time in units of the
+    viscous time t0 = rho_l nu_l R / sigma and the mobility as
+    S = sqrt(M rho_l nu_l) / R (Sec. III.B, fig:mobility), up to t0 *
+    t_over_t0, FP32 precision form."""
+    import math
+    from paper_1708_04678_amd.analysis import contact_angle
+    from workloads import wetting_drop
+    rows = []
+    for mobility in (0.02, 0.05, 0.1, 0.2):
+        w = wetting_drop(120.0, 100.0, 40.0, refine=2, mobility=mobility)
+        xc, yc, R = w.droplets[0]
+        p = w.phys
+        t0 = p.rho_l * p.nu_l * R / p.sigma
+        S = math.sqrt(mobility * p.rho_l * p.nu_l) / R
+        steps = int(round(t_over_t0 * t0 / p.dt))
+        chunk = max(1, steps // samples)
+        log(f"mobility study: M {mobility:g} (S {S:.3e}, t0 {t0:.2f}), {w.mesh.n_nodes} nodes, {chunk * samples} steps")
+        ctx, d0 = make_ctx(felbm, w, "fp32", sweeps32, stream)
+        trace = [(0.0, d0["mean_ke"], d0["max_u"])]
+        for s in range(samples):
+            ctx.step(chunk)
+            d = ctx.diagnostics()
+            trace.append((round((s + 1) * chunk * p.dt / t0, 4), d["mean_ke"], d["max_u"]))
+        th, hgt, base = contact_angle(w.mesh.xy, w.mesh.tri, w.mesh.wall_nodes(0), ctx.read("C"), w.mesh.period_x)
+        log(f"  <T> at t/t0 = {trace[-1][0]:g}: {trace[-1][1]:.3e}, max|u| {trace[-1][2]:.3e}, theta {th:.2f} deg")
+        rows.append({"mobility": mobility, "S": S, "t0": t0, "nodes": w.mesh.n_nodes, "dt": p.dt,
+                     "steps": chunk * samples, "theta_final": round(th, 3),
+                     "mass_drift": abs(d["mass"] - d0["mass"]) / d0["mass"], "trace": trace})
+        ctx.close()
+    return rows
+
+
 def cpu_baseline(cfg, rows):
     """The FP64 CPU oracle, as it stands, on the bottom `rows` node rows of the
     same mesh (one step after one warm-up step)."""
@@ -211,6 +304,12 @@ def main():
     ap.add_argument("--spurious-table", type=float, default=0.0, metavar="T",
                     help="only run the parasitic-current comparison (mixed vs nodal forces, three resolutions) "
                          "up to physical time T and print it")
+    ap.add_argument("--contact-angle-sweep", type=float, default=0.0, metavar="T",
+                    help="only run the equilibrium contact angle against the imposed wetting potential "
+                         "(two contrasts, 30-150 deg, and a mesh-resolution study) up to physical time T")
+    ap.add_argument("--mobility-study", type=float, default=0.0, metavar="T",
+                    help="only run the kinetic-energy decay of a theta = 120 deg droplet for four mobilities up "
+                         "to T viscous times")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB ten times (HBM counter calibration)")
     args = ap.parse_args()
@@ -245,6 +344,18 @@ def main():
         torch.cuda.set_stream(tstream)
         rows = spurious_table(felbm, tstream.cuda_stream, args.spurious_table, args.sweeps32, args.sweeps64)
         print(json.dumps({"spurious_current_table": rows}))
+        return
+    if args.contact_angle_sweep:
+        tstream = torch.cuda.Stream()
+        torch.cuda.set_stream(tstream)
+        sweep, resolution = contact_angle_sweep(felbm, tstream.cuda_stream, args.contact_angle_sweep, args.sweeps32)
+        print(json.dumps({"contact_angle_sweep": sweep, "contact_angle_resolution": resolution}))
+        return
+    if args.mobility_study:
+        tstream = torch.cuda.Stream()
+        torch.cuda.set_stream(tstream)
+        print(json.dumps({"mobility_study": mobility_study(felbm, tstream.cuda_stream, args.mobility_study,
+                                                           args.sweeps32)}))
         return
 
     # a dedicated (default-priority) torch stream: the library and the timing events share it

@@ -3,4 +3,4 @@ the CPU oracle, the tests and the benchmark.  Geometry and input recipes only:
 no lattice Boltzmann or finite element arithmetic lives here."""
 from .mesh import Mesh, graded_rows, split_grid_mesh, uniform_rows, unwrap_tri_xy  # noqa: F401
 from .configs import (Physics, Workload, config, droplet_field, fourier_field, free_droplet,  # noqa: F401
-                      make_physics, wetting_from_angles)
+                      make_physics, wetting_drop, wetting_from_angles)
