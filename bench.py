@@ -47,8 +47,9 @@ def make_ctx(felbm, w, precision, sweeps, stream, force_scheme="mixed"):
     ctx.bind_stream(stream)
     ctx.upload_mesh(w.mesh.xy, w.mesh.tri, w.mesh.wall_edges, w.mesh.period_x)
     ctx.set_wetting(w.omega_c)
-    xc, yc, R = w.droplets[0]
-    ctx.set_band(xc, yc, R, w.phys.xi)
+    if w.droplets:
+        xc, yc, R = w.droplets[0]
+        ctx.set_band(xc, yc, R, w.phys.xi)
     ctx.init(w.C0)
     return ctx, ctx.diagnostics()
 
@@ -237,7 +238,8 @@ def mobility_study(felbm, stream, t_over_t0, sweeps32, samples=60):
     R = 20, h = xi / 8) for four mobilities, with time in units of the
     viscous time t0 = rho_l nu_l R / sigma and the mobility as
     S = sqrt(M rho_l nu_l) / R (Sec. III.B, fig:mobility), up to t0 *
-    t_over_t0, FP32 precision form."""
+    t_over_t0, FP32 precision form.  Trace entries: (t / t0, <T>, max|u|,
+    x of the droplet's centroid)."""
     import math
     from paper_1708_04678_amd.analysis import contact_angle
     from workloads import wetting_drop
@@ -252,17 +254,87 @@ def mobility_study(felbm, stream, t_over_t0, sweeps32, samples=60):
         chunk = max(1, steps // samples)
         log(f"mobility study: M {mobility:g} (S {S:.3e}, t0 {t0:.2f}), {w.mesh.n_nodes} nodes, {chunk * samples} steps")
         ctx, d0 = make_ctx(felbm, w, "fp32", sweeps32, stream)
-        trace = [(0.0, d0["mean_ke"], d0["max_u"])]
+        m = ctx.lumped_mass()
+        trace = [(0.0, d0["mean_ke"], d0["max_u"], float(xc))]
         for s in range(samples):
             ctx.step(chunk)
             d = ctx.diagnostics()
-            trace.append((round((s + 1) * chunk * p.dt / t0, 4), d["mean_ke"], d["max_u"]))
+            C = ctx.read("C")
+            x_c = float((m * C * w.mesh.xy[:, 0]).sum() / (m * C).sum())
+            trace.append((round((s + 1) * chunk * p.dt / t0, 4), d["mean_ke"], d["max_u"], x_c))
         th, hgt, base = contact_angle(w.mesh.xy, w.mesh.tri, w.mesh.wall_nodes(0), ctx.read("C"), w.mesh.period_x)
         log(f"  <T> at t/t0 = {trace[-1][0]:g}: {trace[-1][1]:.3e}, max|u| {trace[-1][2]:.3e}, theta {th:.2f} deg")
         rows.append({"mobility": mobility, "S": S, "t0": t0, "nodes": w.mesh.n_nodes, "dt": p.dt,
                      "steps": chunk * samples, "theta_final": round(th, 3),
                      "mass_drift": abs(d["mass"] - d0["mass"]) / d0["mass"], "trace": trace})
         ctx.close()
+    return rows
+
+
+def washburn_length(t, K, eta_l, eta_v, length, l0):
+    """Liquid length in a 2-D channel of the given length from
+    (eta_l l + eta_v (length - l)) dl/dt = K, l(0) = l0: Poiseuille flow
+    between plates with the capillary pressure 2 sigma cos(theta) / H drawn
+    across both fluids in the channel, K = H sigma cos(theta) / 6."""
+    import numpy as np
+    a, b = 0.5 * (eta_l - eta_v), eta_v * length
+    c = K * np.asarray(t) + a * l0 * l0 + b * l0
+    return (-b + np.sqrt(b * b + 4.0 * a * c)) / (2.0 * a)
+
+
+def capillary_study(felbm, stream, sweeps32, samples=40, fill=0.75):
+    """Capillary intrusion into a 2-D channel (Sec. III.C in its 2-D form):
+    for theta = 56, 72, 83 deg the liquid length l(t) = (liquid volume in the
+    channel) / H against the Washburn law of `washburn_length`, run until the
+    law's l reaches `fill` of the channel.  Over the samples with l beyond
+    l0 + H two fits: the pure law, K_pure = d/dt [(eta_l - eta_v) l^2 / 2 +
+    eta_v L l]; and the law with a constant extra resistance eta_l l_e (the
+    entrance, the reservoir and the moving contact lines), fitted jointly as
+    (eta_l - eta_v) l^2 / 2 + eta_v L l + eta_l l_e l = K_fit t + c.  The
+    effective cos(theta) is 6 K_fit / (H sigma)."""
+    import numpy as np
+    from workloads import capillary_channel
+    rows = []
+    for theta in (56.0, 72.0, 83.0):
+        w = capillary_channel(theta)
+        e, p = w.extra, w.phys
+        H, L, l0 = e["width"], e["length"], e["l0"]
+        eta_l, eta_v = p.rho_l * p.nu_l, p.rho_v * p.nu_v
+        K = H * p.sigma * np.cos(np.radians(theta)) / 6.0
+        lt = fill * L
+        t_end = (0.5 * (eta_l - eta_v) * (lt * lt - l0 * l0) + eta_v * L * (lt - l0)) / K
+        steps = int(round(t_end / p.dt))
+        chunk = max(1, steps // samples)
+        log(f"capillary intrusion: theta {theta:g} ({w.mesh.n_nodes} nodes, {chunk * samples} steps, t {t_end:.0f})")
+        ctx, d0 = make_ctx(felbm, w, "fp32", sweeps32, stream)
+        m = ctx.lumped_mass()
+        inside = (w.mesh.xy[:, 0] > e["x0"]) & (w.mesh.xy[:, 0] < e["x1"])
+        trace = []
+        for s in range(samples + 1):
+            if s:
+                ctx.step(chunk)
+            t = s * chunk * p.dt
+            l_meas = float((m[inside] * ctx.read("C")[inside]).sum() / H)
+            trace.append((round(t, 3), round(l_meas, 4), round(float(washburn_length(t, K, eta_l, eta_v, L, l0)), 4)))
+        d = ctx.diagnostics()
+        ctx.close()
+        tt = np.array([x[0] for x in trace])
+        ll = np.array([x[1] for x in trace])
+        sel = ll > l0 + H
+        I = 0.5 * (eta_l - eta_v) * ll * ll + eta_v * L * ll
+        K_pure = float(np.polyfit(tt[sel], I[sel], 1)[0])
+        A = np.stack([tt[sel], -ll[sel], np.ones(int(sel.sum()))], 1)
+        K_fit, R0 = (float(v) for v in np.linalg.lstsq(A, I[sel], rcond=None)[0][:2])
+        cos_eff = 6.0 * K_fit / (H * p.sigma)
+        log(f"  l(t_end) {ll[-1]:.2f} (law {trace[-1][2]:.2f}); pure law K_fit / K {K_pure / K:.3f}; "
+            f"with an entrance length: K_fit / K {K_fit / K:.3f}, entrance length {R0 / eta_l:.2f}")
+        rows.append({"theta": theta, "nodes": w.mesh.n_nodes, "width": H, "length": L, "l0": l0, "dt": p.dt,
+                     "sigma": p.sigma, "eta_l": eta_l, "eta_v": eta_v, "K": K,
+                     "K_fit_pure_law_over_K": K_pure / K, "K_fit": K_fit, "K_fit_over_K": K_fit / K,
+                     "entrance_length": R0 / eta_l, "cos_theta_effective": cos_eff,
+                     "theta_effective": float(np.degrees(np.arccos(min(1.0, cos_eff)))),
+                     "steps": chunk * samples, "max_u_final": d["max_u"],
+                     "mass_drift": abs(d["mass"] - d0["mass"]) / d0["mass"], "trace": trace})
     return rows
 
 
@@ -310,6 +382,8 @@ def main():
     ap.add_argument("--mobility-study", type=float, default=0.0, metavar="T",
                     help="only run the kinetic-energy decay of a theta = 120 deg droplet for four mobilities up "
                          "to T viscous times")
+    ap.add_argument("--capillary", action="store_true",
+                    help="only run capillary intrusion into a channel (theta = 56, 72, 83 deg) against Washburn")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB ten times (HBM counter calibration)")
     args = ap.parse_args()
@@ -350,6 +424,11 @@ def main():
         torch.cuda.set_stream(tstream)
         sweep, resolution = contact_angle_sweep(felbm, tstream.cuda_stream, args.contact_angle_sweep, args.sweeps32)
         print(json.dumps({"contact_angle_sweep": sweep, "contact_angle_resolution": resolution}))
+        return
+    if args.capillary:
+        tstream = torch.cuda.Stream()
+        torch.cuda.set_stream(tstream)
+        print(json.dumps({"capillary_intrusion": capillary_study(felbm, tstream.cuda_stream, args.sweeps32)}))
         return
     if args.mobility_study:
         tstream = torch.cuda.Stream()

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import paper_1708_04678_amd as felbm
-from workloads import split_grid_mesh, uniform_rows
+from workloads import capillary_channel, channel_mesh, split_grid_mesh, uniform_rows
 
 HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "felbm.h")
 
@@ -42,6 +42,20 @@ def test_validate_accepts_generated_meshes():
     assert felbm.validate_mesh(m.xy, m.tri, m.wall_edges, m.period_x)[0] == 0
     closed = split_grid_mesh(8.0, uniform_rows(4.0, 5), 8, seed=[1], periodic=False)
     assert felbm.validate_mesh(closed.xy, closed.tri, closed.wall_edges, 0.0)[0] == 0
+
+
+def test_validate_accepts_channel_meshes():
+    """Meshes with holes: every boundary edge a wall edge, straight walls,
+    at most two wall edges per node, wall sides classified."""
+    m = channel_mesh(40.0, 16.0, 1.0, 12.0, 28.0, 6.0, 10.0, seed=[7])
+    assert felbm.validate_mesh(m.xy, m.tri, m.wall_edges, m.period_x)[0] == 0
+    assert np.bincount(m.wall_side, minlength=6).tolist() == [24, 24, 0, 0, 32, 24]
+    ys = m.xy[m.wall_nodes(4), 1]
+    assert np.all((ys == 6.0) | (ys == 10.0))
+    assert np.bincount(m.wall_edges.ravel()).max() == 2
+    w = capillary_channel(60.0)
+    assert felbm.validate_mesh(w.mesh.xy, w.mesh.tri, w.mesh.wall_edges, w.mesh.period_x)[0] == 0
+    assert np.count_nonzero(w.omega_c) == w.mesh.wall_nodes(4).size
 
 
 @pytest.mark.parametrize("case", ["index", "clockwise", "repeat", "missing_wall", "interior_wall", "nan_xy",

@@ -20,7 +20,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .mesh import Mesh, graded_rows, split_grid_mesh, uniform_rows
+from .mesh import Mesh, channel_mesh, graded_rows, split_grid_mesh, uniform_rows
 
 
 @dataclass
@@ -195,3 +195,40 @@ def wetting_drop(theta_deg: float, m_rho: float = 10.0, m_nu: float = 1.0, refin
     return Workload(f"wetting-drop-theta{theta_deg:g}-h{1.0 / refine:g}-xi{xi:g}", mesh, phys,
                     droplet_field(mesh, drops, xi), om, int(round(t_end / dt)), drops,
                     extra={"theta": theta_deg, "m_rho": m_rho, "m_nu": m_nu})
+
+
+def capillary_channel(theta_deg: float, width: float = 10.0, length: float = 100.0, refine: int = 2,
+                      xi: float = 4.0, sigma: float = 0.02, m_rho: float = 10.0, m_nu: float = 1.0,
+                      mobility: float = 0.2, l0: float | None = None, t_end: float = 10000.0) -> Workload:
+    """Capillary intrusion (the 2-D analogue of the capillary-tube experiment of
+    Sec. III.C): a channel of the given width and length between two solid
+    blocks (`channel_mesh`), wetting potential Omega_c = -cos(theta) on the
+    channel walls, neutral box walls and block faces.  The box is 4 widths
+    high; the reservoir (8 widths long, joined through the x period) holds a
+    liquid slab of length 4 widths that reaches l0 (default one width) into
+    the channel, vapour elsewhere; flat tanh interfaces of width xi.
+    Spacing h = 1 / refine, dt = 0.1 / refine, nu_l = 1/30."""
+    H = width
+    ly = 4.0 * H
+    y0, y1 = 1.5 * H, 2.5 * H
+    slab = 4.0 * H
+    x0 = slab + 2.0 * H
+    x1 = x0 + length
+    lx = x1 + 2.0 * H
+    l0 = H if l0 is None else l0
+    h = 1.0 / refine
+    mesh = channel_mesh(lx, ly, h, x0, x1, y0, y1, seed=[30])
+    dt = 0.1 / refine
+    nu = 0.1 / 3.0
+    phys = Physics(sigma=sigma, xi=xi, mobility=mobility, rho_l=1.0, rho_v=1.0 / m_rho, nu_l=nu, nu_v=nu * m_nu,
+                   dt=dt)
+    om = np.zeros(mesh.n_nodes)
+    om[mesh.wall_nodes(4)] = -np.cos(np.radians(theta_deg))
+    # corner nodes shared by a channel wall and a block face keep the channel value
+    x = mesh.xy[:, 0]
+    d = np.minimum(x - (x0 - slab), (x0 + l0) - x)
+    C0 = 0.5 + 0.5 * np.tanh(2.0 * d / xi)
+    return Workload(f"capillary-channel-theta{theta_deg:g}-H{H:g}-L{length:g}", mesh, phys, C0, om,
+                    int(round(t_end / dt)), [],
+                    extra={"theta": theta_deg, "x0": x0, "x1": x1, "y0": y0, "y1": y1, "l0": l0, "width": H,
+                           "length": length})

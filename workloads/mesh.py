@@ -158,3 +158,72 @@ def split_grid_mesh(lx: float, rows: np.ndarray, ncols: int, seed, *, jitter: fl
     if not np.all(area2 > 0):
         raise RuntimeError("mesh generator produced a non-positive triangle")
     return mesh
+
+
+def channel_mesh(lx: float, ly: float, h: float, x0: float, x1: float, y0: float, y1: float, seed, *,
+                 jitter: float = 0.2) -> Mesh:
+    """x-periodic box [0, lx) x [0, ly] meshed as a split-quad grid of spacing
+    h, with two solid blocks removed: x0 <= x <= x1 below y0 and above y1.
+    Between the blocks runs a channel of width y1 - y0 and length x1 - x0
+    that joins the two sides of the box (one reservoir, through the period).
+
+    Every boundary edge is a wall edge.  wall_side: 0 bottom and 1 top of the
+    box, 4 the channel walls (y = y0 or y1), 5 the block end faces (x = x0 or
+    x1).  Nodes that lie on no wall are jittered by U(-jitter, jitter) h in x
+    and y; wall nodes stay on the grid lines, so the walls are straight.  The
+    block edges must lie on grid lines (multiples of h)."""
+    seed = list(np.atleast_1d(seed).astype(int))
+    ncols, nrows = int(round(lx / h)), int(round(ly / h)) + 1
+    for v in (x0, x1, y0, y1):
+        if abs(v / h - round(v / h)) > 1e-9:
+            raise ValueError("channel_mesh: block edges must lie on grid lines")
+    if not (0.0 < x0 < x1 < lx and 0.0 < y0 < y1 < ly):
+        raise ValueError("channel_mesh: blocks must lie strictly inside the box")
+    X, Y = np.meshgrid(np.arange(ncols) * h, np.arange(nrows) * h)
+    flip = np.random.default_rng(seed + [2]).random((nrows - 1, ncols)) < 0.5
+    j, i = np.meshgrid(np.arange(nrows - 1), np.arange(ncols), indexing="ij")
+    i1 = (i + 1) % ncols
+    n00, n10 = j * ncols + i, j * ncols + i1
+    n01, n11 = (j + 1) * ncols + i, (j + 1) * ncols + i1
+    # the quad (i, j) spans [i h, (i+1) h] x [j h, (j+1) h]; it is solid when its centre is in a block
+    cx, cy = (i + 0.5) * h, (j + 0.5) * h
+    fluid = ~((cx > x0) & (cx < x1) & ((cy < y0) | (cy > y1)))
+    t_a = np.where(flip[..., None], np.stack([n00, n10, n01], -1), np.stack([n00, n10, n11], -1))
+    t_b = np.where(flip[..., None], np.stack([n10, n11, n01], -1), np.stack([n00, n11, n01], -1))
+    tri = np.stack([t_a, t_b], axis=2)[fluid].reshape(-1, 3)
+    used = np.unique(tri)
+    remap = np.full(nrows * ncols, -1, np.int64)
+    remap[used] = np.arange(used.size)
+    tri = remap[tri].astype(np.int32)
+    xy = np.stack([X.ravel(), Y.ravel()], axis=1)[used]
+
+    # boundary edges: edges of exactly one triangle
+    e = np.concatenate([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [2, 0]]])
+    key = np.sort(e, axis=1)
+    uniq, inv, cnt = np.unique(key, axis=0, return_inverse=True, return_counts=True)
+    bnd = cnt[inv.ravel()] == 1
+    walls = e[bnd].astype(np.int32)          # oriented as in their triangle (fluid on the left)
+    pa, pb = xy[walls[:, 0]], xy[walls[:, 1]]
+    tol = 1e-9 * h
+    side = np.full(len(walls), -1, np.int8)
+    side[(np.abs(pa[:, 1]) < tol) & (np.abs(pb[:, 1]) < tol)] = 0
+    side[(np.abs(pa[:, 1] - ly) < tol) & (np.abs(pb[:, 1] - ly) < tol)] = 1
+    horiz = np.abs(pa[:, 1] - pb[:, 1]) < tol
+    on_ch = horiz & ((np.abs(pa[:, 1] - y0) < tol) | (np.abs(pa[:, 1] - y1) < tol))
+    side[on_ch] = 4
+    vert = np.abs(pa[:, 0] - pb[:, 0]) < tol
+    side[vert & ((np.abs(pa[:, 0] - x0) < tol) | (np.abs(pa[:, 0] - x1) < tol))] = 5
+    if np.any(side < 0):
+        raise RuntimeError("channel_mesh: unclassified boundary edge")
+
+    on_wall = np.zeros(len(xy), bool)
+    on_wall[walls.ravel()] = True
+    if jitter > 0:
+        r = np.random.default_rng(seed + [0]).uniform(-jitter, jitter, (nrows * ncols, 2))[used]
+        xy = xy + np.where(on_wall[:, None], 0.0, r * h)
+    mesh = Mesh(xy=xy, tri=tri, wall_edges=walls, period_x=float(lx), ncols=ncols, nrows=nrows, wall_side=side)
+    p = unwrap_tri_xy(xy, tri, mesh.period_x)
+    area2 = (p[:, 1, 0] - p[:, 0, 0]) * (p[:, 2, 1] - p[:, 0, 1]) - (p[:, 2, 0] - p[:, 0, 0]) * (p[:, 1, 1] - p[:, 0, 1])
+    if not np.all(area2 > 0):
+        raise RuntimeError("mesh generator produced a non-positive triangle")
+    return mesh
