@@ -352,8 +352,15 @@ def cpu_baseline(cfg, rows):
     g, h = o.step(g, h)
     wall = time.perf_counter() - t0
     cpu = time.process_time() - c0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": w.mesh.n_nodes / wall / 1e6, "unit": "MNUPS", "cores": max(1, round(cpu / wall)),
-            "kind": "oracle", "seconds": round(wall, 2),
+            "kind": "oracle", "seconds": round(wall, 2), "host_cpu": model,
+            "host_cpus_visible": os.cpu_count(),
             "sample": f"1 step (after 1 warm-up step) of the FP64 numpy/scipy oracle on the bottom {rows} of the "
                       f"{full_rows} node rows of the same mesh ({w.mesh.n_nodes} nodes, same droplets and walls)"}
 
@@ -468,6 +475,12 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "avg_launch_us": round(avg_ms * 1e3, 2), "algorithmic_bytes_per_launch": dom["bytes_per_launch"]}
+    # whole step: the algorithmic bytes of every kernel of a step over the timed step
+    step_bytes = sum(v["bytes_per_launch"] * v["launches"] for v in stats.values()) / args.steps
+    step_gbs = step_bytes / (ms32 / args.steps * 1e-3) / 1e9
+    step_roofline = {"bound": "hbm", "algorithmic_bytes_per_step": round(step_bytes),
+                     "algorithmic_bytes_per_node_step": round(step_bytes / N, 1), "achieved": round(step_gbs, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(step_gbs / HBM_PEAK_GBS, 4)}
     kernels = {k: {"launches": v["launches"], "avg_us": round(v["total_ms"] / max(v["launches"], 1) * 1e3, 2),
                    "share": round(v["total_ms"] / max(sum(x["total_ms"] for x in stats.values()), 1e-9), 4)}
                for k, v in stats.items() if v["launches"]}
@@ -490,6 +503,7 @@ def main():
                    "solver_sweeps": args.sweeps32, "population_updates_per_s": round(18 * N * args.steps / (ms32 * 1e-3)),
                    "parallelism": "single GPU"},
         "roofline": roofline,
+        "step_roofline": step_roofline,
         "kernels": kernels,
     }
 
