@@ -390,6 +390,34 @@ def wall_velocity_after_step() -> float:
     return float(abs(u[o.geo.is_wall_node]).max())
 
 
+def channel_mesh_pins(n_steps=60):
+    """A mesh with two holes (blocks leaving a channel, 40 x 16 box, blocks
+    16 x 6): the lumped masses sum to the fluid area 40*16 - 2*16*6 = 448
+    (Sec. II.C mass matrix), sum_T A_T grad N_i = 0 at every node off the
+    walls, and over n steps with wetting channel walls and a liquid slab in
+    the channel the composition integral is conserved and every wall node,
+    on the block faces and re-entrant corners too, has zero velocity."""
+    from workloads import channel_mesh
+    mesh = channel_mesh(40.0, 16.0, 1.0, 12.0, 28.0, 6.0, 10.0, seed=[7])
+    phys = make_physics(sigma=0.01, m_rho=10, m_nu=2, dt=0.1)
+    om = np.zeros(mesh.n_nodes)
+    om[mesh.wall_nodes(4)] = -0.5
+    o = fo.Oracle(mesh, phys, om)
+    geo = o.geo
+    area_err = abs(o.mat.lumped.sum() - 448.0) / 448.0
+    s = np.zeros((geo.N, 2))
+    for l in range(3):
+        np.add.at(s, mesh.tri[:, l], geo.area[:, None] * geo.gradN[:, l, :])
+    closure = float(abs(s[~geo.is_wall_node]).max())
+    x = mesh.xy[:, 0]
+    C0 = 0.5 + 0.5 * np.tanh(2.0 * np.minimum(x - 4.0, 16.0 - x) / phys.xi)
+    g, h = o.init_state(C0)
+    m0 = o.mass(h)
+    g, h = o.run(g, h, n_steps)
+    C, p, rho, u = fo.moments(g, h, o.prm)
+    return float(area_err), closure, float(abs(o.mass(h) - m0) / m0), float(abs(u[geo.is_wall_node]).max())
+
+
 def pcg_dense_error() -> float:
     mesh = small_mesh()
     mat = fo.Matrices(fo.Geometry(mesh))

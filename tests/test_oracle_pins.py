@@ -95,6 +95,14 @@ def test_no_slip_at_wall_nodes():
     assert pins.wall_velocity_after_step() < 1e-15
 
 
+def test_mesh_with_holes():
+    area, closure, drift, wall_u = pins.channel_mesh_pins()
+    assert area < 1e-14
+    assert closure < 1e-13
+    assert drift < 1e-13
+    assert wall_u < 1e-15
+
+
 def test_pcg_matches_dense_solve():
     assert pins.pcg_dense_error() < 1e-12
 
