@@ -375,7 +375,7 @@ def main():
     # sweeps per step at which each precision's result reaches its own rounding
     # floor against a converged FP64 solve (FP32: max|u| ~1e-5, C ~2e-7;
     # FP64: ~1e-12), measured on the theta = 60 deg and three-droplet workloads
-    ap.add_argument("--sweeps32", type=int, default=12, help="solver sweeps per step in FP32")
+    ap.add_argument("--sweeps32", type=int, default=11, help="solver sweeps per step in FP32")
     ap.add_argument("--sweeps64", type=int, default=26, help="solver sweeps per step in FP64")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")

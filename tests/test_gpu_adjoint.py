@@ -126,7 +126,7 @@ def test_adjoint_workload_fp32_vs_fd_fp64():
     mesh, phys = w.mesh, w.phys
     n, every = w.steps, w.extra["ckpt_every"]
     log(f"adjoint workload: {mesh.n_nodes} nodes, {n} steps, ckpt {every}")
-    c32 = make_ctx(mesh, phys, w.omega_c, precision="fp32", sweeps=12)
+    c32 = make_ctx(mesh, phys, w.omega_c, precision="fp32", sweeps=11)
     m = c32.lumped_mass()
     c32.init(w.C0)
     c32.forward_ckpt(n, every)

@@ -32,7 +32,7 @@ def intrusion(theta, samples=16, fill=0.5):
     t_end = (0.5 * (eta_l - eta_v) * (lt * lt - l0 * l0) + eta_v * L * (lt - l0)) / K
     chunk = int(round(t_end / p.dt)) // samples
     log(f"capillary intrusion theta {theta:g}: {w.mesh.n_nodes} nodes, {chunk * samples} steps")
-    ctx = make_ctx(w.mesh, w.phys, w.omega_c, precision="fp32", sweeps=12)
+    ctx = make_ctx(w.mesh, w.phys, w.omega_c, precision="fp32", sweeps=11)
     ctx.init(w.C0)
     m = ctx.lumped_mass()
     m0 = ctx.diagnostics()["mass"]
