@@ -7,7 +7,7 @@ densities, kinematic viscosities, time step); the derived free-energy
 constants (kappa, beta, phi_c, relaxation times) are computed by each
 consumer on its own.
 
-Readings for constants the paper leaves open (all documented with the build):
+Readings for constants the paper leaves open:
   * time step: dt = 0.1 on unit-spacing meshes, 0.025 on wall-graded meshes;
   * liquid viscosity nu_l = dt / 3 (liquid relaxation time 1), and the
     viscosity ratio is nu_v / nu_l;
