@@ -1,5 +1,7 @@
-"""The five synthetic droplet-on-wall workloads: mesh, physical constants,
-initial composition field and per-node wetting potential.
+"""The synthetic workloads: the five droplet-on-wall configurations and the
+inputs of the comparison studies (free droplet, sessile droplet, capillary
+channel), each as mesh, physical constants, initial composition field and
+per-node wetting potential.
 
 Everything here is input data.  Physical constants are given in the form the
 paper states them (surface tension sigma, interface width xi, mobility M,
