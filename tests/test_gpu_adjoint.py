@@ -153,6 +153,50 @@ def test_adjoint_workload_fp32_vs_fd_fp64():
     c64.close()
 
 
+def test_adjoint_at_scale_vs_fd_fp64():
+    """The graded 1024 x 512 adjoint workload at full size (527,360 nodes, FP32
+    and FP64 forward and reverse, checkpoint every 10) over a short horizon of
+    40 steps, loss 1/2 sum m (C - C*)^2: the gradient with respect to Omega_c
+    at 4 seeded bottom-wall nodes near the two contact lines against central
+    differences (h = 1e-3) of the FP64 forward.  Bars: FP64 adjoint 1e-5
+    relative (difference truncation O(h^2) and rounding), FP32 adjoint 2 %."""
+    w = config(5)
+    mesh, phys, Ct = w.mesh, w.phys, w.extra["C_target"]
+    n, every = 40, 10
+    log(f"adjoint at scale: {mesh.n_nodes} nodes, {n} steps, ckpt {every}")
+    grads = {}
+    for prec, sweeps in (("fp64", 26), ("fp32", 11)):
+        ctx = make_ctx(mesh, phys, w.omega_c, precision=prec, sweeps=sweeps)
+        m = ctx.lumped_mass()
+        ctx.init(w.C0)
+        ctx.forward_ckpt(n, every)
+        grads[prec] = ctx.backward_host(m * (ctx.read("C") - Ct))
+        ctx.close()
+    c64 = make_ctx(mesh, phys, w.omega_c, precision="fp64", sweeps=26)
+
+    def loss(om):
+        c64.set_wetting(om)
+        c64.init(w.C0)
+        c64.step(n)
+        return 0.5 * np.sum(m * (c64.read("C") - Ct) ** 2)
+
+    bottom = mesh.wall_nodes(0)
+    xb = mesh.xy[bottom, 0]
+    xc, _, R = w.droplets[0]
+    near = bottom[(np.abs(np.abs(xb - xc) - R) < 3.0)]
+    pick = np.random.default_rng([5, 6]).choice(near, 4, replace=False)
+    hstep = 1e-3
+    for k in pick:
+        e = np.zeros(mesh.n_nodes)
+        e[k] = hstep
+        fd = (loss(w.omega_c + e) - loss(w.omega_c - e)) / (2 * hstep)
+        log(f"  node {k} (x {mesh.xy[k, 0]:.2f}): adjoint fp64 {grads['fp64'][k]:.8e}  fp32 {grads['fp32'][k]:.6e}"
+            f"  fd fp64 {fd:.8e}")
+        assert abs(grads["fp64"][k] - fd) <= 1e-5 * abs(fd) + 1e-12
+        assert abs(grads["fp32"][k] - fd) <= 0.02 * abs(fd) + 1e-3 * np.abs(grads["fp32"]).max()
+    c64.close()
+
+
 def test_torch_autograd_function():
     """The torch.autograd.Function path (device buffers and stream from torch)
     gives the same gradient as the host-array reverse pass."""
