@@ -720,8 +720,12 @@ __global__ void __launch_bounds__(BLOCK) k_rhs_lds(int N, int Np, int E, TileArg
   const real dt = (real)P.dt, c1 = dt / (real)3, c2 = (real)0.5 * dt * dt;
   const real drho_cs2 = (real)(CS2 * (P.rho_l - P.rho_v));
   const int e0 = rt.ent_off[t], width = (rt.ent_off[t + 1] - e0) / TILE;
+  // the next entry is loaded one iteration ahead, so that only the element
+  // data wait on memory inside the loop
+  int2 en_next = width > 0 ? rt.ent[e0 + lane] : int2{-1, 0};
   for (int k = 0; k < width; ++k) {
-    const int2 en = rt.ent[e0 + k * TILE + lane];
+    const int2 en = en_next;
+    if (k + 1 < width) en_next = rt.ent[e0 + (k + 1) * TILE + lane];
     if (en.x < 0) continue;
     const int e = en.x >> 2, l = en.x & 3;
     const int s0 = en.y & 511, s1 = (en.y >> 9) & 511, s2 = (en.y >> 18) & 511;
