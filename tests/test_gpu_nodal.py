@@ -2,7 +2,6 @@
 oracle) on the GPU, FP64, against the oracle's nodal scheme element by
 element; tolerances as for the mixed scheme (same solver truncation and
 rounding depth)."""
-import numpy as np
 import pytest
 
 from gpu_common import log, make_ctx, rel, stack

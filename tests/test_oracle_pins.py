@@ -1,5 +1,4 @@
 """The CPU oracle pinned to what the paper and mathematics fix (no GPU)."""
-import numpy as np
 import pytest
 
 import pins
