@@ -159,6 +159,40 @@ def test_channel_mesh_with_internal_walls():
         ctx.close()
 
 
+def test_degenerate_single_phase_states(cfg1_theta60):
+    """Uniform composition, where every interface force vanishes: a pure
+    liquid (C = 1) carrying a shear wave u_x = U sin(pi y / L_y) against the
+    oracle after 20 steps (FP64 1e-12, FP32 1e-5), and a pure vapour (C = 0)
+    at rest, which must stay at rest exactly (the equilibrium is a fixed point
+    of collision and streaming, and the wall operator keeps it)."""
+    w, om, o = cfg1_theta60
+    y = w.mesh.xy[:, 1]
+    Ly = y.max()
+    u0 = np.zeros((w.mesh.n_nodes, 2))
+    u0[:, 0] = 1e-3 * np.sin(np.pi * y / Ly)
+    ones = np.ones(w.mesh.n_nodes)
+    g, h = o.init_state(ones, u0)
+    g, h = o.run(g, h, 20)
+    ref = stack(g, h)
+    for prec, sweeps, bar in (("fp64", 32, 1e-12), ("fp32", 16, 1e-5)):
+        log(f"pure liquid with a shear wave, {prec}, 20 steps")
+        ctx = make_ctx(w.mesh, w.phys, om, precision=prec, sweeps=sweeps)
+        ctx.init(ones, u0)
+        ctx.step(20)
+        err = rel(ctx.read_populations(), ref)
+        log(f"  max rel diff {err:.3e}")
+        assert err < bar
+        ctx.close()
+        log(f"pure vapour at rest, {prec}, 20 steps")
+        ctx = make_ctx(w.mesh, w.phys, om, precision=prec, sweeps=sweeps)
+        ctx.init(np.zeros(w.mesh.n_nodes))
+        ctx.step(20)
+        d = ctx.diagnostics()
+        log(f"  max|u| {d['max_u']:.3e}  mean KE {d['mean_ke']:.3e}")
+        assert d["max_u"] == 0.0 and d["mean_ke"] == 0.0
+        ctx.close()
+
+
 @pytest.mark.parametrize("K", [0, 1, 2, 5])
 def test_short_solver_polynomials(K):
     """K Chebyshev sweeps: the increment's error against the exact solve obeys
