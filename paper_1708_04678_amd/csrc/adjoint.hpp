@@ -83,17 +83,22 @@ __device__ __forceinline__ void adj_lamq(const AdjGeom& g, int e, const real* __
 }
 
 // A3: per element, the transpose of the P0 forces eq:G / eq:H at barycentric
-// values, fed by lam_Phi = lam_q.  Writes the element adjoint record.
+// values, fed by lam_Phi = lam_q.  Writes the element adjoint record and
+// lam_q itself ([NPOP][E], in the compute precision) for the streaming
+// transpose.
 template <typename real>
 __global__ void __launch_bounds__(BLOCK) k_adj_force(AdjGeom g, StepParams P, const real* __restrict__ lb,
                                                     const double* __restrict__ Cn, const real* __restrict__ uxn,
                                                     const real* __restrict__ uyn, const double* __restrict__ mu,
                                                     const double* __restrict__ gC, const real* __restrict__ gp,
-                                                    const double* __restrict__ lapmu, double* __restrict__ ea) {
+                                                    const double* __restrict__ lapmu, double* __restrict__ ea,
+                                                    real* __restrict__ lqe) {
   const int e = xcd_block() * BLOCK + threadIdx.x;
   if (e >= g.E) return;
   double lq[NPOP];
   adj_lamq(g, e, lb, P.dt, lq);
+#pragma unroll
+  for (int p = 0; p < NPOP; ++p) lqe[p * g.E + e] = (real)lq[p];
   const int v0 = g.tri[e], v1 = g.tri[g.E + e], v2 = g.tri[2 * g.E + e];
   const double Cb = (Cn[v0] + Cn[v1] + Cn[v2]) * (1.0 / 3.0);
   const double mub = (mu[v0] + mu[v1] + mu[v2]) * (1.0 / 3.0);
@@ -146,10 +151,11 @@ __global__ void __launch_bounds__(BLOCK) k_adj_force(AdjGeom g, StepParams P, co
   ea[EA_LM * E + e] = P.mobility * ld;
 }
 
-// A4: per node, lam_hat = W lam - sum_{T ni v} lam_q_{a,T} e_a.grad N_v
+// A4: per node, lam_hat = W lam - sum_{T ni v} lam_q_{a,T} e_a.grad N_v, with lam_q
+// as stored by k_adj_force
 template <typename real>
-__global__ void __launch_bounds__(BLOCK) k_adj_stream(AdjGeom g, double dt, const real* __restrict__ lam,
-                                                     const real* __restrict__ lb, real* __restrict__ lhat) {
+__global__ void __launch_bounds__(BLOCK) k_adj_stream(AdjGeom g, const real* __restrict__ lam,
+                                                     const real* __restrict__ lqe, real* __restrict__ lhat) {
   const int v = xcd_block() * BLOCK + threadIdx.x;
   if (v >= g.N) return;
   double l[NPOP];
@@ -168,13 +174,11 @@ __global__ void __launch_bounds__(BLOCK) k_adj_stream(AdjGeom g, double dt, cons
   for (int q = g.n2e_ptr[v]; q < g.n2e_ptr[v + 1]; ++q) {
     const int packed = g.n2e[q];
     const int e = packed >> 2, lv = packed & 3;
-    double lq[NPOP];
-    adj_lamq(g, e, lb, dt, lq);
     const double gx = g.geo[(1 + 2 * lv) * g.E + e], gy = g.geo[(2 + 2 * lv) * g.E + e];
 #pragma unroll
     for (int p = 0; p < NPOP; ++p) {
       const int a = p % Q;
-      l[p] -= lq[p] * (ex(a) * gx + ey(a) * gy);
+      l[p] -= (double)lqe[p * g.E + e] * (ex(a) * gx + ey(a) * gy);
     }
   }
 #pragma unroll

@@ -98,6 +98,7 @@ struct felbm_ctx {
   int32_t *erev = nullptr, *d_node_perm = nullptr;
   void *lam = nullptr, *lhat = nullptr;
   double *ea = nullptr, *lgmu = nullptr, *lgC = nullptr, *lmu = nullptr, *gomega = nullptr;
+  void* lqe = nullptr;  // lam_q per element [18][E], compute precision
   void* ck_buf = nullptr;     // checkpoints every ck_every steps
   void* seg_buf = nullptr;    // replayed states of one segment
   int64_t ck_steps = 0, ck_every = 0, ck_count = 0, ck_start = 0;
@@ -429,6 +430,7 @@ int ensure_adjoint_buffers(felbm_ctx* c) {
   TRY(dalloc_bytes(c, &c->lam, pb));
   TRY(dalloc_bytes(c, &c->lhat, pb));
   TRY(dalloc(c, &c->ea, (size_t)EA_N * c->E));
+  TRY(dalloc_bytes(c, &c->lqe, (size_t)18 * c->E * c->rs));
   TRY(dalloc(c, &c->lgmu, 2 * c->E));
   TRY(dalloc(c, &c->lgC, 2 * c->E));
   TRY(dalloc(c, &c->lmu, c->Np));
@@ -482,9 +484,8 @@ int enqueue_adjoint_step(felbm_ctx* c) {
   TRY(enqueue_adjoint_solve<real>(c, &lb));
   TRY(launch(c, K_ADJ_FORCE, k_adj_force<real>, gE, g, c->sp, (const real*)lb, (const double*)c->Cn,
              (const real*)c->uxn, (const real*)c->uyn, (const double*)c->mu, (const double*)c->gC, (const real*)c->gp,
-             (const double*)c->lapmu, c->ea));
-  TRY(launch(c, K_ADJ_STREAM, k_adj_stream<real>, gN, g, c->sp.dt, (const real*)lam, (const real*)lb,
-             (real*)c->lhat));
+             (const double*)c->lapmu, c->ea, (real*)c->lqe));
+  TRY(launch(c, K_ADJ_STREAM, k_adj_stream<real>, gN, g, (const real*)lam, (const real*)c->lqe, (real*)c->lhat));
   TRY(launch(c, K_ADJ_GMU, k_adj_gmu, gE, g, (const double*)c->ea, c->lgmu));
   TRY(launch(c, K_ADJ_MU, k_adj_mu, gN, g, (const double*)c->ea, (const double*)c->lgmu, c->lmu));
   TRY(launch(c, K_ADJ_GC, k_adj_gC, gE, g, c->sp, (const double*)c->ea, (const double*)c->lmu, c->lgC));
