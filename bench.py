@@ -33,8 +33,10 @@ def log(msg):
 
 
 def kernel_source_sha():
+    """Hash of the sources that set the traffic of the step kernels: the kernels,
+    their launch code and the node ordering."""
     h = hashlib.sha256()
-    for f in ("kernels.hpp", "felbm.hip"):
+    for f in ("kernels.hpp", "felbm.hip", "mesh_prep.cpp"):
         with open(os.path.join(ROOT, "paper_1708_04678_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
