@@ -620,3 +620,148 @@ def nodal_mass_drift(steps=20) -> float:
     m0 = o.mass(h)
     g, h = o.run(g, h, steps)
     return float(abs(o.mass(h) - m0) / m0)
+
+
+# ---------------------------------------------------------------------------
+# Second moments of the equilibria, the composition flux of eq:H, the element
+# Laplacian of mu, the contact-angle measurement and the band energy
+# ---------------------------------------------------------------------------
+def second_moment_error() -> float:
+    """Second moments that the D2Q9 equilibria must reproduce (eqn::g_eq,
+    eqn::f_eq) for the Chapman-Enskog recovery of the momentum flux:
+    sum_a e_i e_j Gamma_a = c_s^2 delta_ij + u_i u_j and
+    sum_a e_i e_j g_eq_a = c_s^2 (p delta_ij + rho u_i u_j)."""
+    rng = np.random.default_rng(15)
+    n = 60
+    C = rng.uniform(0, 1, n); p = rng.normal(0, 1e-3, n)
+    u = rng.normal(0, 0.08, (n, 2))
+    rho = 0.1 + 0.9 * C
+    geq, heq = fo.equilibria(C, p, rho, u)
+    G = fo.gamma(u)
+    e = fo.E
+    eye = np.eye(2)[None]
+    uu = u[:, :, None] * u[:, None, :]
+    m2G = np.einsum("na,ai,aj->nij", G, e, e)
+    m2g = np.einsum("na,ai,aj->nij", geq, e, e)
+    m2h = np.einsum("na,ai,aj->nij", heq, e, e)
+    errs = [abs(m2G - (fo.CS2 * eye + uu)).max(),
+            abs(m2g - fo.CS2 * (p[:, None, None] * eye + rho[:, None, None] * uu)).max(),
+            abs(m2h - C[:, None, None] * (fo.CS2 * eye + uu)).max()]
+    return float(max(errs))
+
+
+def first_step_composition_error(h: float, rho_l: float = 3.0, rho_v: float = 1.0, p0: float = 2e-3) -> float:
+    """Composition change over the first step from rest (u = 0, populations at
+    equilibrium) with mobility M = 0.  The continuum equations of Sec. II give
+    dC/dt = -div(C u) and, with rho du/dt = -grad p + mu grad C at rest,
+    d2C/dt2 = div[(C / rho)(grad p - mu grad C)]; so over one step
+    dC = dt^2/2 d/dy[(C / rho)(p' - mu C')] + O(dt^3).  In the h-scheme this
+    comes entirely from the C/(rho c_s^2)(grad p - mu grad C) term of eq:H (the
+    rest of the second moment cancels against grad C).  Layered fields
+    C = 0.5 + 0.3 cos(k y), p = p0 sin(k y) on a uniform mesh; the exact side
+    uses the closed-form mu = 2 beta C (C-1)(2C-1) - kappa C''.  Returns the
+    max error away from the walls relative to the max of the exact change."""
+    L = 32.0
+    n = int(round(L / h))
+    mesh = split_grid_mesh(8.0, uniform_rows(L, n + 1), int(round(8 / h)), seed=[5], jitter=0.0, diag="up")
+    phys = make_physics(sigma=0.01, m_rho=rho_l / rho_v, m_nu=1, dt=0.1, mobility=0.0, rho_l=rho_l)
+    o = fo.Oracle(mesh, phys, np.zeros(mesh.n_nodes))
+    k = 2 * np.pi / L
+    y = mesh.xy[:, 1]
+    g, hh = o.init_state(0.5 + 0.3 * np.cos(k * y), p=p0 * np.sin(k * y))
+    g1, h1 = o.step(g, hh)
+    dC = h1.sum(1) - hh.sum(1)
+    kap, bet = 1.5 * phys.sigma * phys.xi, 12.0 * phys.sigma / phys.xi
+
+    def flux(yy):
+        C = 0.5 + 0.3 * np.cos(k * yy)
+        Cp, Cpp = -0.3 * k * np.sin(k * yy), -0.3 * k * k * np.cos(k * yy)
+        mu = 2 * bet * C * (C - 1) * (2 * C - 1) - kap * Cpp
+        return (C / (C * rho_l + (1 - C) * rho_v)) * (p0 * k * np.cos(k * yy) - mu * Cp)
+
+    eps = 1e-5
+    exact = 0.5 * phys.dt ** 2 * (flux(y + eps) - flux(y - eps)) / (2 * eps)
+    inner = (y > 4) & (y < L - 4)
+    return float(abs(dC[inner] - exact[inner]).max() / abs(exact[inner]).max())
+
+
+def element_laplacian_quadratic_error() -> float:
+    """Element Laplacian of mu (Sec. II.D) of the quadratics x^2, y^2, x y and
+    x^2 + y^2 on a uniform split-quad mesh with walls on all sides: every
+    element's P1 gradient there is the exact gradient at the midpoint of its
+    row (column) strip, and the averaged edge gradients integrate to the exact
+    Laplacian (2, 2, 0, 4 times the coefficient) at every element two or more
+    cells from the walls.  This fixes the operator's interior scale
+    (fig:element_nabla_mu).  Returns the max error over the four fields,
+    relative to the coefficient."""
+    mesh = split_grid_mesh(12.0, uniform_rows(10.0, 11), 12, seed=[7], jitter=0.0, diag="up", periodic=False)
+    geo = fo.Geometry(mesh)
+    x, y = mesh.xy[:, 0], mesh.xy[:, 1]
+    c = 0.021
+    cx, cy = geo.centroid[:, 0], geo.centroid[:, 1]
+    inner = (cx > 2) & (cx < 10) & (cy > 2) & (cy < 8)
+    err = 0.0
+    for mu, ref in ((0.3 - 0.04 * y + c * x * x, 2 * c), (0.3 + 0.05 * x + c * y * y, 2 * c),
+                    (0.1 + c * x * y, 0.0), (c * (x * x + y * y), 4 * c)):
+        lap = fo.laplacian_mu(geo, fo.element_gradient(geo, mu))
+        err = max(err, abs(lap[inner] - ref).max() / c)
+    return float(err)
+
+
+def cap_field(mesh: Mesh, theta_deg: float, r: float, x0: float, xi: float) -> np.ndarray:
+    """Composition of a circular cap meeting the bottom wall y = 0 at theta:
+    the tanh profile about a circle of radius r centred at (x0, -r cos theta)."""
+    th = np.deg2rad(theta_deg)
+    yc = -r * np.cos(th)
+    d = np.sqrt((mesh.xy[:, 0] - x0) ** 2 + (mesh.xy[:, 1] - yc) ** 2)
+    return 0.5 + 0.5 * np.tanh(2.0 * (r - d) / xi)
+
+
+def cap_mesh(h: float, rough_amp: float = 0.0) -> Mesh:
+    return split_grid_mesh(128.0, uniform_rows(64.0, int(round(64 / h)) + 1), int(round(128 / h)), seed=[17],
+                           jitter=0.2, rough_amp=rough_amp)
+
+
+def contact_angle_cap_errors(measure, h: float, thetas=(30.0, 60.0, 90.0, 120.0, 150.0), rough_amp: float = 0.0):
+    """Sec. III.B: the angle a measurement reads on exact circular caps (tanh
+    profile, xi = 4) of base 2 r sin theta and height r (1 - cos theta) against
+    the imposed geometric angle, on a jittered mesh of spacing h.  The cap
+    radius is chosen so that the cap area is that of a half disc of radius 20.
+    measure(mesh, C) -> theta in degrees.  Returns the signed errors."""
+    mesh = cap_mesh(h, rough_amp)
+    out = []
+    for th in thetas:
+        t = np.deg2rad(th)
+        r = 20.0 * np.sqrt(0.5 * np.pi / (t - np.sin(t) * np.cos(t)))   # cap area = pi 20^2 / 2
+        out.append(measure(mesh, cap_field(mesh, th, r, 64.0, 4.0)) - th)
+    return np.asarray(out)
+
+
+def band_energy_error() -> float:
+    """Band average <rho u.u> of the parasitic-current table (Sec. III.A) against
+    a hand count: on a unit grid, the nodes (i, j) with 3 <= |(i, j) - (16, 8)|
+    <= 5 enumerated one by one, with C = 1 (rho = rho_l = 1) and the velocity
+    field u = (0.01 (x - 16), 0.002 y) set through the equilibria.  Also the
+    whole-domain <T> = 1/2 sum rho |u|^2 / N and max |u| (Sec. III.B)."""
+    mesh = split_grid_mesh(32.0, uniform_rows(16.0, 17), 32, seed=[1], jitter=0.0, diag="up")
+    phys = make_physics(sigma=0.01, m_rho=10, m_nu=1, dt=0.1)
+    o = fo.Oracle(mesh, phys, np.zeros(mesh.n_nodes))
+    x, y = mesh.xy[:, 0], mesh.xy[:, 1]
+    u = np.stack([0.01 * (x - 16.0), 0.002 * y], 1)
+    g, h = o.init_state(np.ones(mesh.n_nodes), u=u)
+    d = o.diagnostics(g, h, band=(16.0, 8.0, 4.0, 1.0))
+    vals, total, peak = [], 0.0, 0.0
+    for j in range(17):
+        for i in range(32):
+            ux, uy = 0.01 * (i - 16.0), 0.002 * j
+            if j in (0, 16):
+                ux = uy = 0.0                  # the wall operator zeroes the wall velocity
+            total += ux * ux + uy * uy
+            peak = max(peak, np.hypot(ux, uy))
+            r2 = (i - 16) ** 2 + (j - 8) ** 2
+            if 9 <= r2 <= 25:
+                vals.append(ux * ux + uy * uy)
+    band_ref = sum(vals) / len(vals)
+    errs = [abs(d["band_ke"] - band_ref) / band_ref, abs(d["mean_ke"] - 0.5 * total / (17 * 32)) / (0.5 * total / (17 * 32)),
+            abs(d["max_u"] - peak) / peak]
+    return float(max(errs))

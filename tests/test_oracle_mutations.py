@@ -124,6 +124,62 @@ def point_forces_no_mobility(prm, C, rho, u, mu, gradC, gradp, gradrho, lapmu):
     return _point(prm, C, rho, u, mu, gradC, gradp, gradrho, 0 * lapmu)
 
 
+def _edot(u, X):
+    return (fo.E[:, 0][None, :] - u[:, 0, None]) * X[:, 0, None] + (fo.E[:, 1][None, :] - u[:, 1, None]) * X[:, 1, None]
+
+
+def _h_force(eq_h_term):
+    """point_forces with the X vector of eq:H replaced by eq_h_term(C, rho, mu, gradC, gradp)."""
+    def forces(prm, C, rho, u, mu, gradC, gradp, gradrho, lapmu):
+        Pg, _ = _point(prm, C, rho, u, mu, gradC, gradp, gradrho, lapmu)
+        Gu = fo.gamma(u)
+        X = eq_h_term(C, rho, mu, gradC, gradp)
+        return Pg, _edot(u, X) * Gu + prm.mobility * lapmu[:, None] * Gu
+    return forces
+
+
+eqH_term_deleted = _h_force(lambda C, rho, mu, gC, gp: gC)
+eqH_mu_sign = _h_force(lambda C, rho, mu, gC, gp: gC - (C / (rho * fo.CS2))[:, None] * (gp + mu[:, None] * gC))
+eqH_rho_one = _h_force(lambda C, rho, mu, gC, gp: gC - (C / fo.CS2)[:, None] * (gp - mu[:, None] * gC))
+
+_gamma = fo.gamma
+
+
+def gamma_quadratic_doubled(u):
+    eu = u[..., 0, None] * fo.E[:, 0] + u[..., 1, None] * fo.E[:, 1]
+    uu = (u[..., 0] * u[..., 0] + u[..., 1] * u[..., 1])[..., None]
+    return fo.W * (1.0 + eu / fo.CS2 + (eu * eu - fo.CS2 * uu) / (fo.CS2 * fo.CS2))
+
+
+def g_eq_quadratic_doubled(C, p, rho, u):
+    g, h = _equil(C, p, rho, u)
+    eu = u[:, 0, None] * fo.E[:, 0] + u[:, 1, None] * fo.E[:, 1]
+    uu = (u[:, 0] * u[:, 0] + u[:, 1] * u[:, 1])[:, None]
+    return g + fo.W * rho[:, None] * fo.CS2 * (eu * eu - fo.CS2 * uu) / (2.0 * fo.CS2 * fo.CS2), h
+
+
+def laplacian_mu_doubled(geo, gradmu):
+    return 2.0 * _lapmu(geo, gradmu)
+
+
+_angle = fo.contact_angle
+
+
+def contact_angle_supplement(mesh, C, level=0.5):
+    th, h, b = _angle(mesh, C, level)
+    return 180.0 - th, h, b
+
+
+_diag = fo.Oracle.diagnostics
+
+
+def band_ke_doubled(self, g, h, band=None):
+    out = _diag(self, g, h, band)
+    if "band_ke" in out:
+        out["band_ke"] *= 2.0
+    return out
+
+
 MUTATIONS = [
     ("printed M10 sign", "rhs", rhs_printed_sign, lambda: pins.static_balance_drift() > 1e-8),
     ("dropped D term", "rhs", rhs_no_D, lambda: pins.advection_error() > 0.05),
@@ -146,6 +202,17 @@ MUTATIONS = [
     ("unweighted nodal average", "nodal_average", nodal_average_unweighted, lambda: pins.nodal_average_error() > 1e-6),
     ("nodal forces without mobility", "point_forces", point_forces_no_mobility,
      lambda: pins.nodal_force_moments_error() > 1e-8),
+    ("eq:H pressure/mu term deleted", "point_forces", eqH_term_deleted,
+     lambda: pins.first_step_composition_error(0.5) > 0.05),
+    ("eq:H mu grad C sign", "point_forces", eqH_mu_sign, lambda: pins.first_step_composition_error(0.5) > 0.05),
+    ("eq:H rho -> 1", "point_forces", eqH_rho_one, lambda: pins.first_step_composition_error(0.5) > 0.05),
+    ("Gamma quadratic doubled", "gamma", gamma_quadratic_doubled, lambda: pins.second_moment_error() > 1e-8),
+    ("g_eq quadratic doubled", "equilibria", g_eq_quadratic_doubled, lambda: pins.second_moment_error() > 1e-8),
+    ("element lap mu doubled", "laplacian_mu", laplacian_mu_doubled,
+     lambda: pins.element_laplacian_quadratic_error() > 1e-3),
+    ("contact angle pi - theta", "contact_angle", contact_angle_supplement,
+     lambda: abs(pins.contact_angle_cap_errors(lambda m, C: fo.contact_angle(m, C)[0], 0.5)).max() > 0.5),
+    ("band energy doubled", "Oracle.diagnostics", band_ke_doubled, lambda: pins.band_energy_error() > 1e-6),
 ]
 
 

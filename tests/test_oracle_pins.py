@@ -138,3 +138,50 @@ def test_nodal_force_moments():
 
 def test_nodal_scheme_conserves_mass():
     assert pins.nodal_mass_drift() < 1e-12
+
+
+def test_second_moments_of_the_equilibria():
+    # eqn::g_eq, eqn::f_eq: sum e e Gamma = c_s^2 I + u u, sum e e g_eq = c_s^2 (p I + rho u u)
+    assert pins.second_moment_error() < 1e-15
+
+
+def test_first_step_composition_flux_of_eq_H():
+    # from rest with M = 0 the composition changes by dt^2/2 div[(C/rho)(grad p - mu grad C)],
+    # which the h-scheme carries only through the C/(rho c_s^2)(grad p - mu grad C) term of eq:H
+    e1, e2 = pins.first_step_composition_error(1.0), pins.first_step_composition_error(0.5)
+    assert e2 < 0.01
+    assert e1 / e2 > 3.0          # second order in h
+
+
+def test_element_laplacian_exact_on_quadratics():
+    # Sec. II.D, fig:element_nabla_mu: averaged edge gradients, unit interior scale
+    assert pins.element_laplacian_quadratic_error() < 1e-12
+
+
+@pytest.mark.parametrize("h", [0.5, 0.25])
+def test_oracle_contact_angle_on_exact_caps(h):
+    from oracle import felbm_oracle as fo
+    err = pins.contact_angle_cap_errors(lambda m, C: fo.contact_angle(m, C)[0], h)
+    assert abs(err).max() < (0.02 if h == 0.5 else 0.005)
+
+
+@pytest.mark.parametrize("h", [0.5, 0.25])
+def test_analysis_contact_angle_on_exact_caps(h):
+    from paper_1708_04678_amd import analysis as an
+    err = pins.contact_angle_cap_errors(
+        lambda m, C: an.contact_angle(m.xy, m.tri, m.wall_nodes(0), C, m.period_x)[0], h)
+    assert abs(err).max() < (0.02 if h == 0.5 else 0.005)
+
+
+@pytest.mark.parametrize("rough", [0.0, 4.0])
+def test_cap_fit_angle_on_exact_caps(rough):
+    # the apparent angle against the mean wall line, on a flat and on a sinusoidally rough wall
+    from paper_1708_04678_amd import analysis as an
+    err = pins.contact_angle_cap_errors(
+        lambda m, C: an.cap_fit_angle(m.xy, m.tri, C, m.period_x, x_window=(0.0, 128.0), y_min=8.0)[0], 0.25,
+        thetas=(30.0, 45.0, 60.0, 90.0, 120.0, 135.0, 150.0), rough_amp=rough)
+    assert abs(err).max() < 0.005
+
+
+def test_band_energy_against_hand_count():
+    assert pins.band_energy_error() < 1e-13
