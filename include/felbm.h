@@ -101,20 +101,30 @@ typedef struct {
   int32_t force_scheme;
 } felbm_params;
 
-/* Global FP64 reductions of the current state (Sec. III).
+/* Global FP64 reductions of the current state (Sec. III) and the state of
+ * the mass-matrix solve (end of Sec. II.C).
  *   mass     sum_i m_i C_i with m the lumped mass vector (int C dx)
  *   mean_ke  <T> = 0.5 sum_i rho_i |u_i|^2 / N (caption of the mobility figure)
  *   max_u    max_i |u_i|
  *   band_ke  mean of rho |u|^2 over nodes in the band set by felbm_set_band
  *            (the <rho u.u> of the parasitic-current table); 0 if unset
  *   band_nodes number of nodes in that band
- *   nonfinite 1 if any population is NaN/Inf                              */
+ *   nonfinite 1 if any population is NaN/Inf
+ *   solver_sweeps    K, the fixed number of preconditioned sweeps per step
+ *   solver_residual  relative residual of the most recently sampled solve
+ *                    (see felbm_set_residual_sampling): the largest over the
+ *                    18 systems of ||M11 x_K - b|| / ||b|| in the norm
+ *                    ||v||^2 = sum_i v_i^2 / m_i; -1 if none was sampled
+ *   residual_step    the step whose solve was sampled; -1 if none
+ * felbm_history fills the first eight members only (solver_* = 0 / -1).  */
 typedef struct {
   int64_t step;
   double mass, mean_ke, max_u, band_ke;
   int64_t band_nodes;
   int32_t nonfinite;
-  int32_t pad_;
+  int32_t solver_sweeps;
+  double solver_residual;
+  int64_t residual_step;
 } felbm_diag;
 
 /* Fields for felbm_read.  Nodal fields have N values, element fields E. */
@@ -203,6 +213,13 @@ int felbm_set_band(felbm_ctx* ctx, double xc, double yc, double R, double w);
 /* FP64 reductions of the current state.  Errors: EINVAL, ESTATE. */
 int felbm_diagnostics(felbm_ctx* ctx, felbm_diag* out);
 
+/* Sample the residual of the mass-matrix solve every `every` steps (every
+ * step whose index is a multiple of `every`); 0 (the default) disables it.
+ * A sampled step ends its solve with a plain sweep, an FP64 residual
+ * reduction and a separate update; its populations are bitwise those of an
+ * unsampled step.  Errors: EINVAL (every < 0). */
+int felbm_set_residual_sampling(felbm_ctx* ctx, int64_t every);
+
 /* Per-step history of the FP64 reductions computed inside the step (mass,
  * mean KE, max |u| of the state entering each step), most recent last.
  * Copies min(max_entries, available) records; *n_out receives the count. */
@@ -238,6 +255,16 @@ int felbm_bind_stream(felbm_ctx* ctx, void* hip_stream);
  * felbm_backward_host: the same with host arrays. */
 int felbm_forward_ckpt(felbm_ctx* ctx, int64_t n_steps, int64_t every);
 int felbm_backward(felbm_ctx* ctx, const double* dL_dC_dev, double* dL_domega_dev);
+
+/* Identifier (> 0) of the felbm_forward_ckpt run that felbm_backward would
+ * reverse, or 0 if there is none: every call that changes the state or the
+ * wetting field (felbm_set_wetting, felbm_init, felbm_step, felbm_step_async,
+ * felbm_step_debug, felbm_load_state, a failed felbm_forward_ckpt) discards
+ * the checkpoints, after which felbm_backward returns ESTATE.  A caller that
+ * keeps a run for later (an autograd graph) stores the identifier and checks
+ * it before reversing.  felbm_backward itself restores the run's final state
+ * on every exit path, including errors.  Errors: EINVAL (null). */
+int felbm_adjoint_run(const felbm_ctx* ctx, int64_t* run_id);
 int felbm_backward_host(felbm_ctx* ctx, const double* dL_dC, double* dL_domega);
 
 /* The same with a general seed (host arrays, caller order): dL/dpsi_bar of

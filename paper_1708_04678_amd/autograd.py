@@ -23,11 +23,15 @@ class WettingToComposition(torch.autograd.Function):
         sim.forward_ckpt(n_steps, every)
         C = torch.from_numpy(sim.read("C")).to(omega.device)
         ctx.sim = sim
+        ctx.run = sim.adjoint_run()
         return C
 
     @staticmethod
     def backward(ctx, grad_C: torch.Tensor):
         sim = ctx.sim
+        if sim.adjoint_run() != ctx.run:
+            raise RuntimeError("the Context was stepped, re-initialised or run forward again since this "
+                               "composition was computed; its checkpoints are gone (call composition_after again)")
         g = grad_C.detach().to(torch.float64).contiguous()
         out = torch.empty_like(g)
         sim.bind_stream(torch.cuda.current_stream(g.device).cuda_stream)

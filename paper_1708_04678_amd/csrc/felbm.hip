@@ -22,12 +22,12 @@ namespace {
 
 enum KernelId {
   K_MOMENTS = 0, K_REDUCE, K_GRAD, K_EFLUX, K_LAPC, K_GRADMU, K_LAPMU, K_NODEF, K_RHS, K_SWEEP_FIRST, K_SWEEP_MID,
-  K_SWEEP_LAST, K_ADJ_PREP, K_ADJ_FORCE, K_ADJ_STREAM, K_ADJ_GMU, K_ADJ_MU, K_ADJ_GC, K_ADJ_NODE, K_COUNT
+  K_SWEEP_LAST, K_ADJ_PREP, K_ADJ_FORCE, K_ADJ_STREAM, K_ADJ_GMU, K_ADJ_MU, K_ADJ_GC, K_ADJ_NODE, K_RESID, K_COUNT
 };
 const char* const kKernelNames[K_COUNT] = {"moments_collide", "reduce_final", "elem_grad", "edge_flux", "lapC_mu",
                                            "elem_gradmu", "elem_lapmu", "node_forces", "rhs_gather", "sweep_first",
                                            "sweep_mid", "sweep_last", "adj_prep", "adj_force", "adj_stream",
-                                           "adj_gmu", "adj_mu", "adj_gC", "adj_node"};
+                                           "adj_gmu", "adj_mu", "adj_gC", "adj_node", "residual"};
 
 struct KStat {
   int64_t launches = 0;
@@ -102,6 +102,11 @@ struct felbm_ctx {
   void* ck_buf = nullptr;     // checkpoints every ck_every steps
   void* seg_buf = nullptr;    // replayed states of one segment
   int64_t ck_steps = 0, ck_every = 0, ck_count = 0, ck_start = 0;
+  int64_t ck_run = 0, ck_next_run = 0;  // identifier of the run the checkpoints belong to (0 = none)
+  // sampled solver residual
+  int64_t residual_every = 0, residual_step = -1;
+  double* res_partials = nullptr;  // [2*18][grid]
+  double* res_out = nullptr;       // relative residual of the last sampled solve
   size_t ck_cap = 0, seg_cap = 0;
   // FP32 only: FP64 composition transport (remainder, rhs moment, iterates, diagonal)
   double *rC = nullptr, *fC = nullptr, *xCa = nullptr, *xCb = nullptr, *dlt = nullptr;
@@ -213,6 +218,13 @@ int harvest_timing(felbm_ctx* c) {
   return FELBM_OK;
 }
 
+// The checkpoints of a forward_ckpt run describe one trajectory; any call that
+// changes the state or the wetting field discards them.
+void invalidate_adjoint(felbm_ctx* c) {
+  c->ck_steps = 0;
+  c->ck_run = 0;
+}
+
 #define TRY(x)                   \
   do {                           \
     int r_ = (x);                \
@@ -294,10 +306,11 @@ int enqueue_rhs(felbm_ctx* c) {
 }
 
 template <typename real, int MODE>
-int sweep(felbm_ctx* c, int kid, const real* xin, real* xout, real w, const ConsArgs& cs) {
+int sweep(felbm_ctx* c, int kid, const real* xin, real* xout, real w, const ConsArgs& cs,
+          const real* fsrc = nullptr) {
   const int N = (int)c->N, Np = (int)c->Np;
   real* pop = (real*)c->pop;
-  const real* f = (const real*)c->f;
+  const real* f = fsrc ? fsrc : (const real*)c->f;
   if (c->use_lds) {
     TileArgs ta{c->tile_off, c->tslot, c->halo_off, c->halo, c->ntiles, c->tile_slots};
     return launch_sm(c, kid, k_sweep_dma<real, MODE>, (2 * c->ntiles + 7) / 8 * 8, BLOCK, sweep_dma_lds_bytes<real>(),
@@ -307,11 +320,57 @@ int sweep(felbm_ctx* c, int kid, const real* xin, real* xout, real w, const Cons
                 (const real*)c->sell_val, f, xin, xout, pop, (const uint8_t*)c->is_wall, w, cs);
 }
 
+// Residual of the solve: M-weighted norms of (A x - f) and f per population,
+// reduced in FP64 into c->res_out.
+template <typename real>
+int enqueue_residual(felbm_ctx* c, const real* x) {
+  const int gN = grid_for(c->N);
+  TRY(launch(c, K_RESID, k_residual<real>, gN, (int)c->N, (int)c->Np, (const int*)c->sell_ptr, (const int*)c->sell_col,
+             (const real*)c->sell_val, (const real*)c->f, x, (const double*)c->mass, c->res_partials));
+  return launch_bs(c, K_RESID, k_residual_final, 1, RBLOCK_RES, (const double*)c->res_partials, gN, c->res_out);
+}
+
+// The solve of a step whose residual is sampled: all K sweeps write their
+// iterate, the residual of x_K is reduced, then the update psi_hat + x_K and
+// the wall operator run as the no-sweep form with x_K (and its FP64
+// composition part) in place of f.  Bitwise the same update as the fused
+// last sweep.
+template <typename real>
+int enqueue_solve_sampled(felbm_ctx* c) {
+  const int K = c->prm.solver_sweeps;
+  real *xin = (real*)c->f, *xout = (real*)c->xa, *spare = (real*)c->xb;
+  double *cin = c->fC, *cout = c->xCa, *cspare = c->xCb;
+  ConsArgs cs{c->fC, nullptr, nullptr, c->dlt, c->Cn, c->rC, 0.0};
+  for (int j = 0; j < K; ++j) {
+    cs.w = c->cheb_w[j];
+    cs.xCin = cin;
+    cs.xCout = cout;
+    if (j == 0)
+      TRY((sweep<real, 0>(c, K_SWEEP_FIRST, nullptr, xout, (real)c->cheb_w[0], cs)));
+    else
+      TRY((sweep<real, 1>(c, K_SWEEP_MID, xin, xout, (real)c->cheb_w[j], cs)));
+    // the next sweep reads this iterate; the other buffer receives the next one
+    real* nx = j == 0 ? spare : xin;
+    double* ncx = j == 0 ? cspare : cin;
+    xin = xout;
+    cin = cout;
+    xout = nx;
+    cout = ncx;
+  }
+  TRY(enqueue_residual<real>(c, xin));
+  ConsArgs fin{cin, nullptr, nullptr, c->dlt, c->Cn, c->rC, 0.0};
+  return sweep<real, 4>(c, K_SWEEP_LAST, nullptr, nullptr, (real)0, fin, xin);
+}
+
 // K Chebyshev-step Richardson sweeps on f, then psi_bar^{n+1} = psi_hat + x_K
 // and the wall operator (fused into the last sweep)
 template <typename real>
 int enqueue_solve(felbm_ctx* c) {
   const int K = c->prm.solver_sweeps;
+  if (c->residual_every > 0 && c->step % c->residual_every == 0) {
+    c->residual_step = c->step;
+    return enqueue_solve_sampled<real>(c);
+  }
   real *xa = (real*)c->xa, *xb = (real*)c->xb;
   ConsArgs cs{c->fC, nullptr, nullptr, c->dlt, c->Cn, c->rC, 0.0};
   if (K == 0) return sweep<real, 4>(c, K_SWEEP_LAST, nullptr, nullptr, (real)0, cs);
@@ -638,6 +697,22 @@ int build_tiles(felbm_ctx* c, const MeshPrep& m) {
   return FELBM_OK;
 }
 
+// felbm_diag from a device reduction record (and, with a context, the solver
+// state of that context)
+void fill_diag(const felbm_ctx* c, const DiagRecord& r, double residual, felbm_diag* out) {
+  std::memset(out, 0, sizeof(*out));
+  out->step = r.step;
+  out->mass = r.mass;
+  out->mean_ke = r.mean_ke;
+  out->max_u = r.max_u;
+  out->band_ke = r.band_ke;
+  out->band_nodes = r.band_nodes;
+  out->nonfinite = r.nonfinite;
+  out->solver_sweeps = c ? c->prm.solver_sweeps : 0;
+  out->solver_residual = (c && c->residual_step >= 0) ? residual : -1.0;
+  out->residual_step = c ? c->residual_step : -1;
+}
+
 }  // namespace
 
 extern "C" {
@@ -769,6 +844,8 @@ int felbm_upload_mesh(felbm_ctx* c, int64_t n_nodes, const double* xy, int64_t n
     TRY(dalloc(c, &c->dlt, Np));
   }
   TRY(dalloc(c, &c->partials, (size_t)NRED * grid_for(N)));
+  TRY(dalloc(c, &c->res_partials, (size_t)NRES * grid_for(N)));
+  TRY(dalloc(c, &c->res_out, 1));
   TRY(dalloc(c, &c->hist, c->hist_cap));
   TRY(dalloc(c, &c->diag_now, 1));
   TRY(dalloc(c, &c->first_bad, 1));
@@ -868,6 +945,7 @@ int felbm_set_wetting(felbm_ctx* c, const double* omega_c) {
     if (kappa <= 0.0) return fail(c, FELBM_EINVAL, "set_wetting: a nonzero wetting potential needs kappa > 0");
     bc[i] = om * std::sqrt(2.0 * kappa * beta) / kappa;  // phi_c / kappa, Young: phi_c = Omega_c sqrt(2 kappa beta)
   }
+  invalidate_adjoint(c);
   TRY(upload(c, c->bc, bc));
   HIP_OK(c, hipStreamSynchronize(c->stream));
   return FELBM_OK;
@@ -891,6 +969,7 @@ int felbm_init(felbm_ctx* c, const double* C, const double* u, const double* p) 
   for (int64_t i = 0; i < N; ++i)
     if (!std::isfinite(hC[i]) || !std::isfinite(hU[2 * i]) || !std::isfinite(hU[2 * i + 1]) || !std::isfinite(hP[i]))
       return fail(c, FELBM_EINVAL, "init: non-finite input at node " + std::to_string(i));
+  invalidate_adjoint(c);
   double *dC = nullptr, *dU = nullptr, *dP = nullptr;
   HIP_OK(c, hipMallocAsync((void**)&dC, N * 8, c->stream));
   HIP_OK(c, hipMallocAsync((void**)&dU, 2 * N * 8, c->stream));
@@ -921,6 +1000,7 @@ int felbm_step_async(felbm_ctx* c, int64_t n) {
   if (!c) return FELBM_EINVAL;
   if (!c->has_state) return fail(c, FELBM_ESTATE, "step: not initialised");
   if (n < 0) return fail(c, FELBM_EINVAL, "step: negative step count");
+  if (n > 0) invalidate_adjoint(c);
   return enqueue_steps(c, n);
 }
 
@@ -979,6 +1059,7 @@ int felbm_read_populations(felbm_ctx* c, double* out) {
 int felbm_step_debug(felbm_ctx* c, double* psi_hat, double* rhs_over_m, double* delta) {
   if (!c) return FELBM_EINVAL;
   if (!c->has_state) return fail(c, FELBM_ESTATE, "step_debug: not initialised");
+  invalidate_adjoint(c);
   // the step's pipeline, split after the right-hand side to capture psi_hat and b/m
   TRY(enqueue_fields_any(c, true, true, c->hist + (c->step % c->hist_cap)));
   if (c->prm.precision == FELBM_FP64)
@@ -1032,7 +1113,7 @@ int felbm_diagnostics(felbm_ctx* c, felbm_diag* out) {
   if (!c) return FELBM_EINVAL;
   if (!c->has_state) return fail(c, FELBM_ESTATE, "diagnostics: not initialised");
   if (!out) return fail(c, FELBM_EINVAL, "diagnostics: null output");
-  static_assert(sizeof(DiagRecord) == sizeof(felbm_diag), "diag layout");
+
   const int gN = grid_for(c->N);
   const int N = (int)c->N, Np = (int)c->Np;
   int32_t* scratch_bad = nullptr;
@@ -1047,10 +1128,21 @@ int felbm_diagnostics(felbm_ctx* c, felbm_diag* out) {
                (float*)c->uxn, (float*)c->uyn, (const double*)c->mass, (const double*)c->xy, c->band, (const double*)c->rC, c->partials));
   TRY(launch_bs(c, K_REDUCE, k_reduce_final, 1, RBLOCK, (const double*)c->partials, gN, N, (int64_t)c->step, c->diag_now,
              scratch_bad));
-  HIP_OK(c, hipMemcpyAsync(out, c->diag_now, sizeof(felbm_diag), hipMemcpyDeviceToHost, c->stream));
+  DiagRecord rec;
+  double res = -1.0;
+  HIP_OK(c, hipMemcpyAsync(&rec, c->diag_now, sizeof(DiagRecord), hipMemcpyDeviceToHost, c->stream));
+  if (c->residual_step >= 0) HIP_OK(c, hipMemcpyAsync(&res, c->res_out, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIP_OK(c, hipFreeAsync(scratch_bad, c->stream));
   HIP_OK(c, hipStreamSynchronize(c->stream));
   if (c->timing) TRY(harvest_timing(c));
+  fill_diag(c, rec, res, out);
+  return FELBM_OK;
+}
+
+int felbm_set_residual_sampling(felbm_ctx* c, int64_t every) {
+  if (!c) return FELBM_EINVAL;
+  if (every < 0) return fail(c, FELBM_EINVAL, "set_residual_sampling: negative interval");
+  c->residual_every = every;
   return FELBM_OK;
 }
 
@@ -1064,7 +1156,7 @@ int felbm_history(felbm_ctx* c, felbm_diag* out, int64_t max_entries, int64_t* n
   if (n > 0) HIP_OK(c, hipMemcpy(all.data(), c->hist, c->hist_cap * sizeof(DiagRecord), hipMemcpyDeviceToHost));
   for (int64_t k = 0; k < n; ++k) {
     const int64_t s = c->step - n + k;
-    std::memcpy(&out[k], &all[s % c->hist_cap], sizeof(felbm_diag));
+    fill_diag(nullptr, all[s % c->hist_cap], -1.0, &out[k]);
   }
   *n_out = n;
   return FELBM_OK;
@@ -1104,6 +1196,7 @@ int felbm_load_state(felbm_ctx* c, const void* buf, int64_t bytes) {
   if (h.magic != kStateMagic || h.precision != c->prm.precision || h.n_nodes != c->N ||
       h.payload_bytes != payload_bytes(c) || h.perm_hash != c->perm_hash)
     return fail(c, FELBM_EINVAL, "load_state: header does not match this context");
+  invalidate_adjoint(c);
   const int64_t pb = 18 * c->Np * (int64_t)c->rs;
   HIP_OK(c, hipMemcpyAsync(c->pop, (const char*)buf + sizeof(h), pb, hipMemcpyHostToDevice, c->stream));
   if (c->rC) HIP_OK(c, hipMemcpyAsync(c->rC, (const char*)buf + sizeof(h) + pb, c->Np * 8, hipMemcpyHostToDevice, c->stream));
@@ -1157,6 +1250,7 @@ int felbm_forward_ckpt(felbm_ctx* c, int64_t n_steps, int64_t every) {
   if (n_steps < 1 || every < 1) return fail(c, FELBM_EINVAL, "forward_ckpt: n_steps and every must be >= 1");
   if (c->prm.force_scheme != FELBM_FORCES_MIXED)
     return fail(c, FELBM_EINVAL, "forward_ckpt: the adjoint covers the mixed force scheme only");
+  invalidate_adjoint(c);
   TRY(ensure_adjoint_buffers(c));
   const size_t sb = dev_state_bytes(c);
   const int64_t nck = (n_steps + every - 1) / every;
@@ -1176,7 +1270,6 @@ int felbm_forward_ckpt(felbm_ctx* c, int64_t n_steps, int64_t every) {
     if (hipMalloc(&c->seg_buf, need_seg) != hipSuccess) return fail(c, FELBM_ENOMEM, "forward_ckpt: segment storage");
     c->seg_cap = need_seg;
   }
-  c->ck_steps = n_steps;
   c->ck_every = every;
   c->ck_count = nck;
   c->ck_start = c->step;
@@ -1189,20 +1282,24 @@ int felbm_forward_ckpt(felbm_ctx* c, int64_t n_steps, int64_t every) {
   int32_t bad = -1;
   HIP_OK(c, hipMemcpy(&bad, c->first_bad, sizeof(int32_t), hipMemcpyDeviceToHost));
   if (bad >= 0) return fail(c, FELBM_ENONFINITE, "forward_ckpt: non-finite state entering step " + std::to_string(bad));
+  // the checkpoints are complete: this run can be reversed
+  c->ck_steps = n_steps;
+  c->ck_run = ++c->ck_next_run;
+  return FELBM_OK;
+}
+
+int felbm_adjoint_run(const felbm_ctx* c, int64_t* run_id) {
+  if (!c || !run_id) return FELBM_EINVAL;
+  *run_id = c->ck_steps > 0 ? c->ck_run : 0;
   return FELBM_OK;
 }
 
 namespace {
-// reverse the last forward_ckpt run from the seed already in c->lam
-int run_backward(felbm_ctx* c, double* dL_domega_dev) {
+// the reverse sweep over all segments, from the seed already in c->lam
+int backward_segments(felbm_ctx* c, double* dL_domega_dev) {
   const size_t sb = dev_state_bytes(c);
   const int N = (int)c->N;
   const int g1 = (N + BLOCK - 1) / BLOCK;
-  // the forward's final state, restored when done
-  void* final_state = nullptr;
-  HIP_OK(c, hipMallocAsync(&final_state, sb, c->stream));
-  TRY(state_to(c, final_state));
-  const int64_t end_step = c->step;
   HIP_OK(c, hipMemsetAsync(c->gomega, 0, c->Np * 8, c->stream));
   for (int64_t seg = c->ck_count - 1; seg >= 0; --seg) {
     const int64_t m0 = seg * c->ck_every, m1 = std::min(c->ck_steps, m0 + c->ck_every);
@@ -1222,12 +1319,37 @@ int run_backward(felbm_ctx* c, double* dL_domega_dev) {
   hipLaunchKernelGGL(k_to_caller, dim3(g1), dim3(BLOCK), 0, c->stream, N, (const int*)c->d_node_perm,
                      (const double*)c->gomega, dL_domega_dev);
   HIP_OK(c, hipGetLastError());
-  TRY(state_from(c, final_state));
-  HIP_OK(c, hipFreeAsync(final_state, c->stream));
-  c->step = end_step;
-  HIP_OK(c, hipStreamSynchronize(c->stream));
-  if (c->timing) TRY(harvest_timing(c));
   return FELBM_OK;
+}
+
+// Reverse the last forward_ckpt run.  The replay overwrites the state, so the
+// forward's final state and step counter are saved first and restored on
+// every exit path; the saved copy is freed on every path as well.  If even
+// the restoration fails, the context is marked as holding no state.
+int run_backward(felbm_ctx* c, double* dL_domega_dev) {
+  const size_t sb = dev_state_bytes(c);
+  void* final_state = nullptr;
+  HIP_OK(c, hipMallocAsync(&final_state, sb, c->stream));
+  const int64_t end_step = c->step;
+  int r = state_to(c, final_state);
+  if (r == FELBM_OK) {
+    r = backward_segments(c, dL_domega_dev);
+    const std::string err = c->err;
+    const int rr = state_from(c, final_state);
+    c->step = end_step;
+    if (rr != FELBM_OK) {
+      c->has_state = false;
+      invalidate_adjoint(c);
+      if (r == FELBM_OK) r = rr;
+    } else if (r != FELBM_OK) {
+      c->err = err;  // report the first failure
+    }
+  }
+  (void)hipFreeAsync(final_state, c->stream);
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (r == FELBM_OK && e != hipSuccess) r = fail(c, FELBM_EDEVICE, std::string("backward: ") + hipGetErrorString(e));
+  if (r == FELBM_OK && c->timing) r = harvest_timing(c);
+  return r;
 }
 }  // namespace
 

@@ -177,6 +177,7 @@ struct DiagRecord {  // mirrors felbm_diag
 // Second, fixed-order pass over the block partials (one block of RBLOCK
 // threads, four independent accumulators per thread to hide load latency).
 constexpr int RBLOCK = 1024;
+constexpr int RBLOCK_RES = 256;
 __global__ void __launch_bounds__(RBLOCK) k_reduce_final(const double* __restrict__ partials, int nblk, int N,
                                                           int64_t step, DiagRecord* __restrict__ out,
                                                           int* __restrict__ first_bad) {
@@ -220,6 +221,76 @@ __global__ void __launch_bounds__(RBLOCK) k_reduce_final(const double* __restric
     d.pad_ = 0;
     *out = d;
     if (d.nonfinite && *first_bad < 0) *first_bad = (int)step;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Residual of the mass-matrix solve (end of Sec. II.C) for a sampled step:
+// with f = b/m and A = diag(m)^-1 M11, M11 x - b = m (A x - f), so in the
+// norm ||v||^2 = sum_i v_i^2 / m_i the residual and the right-hand side are
+// sum_i m_i (A x - f)_i^2 and sum_i m_i f_i^2 per population.  Block partials
+// [2*18][nblk] in FP64, then one block forms max_a sqrt(res_a / rhs_a).
+// Uses the sliced-ELL copy of A (present for every mesh).
+// ----------------------------------------------------------------------------
+constexpr int NRES = 2 * NPOP;
+
+template <typename real>
+__global__ void __launch_bounds__(BLOCK) k_residual(int N, int Np, const int* __restrict__ sell_ptr,
+                                                   const int* __restrict__ sell_col, const real* __restrict__ sell_val,
+                                                   const real* __restrict__ f, const real* __restrict__ x,
+                                                   const double* __restrict__ mass, double* __restrict__ partials) {
+  const int blk = xcd_block();
+  const int i = blk * BLOCK + threadIdx.x;
+  double v[NRES];
+#pragma unroll
+  for (int k = 0; k < NRES; ++k) v[k] = 0.0;
+  if (i < N) {
+    double acc[NPOP];
+#pragma unroll
+    for (int a = 0; a < NPOP; ++a) acc[a] = 0.5 * (double)x[a * Np + i];
+    const int slice = i >> 6, lane = i & 63;
+    const int base = sell_ptr[slice], width = (sell_ptr[slice + 1] - base) >> 6;
+    for (int k = 0; k < width; ++k) {
+      const int idx = base + (k << 6) + lane;
+      const int j = sell_col[idx];
+      const double aij = (double)sell_val[idx];
+#pragma unroll
+      for (int a = 0; a < NPOP; ++a) acc[a] += aij * (double)x[a * Np + j];
+    }
+    const double m = mass[i];
+#pragma unroll
+    for (int a = 0; a < NPOP; ++a) {
+      const double fa = (double)f[a * Np + i], r = acc[a] - fa;
+      v[a] = m * r * r;
+      v[NPOP + a] = m * fa * fa;
+    }
+  }
+  block_reduce_store<NRES>(v, -1, partials, gridDim.x, blk);
+}
+
+__global__ void __launch_bounds__(RBLOCK_RES) k_residual_final(const double* __restrict__ partials, int nblk,
+                                                                double* __restrict__ out) {
+  __shared__ double red[NRES][RBLOCK_RES / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int k = 0; k < NRES; ++k) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += RBLOCK_RES) s += partials[(size_t)k * nblk + b];
+    s = wave_sum(s);
+    if (lane == 0) red[k][wid] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double worst = 0.0;
+    for (int a = 0; a < NPOP; ++a) {
+      double r = 0.0, fs = 0.0;
+      for (int w = 0; w < RBLOCK_RES / 64; ++w) {
+        r += red[a][w];
+        fs += red[NPOP + a][w];
+      }
+      const double rel = fs > 0.0 ? sqrt(r / fs) : (r > 0.0 ? INFINITY : 0.0);
+      worst = fmax(worst, rel);
+    }
+    *out = worst;
   }
 }
 

@@ -32,10 +32,11 @@ class Params(ct.Structure):
 
 class Diag(ct.Structure):
     _fields_ = [("step", ct.c_int64), ("mass", ct.c_double), ("mean_ke", ct.c_double), ("max_u", ct.c_double),
-                ("band_ke", ct.c_double), ("band_nodes", ct.c_int64), ("nonfinite", ct.c_int32), ("pad_", ct.c_int32)]
+                ("band_ke", ct.c_double), ("band_nodes", ct.c_int64), ("nonfinite", ct.c_int32),
+                ("solver_sweeps", ct.c_int32), ("solver_residual", ct.c_double), ("residual_step", ct.c_int64)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class KStat(ct.Structure):
@@ -73,6 +74,8 @@ _SIGNATURES = {
     "felbm_validate_mesh": ([ct.c_int64, _D, ct.c_int64, _I, ct.c_int64, _I, ct.c_double, ct.c_char_p, ct.c_int32],
                             ct.c_int),
     "felbm_forward_ckpt": ([_P, ct.c_int64, ct.c_int64], ct.c_int),
+    "felbm_adjoint_run": ([_P, ct.POINTER(ct.c_int64)], ct.c_int),
+    "felbm_set_residual_sampling": ([_P, ct.c_int64], ct.c_int),
     "felbm_backward": ([_P, ct.c_void_p, ct.c_void_p], ct.c_int),
     "felbm_backward_host": ([_P, _D, _D], ct.c_int),
     "felbm_lumped_mass": ([_P, _D], ct.c_int),
@@ -207,6 +210,10 @@ class Context:
         self._check(self._lib.felbm_diagnostics(self._h, ct.byref(d)))
         return d.as_dict()
 
+    def set_residual_sampling(self, every):
+        """Sample the solve's relative residual every `every` steps (0 = off)."""
+        self._check(self._lib.felbm_set_residual_sampling(self._h, int(every)))
+
     def history(self, max_entries=16384):
         buf = (Diag * max_entries)()
         n = ct.c_int64()
@@ -240,6 +247,12 @@ class Context:
     # -- adjoint ---------------------------------------------------------------
     def forward_ckpt(self, n_steps, every):
         self._check(self._lib.felbm_forward_ckpt(self._h, int(n_steps), int(every)))
+
+    def adjoint_run(self):
+        """Identifier of the forward_ckpt run that backward would reverse (0 = none)."""
+        v = ct.c_int64()
+        self._check(self._lib.felbm_adjoint_run(self._h, ct.byref(v)))
+        return v.value
 
     def backward(self, dL_dC_dev_ptr, dL_domega_dev_ptr):
         """Device pointers (ints) to N doubles each, caller node order."""

@@ -222,3 +222,54 @@ def test_torch_autograd_function():
     assert np.allclose(g_torch, g_ref, rtol=1e-12, atol=1e-15 * np.abs(g_ref).max())
     ctx.close()
     ref_ctx.close()
+
+
+def test_state_changes_discard_checkpoints():
+    """felbm_backward reverses only the run whose checkpoints are current:
+    stepping, re-initialising, changing the wetting field or loading a state
+    discards them (ESTATE), and the autograd binding refuses a stale graph."""
+    import torch
+
+    import paper_1708_04678_amd as felbm
+    from paper_1708_04678_amd.autograd import composition_after
+    mesh, phys, om, C0 = small_case(seed=8)
+    log("checkpoint invalidation")
+    ctx = make_ctx(mesh, phys, om)
+    ctx.init(C0)
+    assert ctx.adjoint_run() == 0
+    saved = ctx.save_state()
+    m = ctx.lumped_mass()
+    actions = [("step", lambda: ctx.step(1)), ("init", lambda: ctx.init(C0)), ("set_wetting", lambda: ctx.set_wetting(om)),
+               ("load_state", lambda: ctx.load_state(saved)), ("step_debug", lambda: ctx.step_debug())]
+    runs = []
+    for name, act in actions:
+        ctx.forward_ckpt(3, 2)
+        runs.append(ctx.adjoint_run())
+        assert runs[-1] > 0
+        ref = ctx.backward_host(m)                      # a reverse pass keeps the checkpoints
+        assert ctx.adjoint_run() == runs[-1]
+        assert np.array_equal(ctx.backward_host(m), ref)
+        act()
+        assert ctx.adjoint_run() == 0, name
+        with pytest.raises(felbm.FelbmError) as ei:
+            ctx.backward_host(m)
+        assert ei.value.name == "ESTATE", name
+    assert len(set(runs)) == len(runs)
+    # a reverse pass leaves the forward's final state in place
+    ctx.init(C0)
+    ctx.forward_ckpt(4, 3)
+    before = ctx.read_populations()
+    ctx.backward_host(m)
+    assert np.array_equal(ctx.read_populations(), before)
+    # autograd: a second forward on the same Context makes the first graph stale
+    dev = torch.device("cuda", 0)
+    omt = torch.tensor(om, dtype=torch.float64, device=dev, requires_grad=True)
+    C1 = composition_after(omt, ctx, C0, 3, 2)
+    C2 = composition_after(omt, ctx, C0, 3, 2)
+    w = torch.tensor(m, dtype=torch.float64, device=dev)
+    (w * C2).sum().backward()
+    assert omt.grad is not None
+    omt.grad = None
+    with pytest.raises(RuntimeError, match="checkpoints are gone"):
+        (w * C1).sum().backward()
+    ctx.close()

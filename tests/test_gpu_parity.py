@@ -341,3 +341,51 @@ def test_api_state_errors():
         ctx.init(bad)
     assert ei.value.name == "EINVAL"
     ctx.close()
+
+
+@pytest.mark.parametrize("prec,kernels", [("fp64", "auto"), ("fp32", "auto"), ("fp32", "global")])
+def test_residual_sampling_is_bitwise_neutral_and_bounded(cfg1_theta60, prec, kernels):
+    """A step whose solve residual is sampled gives bitwise the same state as an
+    unsampled one, and the sampled relative residual ||A x_K - f||_m / ||f||_m
+    obeys the Chebyshev bound (3/4) / T_K(5/3) of the K-sweep iterate from
+    x_0 = f on the spectrum [1/4, 1] (A = diag(m)^-1 M11 is self-adjoint in the
+    m inner product), up to the working precision's rounding floor."""
+    w, om, _ = cfg1_theta60
+    floor = 1e-13 if prec == "fp64" else 2e-6
+    for K in (0, 1, 2, 5, 11):
+        log(f"residual sampling {prec} {kernels} K={K}")
+        outs = []
+        for every in (0, 1):
+            ctx = make_ctx(w.mesh, w.phys, om, precision=prec, sweeps=K, kernels=kernels)
+            ctx.set_residual_sampling(every)
+            ctx.init(w.C0)
+            ctx.step(4)
+            d = ctx.diagnostics()
+            outs.append((ctx.read_populations(), ctx.read("C"), d))
+            ctx.close()
+        assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+        d0, d1 = outs[0][2], outs[1][2]
+        assert d0["solver_residual"] == -1.0 and d0["residual_step"] == -1 and d0["solver_sweeps"] == K
+        res = d1["solver_residual"]
+        bound = 0.75 / np.cosh(K * np.log(3.0))
+        log(f"  residual {res:.3e} bound {bound:.3e} (step {d1['residual_step']})")
+        assert d1["residual_step"] == 3
+        assert 0.0 < res <= 1.001 * bound + floor
+
+
+def test_residual_at_full_sweep_counts():
+    """At the bench's sweep counts the sampled residual reaches the rounding
+    floor of each precision (K = 26 in FP64, K = 11 in FP32 at the Chebyshev
+    bound 2e-6)."""
+    w = config(2)
+    om = wetting_from_angles(w.mesh, 60.0)
+    for prec, K, bar in (("fp64", 26, 1e-12), ("fp32", 11, 2e-5)):
+        log(f"residual at K={K} {prec}, workload 2")
+        ctx = make_ctx(w.mesh, w.phys, om, precision=prec, sweeps=K)
+        ctx.set_residual_sampling(5)
+        ctx.init(w.C0)
+        ctx.step(11)
+        d = ctx.diagnostics()
+        log(f"  residual {d['solver_residual']:.3e} at step {d['residual_step']}")
+        assert d["residual_step"] == 10 and 0.0 < d["solver_residual"] < bar
+        ctx.close()
