@@ -220,6 +220,19 @@ int felbm_diagnostics(felbm_ctx* ctx, felbm_diag* out);
  * unsampled step.  Errors: EINVAL (every < 0). */
 int felbm_set_residual_sampling(felbm_ctx* ctx, int64_t every);
 
+/* felbm_diagnostics for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same reductions, bitwise the same results, with the block
+ * partials, the reduced record and the non-finite flag in a fixed scratch
+ * array of 1.5 MiB per device, held until the process ends, instead of
+ * memory allocated per call.  Calls no allocating routine.  Every call on a
+ * device shares that device's scratch, so calls that overlap on one device
+ * (several host threads, or streams not ordered against each other) race.
+ * The last call's contents stay in the scratch.
+ * Errors: EINVAL (null output, or more than 8,388,608 nodes), ESTATE,
+ * EDEVICE. */
+int felbm_diagnostics_noalloc(felbm_ctx* ctx, felbm_diag* out);
+
 /* Per-step history of the FP64 reductions computed inside the step (mass,
  * mean KE, max |u| of the state entering each step), most recent last.
  * Copies min(max_entries, available) records; *n_out receives the count. */

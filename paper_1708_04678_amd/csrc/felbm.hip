@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -55,6 +56,49 @@ inline int grid_for(int64_t n) {
   int64_t b = (n + BLOCK - 1) / BLOCK;
   b = (b + 7) / 8 * 8;  // multiple of 8 for the XCD remap
   return (int)std::max<int64_t>(b, 8);
+}
+
+// Scratch of felbm_diagnostics_noalloc, which allocates nothing: the FP64
+// block partials of the reductions ([NRED][blocks], row stride the launch's
+// block count), then the reduced record and the non-finite flag.  Blocks of
+// 256 nodes, at most kNoAllocMaxBlocks of them: meshes of up to 8,388,608
+// nodes; 1.5 MiB per device, held until the process ends.  Every context on
+// a device shares that device's copy.
+constexpr int kNoAllocMaxBlocks = 32768;
+constexpr size_t kNoAllocRecordOffset = (size_t)NRED * kNoAllocMaxBlocks;  // in doubles
+constexpr size_t kNoAllocDoubles = kNoAllocRecordOffset + 16;              // record (56 B) + flag
+static_assert(sizeof(DiagRecord) + sizeof(int32_t) <= 16 * sizeof(double), "noalloc record slot");
+
+// Per-device address of `scratch`, taken once per device with that device
+// current (the array's name is only a host-side stand-in for it).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+namespace {
+
+// Called by felbm_create with the context's device current.
+int noalloc_scratch_for_current_device(int device, void** out, std::string& err) {
+  if (device < 0 || device >= kMaxDevices) {
+    err = "create: device index beyond the no-alloc scratch table";
+    return FELBM_EDEVICE;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      err = std::string("create: hipGetSymbolAddress of the no-alloc scratch failed: ") + hipGetErrorString(e);
+      return FELBM_EDEVICE;
+    }
+    g_scratch_dev[device] = ptr;
+  }
+  *out = g_scratch_dev[device];
+  return FELBM_OK;
 }
 
 }  // namespace
@@ -105,6 +149,7 @@ struct felbm_ctx {
   int64_t ck_run = 0, ck_next_run = 0;  // identifier of the run the checkpoints belong to (0 = none)
   // sampled solver residual
   int64_t residual_every = 0, residual_step = -1;
+  void* noalloc_scratch = nullptr;  // this device's address of the no-alloc scratch array
   double* res_partials = nullptr;  // [2*18][grid]
   double* res_out = nullptr;       // relative residual of the last sampled solve
   size_t ck_cap = 0, seg_cap = 0;
@@ -780,6 +825,11 @@ int felbm_create(const felbm_params* p, felbm_ctx** out) {
     return FELBM_EDEVICE;
   }
   c->stream = c->own_stream;
+  if (const int r = noalloc_scratch_for_current_device(c->device, &c->noalloc_scratch, g_create_error); r != FELBM_OK) {
+    (void)hipStreamDestroy(c->own_stream);
+    delete c;
+    return r;
+  }
   *out = c;
   return FELBM_OK;
 }
@@ -1136,6 +1186,42 @@ int felbm_diagnostics(felbm_ctx* c, felbm_diag* out) {
   HIP_OK(c, hipStreamSynchronize(c->stream));
   if (c->timing) TRY(harvest_timing(c));
   fill_diag(c, rec, res, out);
+  return FELBM_OK;
+}
+
+int felbm_diagnostics_noalloc(felbm_ctx* c, felbm_diag* out) {
+  if (!c) return FELBM_EINVAL;
+  if (!c->has_state) return fail(c, FELBM_ESTATE, "diagnostics_noalloc: not initialised");
+  if (!out) return fail(c, FELBM_EINVAL, "diagnostics_noalloc: null output");
+  const int gN = grid_for(c->N);
+  if (gN > kNoAllocMaxBlocks)
+    return fail(c, FELBM_EINVAL, "diagnostics_noalloc: " + std::to_string(c->N) + " nodes exceed the no-alloc scratch (at most " +
+                                     std::to_string((int64_t)kNoAllocMaxBlocks * BLOCK) + " nodes); use felbm_diagnostics");
+  if (!c->noalloc_scratch) return fail(c, FELBM_EDEVICE, "diagnostics_noalloc: no scratch address for this device");
+  const int N = (int)c->N, Np = (int)c->Np;
+  double* partials = static_cast<double*>(c->noalloc_scratch);
+  DiagRecord* rec = reinterpret_cast<DiagRecord*>(partials + kNoAllocRecordOffset);
+  int32_t* flag = reinterpret_cast<int32_t*>(rec + 1);
+  // the flag is written only where it is negative; 0 keeps it untouched (a
+  // fill kernel, not a memset node, so that a captured call replays it)
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->stream, flag, 1, 0);
+  if (c->prm.precision == FELBM_FP64)
+    hipLaunchKernelGGL((k_moments<double, false>), dim3(gN), dim3(BLOCK), 0, c->stream, (double*)c->pop, N, Np, c->sp,
+                       c->Cn, (double*)c->pn, (double*)c->uxn, (double*)c->uyn, (const double*)c->mass,
+                       (const double*)c->xy, c->band, (const double*)c->rC, partials);
+  else
+    hipLaunchKernelGGL((k_moments<float, false>), dim3(gN), dim3(BLOCK), 0, c->stream, (float*)c->pop, N, Np, c->sp,
+                       c->Cn, (float*)c->pn, (float*)c->uxn, (float*)c->uyn, (const double*)c->mass,
+                       (const double*)c->xy, c->band, (const double*)c->rC, partials);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RBLOCK), 0, c->stream, (const double*)partials, gN, N,
+                     (int64_t)c->step, rec, flag);
+  HIP_OK(c, hipGetLastError());
+  DiagRecord host;
+  double res = -1.0;
+  HIP_OK(c, hipMemcpyAsync(&host, rec, sizeof(DiagRecord), hipMemcpyDeviceToHost, c->stream));
+  if (c->residual_step >= 0) HIP_OK(c, hipMemcpyAsync(&res, c->res_out, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  fill_diag(c, host, res, out);
   return FELBM_OK;
 }
 

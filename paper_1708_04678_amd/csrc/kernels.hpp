@@ -1190,6 +1190,11 @@ __global__ void __launch_bounds__(BLOCK) k_init(int N, int Np, StepParams P, con
   if (Conserve<real>::on) rC[i] = c - sh;
 }
 
+__global__ void k_fill_i32(int32_t* __restrict__ p, int n, int32_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 template <typename real>
 __global__ void __launch_bounds__(BLOCK) k_to_double(int n, const real* __restrict__ in, double* __restrict__ out) {
   const int i = blockIdx.x * BLOCK + threadIdx.x;

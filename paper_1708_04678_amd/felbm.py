@@ -62,6 +62,7 @@ _SIGNATURES = {
     "felbm_step_debug": ([_P, _D, _D, _D], ct.c_int),
     "felbm_set_band": ([_P, ct.c_double, ct.c_double, ct.c_double, ct.c_double], ct.c_int),
     "felbm_diagnostics": ([_P, ct.POINTER(Diag)], ct.c_int),
+    "felbm_diagnostics_noalloc": ([_P, ct.POINTER(Diag)], ct.c_int),
     "felbm_history": ([_P, ct.POINTER(Diag), ct.c_int64, ct.POINTER(ct.c_int64)], ct.c_int),
     "felbm_state_bytes": ([_P], ct.c_int64),
     "felbm_save_state": ([_P, ct.c_void_p, ct.c_int64], ct.c_int),
@@ -208,6 +209,12 @@ class Context:
     def diagnostics(self):
         d = Diag()
         self._check(self._lib.felbm_diagnostics(self._h, ct.byref(d)))
+        return d.as_dict()
+
+    def diagnostics_noalloc(self):
+        """felbm_diagnostics without device allocation (fixed per-device scratch)."""
+        d = Diag()
+        self._check(self._lib.felbm_diagnostics_noalloc(self._h, ct.byref(d)))
         return d.as_dict()
 
     def set_residual_sampling(self, every):
