@@ -23,12 +23,14 @@ namespace {
 
 enum KernelId {
   K_MOMENTS = 0, K_REDUCE, K_GRAD, K_EFLUX, K_LAPC, K_GRADMU, K_LAPMU, K_NODEF, K_RHS, K_SWEEP_FIRST, K_SWEEP_MID,
-  K_SWEEP_LAST, K_ADJ_PREP, K_ADJ_FORCE, K_ADJ_STREAM, K_ADJ_GMU, K_ADJ_MU, K_ADJ_GC, K_ADJ_NODE, K_RESID, K_COUNT
+  K_SWEEP_LAST, K_ADJ_PREP, K_ADJ_FORCE, K_ADJ_STREAM, K_ADJ_GMU, K_ADJ_MU, K_ADJ_GC, K_ADJ_NODE, K_RESID,
+  K_LAPC_OP, K_LAPMU_OP, K_COUNT
 };
 const char* const kKernelNames[K_COUNT] = {"moments_collide", "reduce_final", "elem_grad", "edge_flux", "lapC_mu",
                                            "elem_gradmu", "elem_lapmu", "node_forces", "rhs_gather", "sweep_first",
                                            "sweep_mid", "sweep_last", "adj_prep", "adj_force", "adj_stream",
-                                           "adj_gmu", "adj_mu", "adj_gC", "adj_node", "residual"};
+                                           "adj_gmu", "adj_mu", "adj_gC", "adj_node", "residual",
+                                           "lapC_mu_op", "lapmu_op"};
 
 struct KStat {
   int64_t launches = 0;
@@ -127,6 +129,11 @@ struct felbm_ctx {
   void *pop = nullptr, *f = nullptr, *xa = nullptr, *xb = nullptr;
   double *Cn = nullptr, *mu = nullptr, *lapC = nullptr, *gC = nullptr, *gmu = nullptr, *lapmu = nullptr;
   void *pn = nullptr, *uxn = nullptr, *uyn = nullptr, *gp = nullptr;
+  // precomputed operators of the chemical-potential chain (see k_lapC_mu_op, k_lapmu_op)
+  int32_t *lop_ptr = nullptr, *lop_col = nullptr, *wptr = nullptr, *eopp = nullptr;
+  int2* wab = nullptr;
+  double* wlen = nullptr;
+  void *lop_w = nullptr, *ew = nullptr;
   // LDS-tiled solve: per-tile halo lists and matrix rows with local slots
   bool use_lds = false;
   int ntiles = 0, tile_slots = 0;
@@ -288,15 +295,25 @@ void set_kernel_bytes(felbm_ctx* c) {
   c->kstat[K_LAPC].bytes = N * (4 + 8 + 8 + 8 + 8 + 8 + 8 * 2 + 4 * 2) + 3 * E * (4 + 8);
   c->kstat[K_GRADMU].bytes = E * (12 + 48 + 16) + N * 8;
   c->kstat[K_LAPMU].bytes = E * (12 + 48 + 16 + 8);
-  c->kstat[K_RHS].bytes = 2 * pops + N * (4 + 8 + 8 + 2 * s + 8) + 3 * E * 4 + E * (12 + 7 * s + 16 + 2 * s + 8);
+  c->kstat[K_RHS].bytes = 2 * pops + N * (4 + 8 + 8 + 3 * s + 8) + 3 * E * 4 + E * (12 + 7 * s + 56 + 8);
   const double cons = c->prm.precision == FELBM_FP32 ? 8.0 * N : 0.0;  // one FP64 composition vector
   c->kstat[K_SWEEP_FIRST].bytes = 2 * pops + mat + 3 * cons;
   c->kstat[K_SWEEP_MID].bytes = 3 * pops + mat + 4 * cons;
   c->kstat[K_SWEEP_LAST].bytes = 4 * pops + mat + N + 5 * cons;
 }
 
+// How much of the field chain to compute: the time step's path (the
+// precomputed operators: mu and lap mu only), the same with the nodal lap C
+// kept for read-back, or the element-array chain (element gradients of C, p
+// and mu, edge fluxes) that the adjoint and the nodal force scheme read.
+enum FieldMode { FIELDS_STEP = 0, FIELDS_READ = 1, FIELDS_FULL = 2 };
+
+FieldOps field_ops(felbm_ctx* c) {
+  return FieldOps{c->lop_ptr, c->lop_col, c->lop_w, c->wptr, c->wab, c->wlen, c->eopp, c->ew};
+}
+
 template <typename real>
-int enqueue_fields(felbm_ctx* c, bool collide, bool record, DiagRecord* rec_target) {
+int enqueue_fields(felbm_ctx* c, bool collide, bool record, DiagRecord* rec_target, int mode) {
   const int gN = grid_for(c->N), gE = grid_for(c->E);
   const int N = (int)c->N, Np = (int)c->Np, E = (int)c->E;
   real* pop = (real*)c->pop;
@@ -309,6 +326,16 @@ int enqueue_fields(felbm_ctx* c, bool collide, bool record, DiagRecord* rec_targ
   if (record)
     TRY(launch_bs(c, K_REDUCE, k_reduce_final, 1, RBLOCK, (const double*)c->partials, gN, N, (int64_t)c->step, rec_target,
                c->first_bad));
+  if (mode != FIELDS_FULL) {
+    const FieldOps op = field_ops(c);
+    if (mode == FIELDS_READ)
+      TRY(launch(c, K_LAPC_OP, k_lapC_mu_op<real, true>, gN, N, op, (const double*)c->Cn, (const double*)c->bc, c->sp,
+                 c->lapC, c->mu));
+    else
+      TRY(launch(c, K_LAPC_OP, k_lapC_mu_op<real, false>, gN, N, op, (const double*)c->Cn, (const double*)c->bc, c->sp,
+                 c->lapC, c->mu));
+    return launch(c, K_LAPMU_OP, k_lapmu_op<real>, gE, E, (const int*)c->tri, op, (const double*)c->mu, c->lapmu);
+  }
   TRY(launch(c, K_GRAD, k_elem_grad<real>, gE, E, (const int*)c->tri, (const double*)c->geo, (const double*)c->Cn,
              (const real*)c->pn, c->gC, (real*)c->gp));
   TRY(launch(c, K_EFLUX, k_edge_flux, gE, E, (const int*)c->tri, (const int*)c->enbr, (const double*)c->geo,
@@ -340,12 +367,12 @@ int enqueue_rhs(felbm_ctx* c) {
     TileArgs ta{c->tile_off, c->tslot, c->halo_off, c->halo, c->ntiles, c->tile_slots};
     const int grid = (c->ntiles + 7) / 8 * 8;
     return launch_sm(c, K_RHS, k_rhs_lds<real>, grid, BLOCK, rhs_lds_bytes<real>(), N, Np, E, ta,
-                     RhsTile{c->rhs_off, c->rhs_ent, c->gaos, c->gC, c->gp, c->lapmu}, (const double*)c->Cn,
+                     RhsTile{c->rhs_off, c->rhs_ent, c->gaos, c->lapmu}, (const double*)c->Cn, (const real*)c->pn,
                      (const real*)c->uxn, (const real*)c->uyn, (const double*)c->mu, (const real*)c->pop,
                      (const double*)c->mass, c->sp, (real*)c->f, c->fC);
   }
   return launch(c, K_RHS, k_rhs<real>, gN, N, Np, E, (const int*)c->n2e_ptr, (const int*)c->n2e, (const int*)c->tri,
-                (const real*)c->geor, (const double*)c->geo, (const double*)c->gC, (const real*)c->gp,
+                (const real*)c->geor, (const double*)c->geo, (const real*)c->pn,
                 (const double*)c->lapmu, (const double*)c->Cn, (const real*)c->uxn, (const real*)c->uyn,
                 (const double*)c->mu, (const real*)c->pop, (const double*)c->mass, c->sp, (real*)c->f, c->fC);
 }
@@ -439,9 +466,13 @@ int enqueue_solve(felbm_ctx* c) {
   return sweep<real, 2>(c, K_SWEEP_LAST, xin, nullptr, (real)c->cheb_w[K - 1], cs);
 }
 
+int step_field_mode(const felbm_ctx* c) {
+  return c->prm.force_scheme == FELBM_FORCES_NODAL ? FIELDS_FULL : FIELDS_STEP;
+}
+
 template <typename real>
 int enqueue_step(felbm_ctx* c) {
-  TRY(enqueue_fields<real>(c, true, true, c->hist + (c->step % c->hist_cap)));
+  TRY(enqueue_fields<real>(c, true, true, c->hist + (c->step % c->hist_cap), step_field_mode(c)));
   TRY(enqueue_rhs<real>(c));
   TRY(enqueue_solve<real>(c));
   c->step += 1;
@@ -458,9 +489,9 @@ int enqueue_steps(felbm_ctx* c, int64_t n) {
   return FELBM_OK;
 }
 
-int enqueue_fields_any(felbm_ctx* c, bool collide, bool record, DiagRecord* target) {
-  return c->prm.precision == FELBM_FP64 ? enqueue_fields<double>(c, collide, record, target)
-                                        : enqueue_fields<float>(c, collide, record, target);
+int enqueue_fields_any(felbm_ctx* c, bool collide, bool record, DiagRecord* target, int mode) {
+  return c->prm.precision == FELBM_FP64 ? enqueue_fields<double>(c, collide, record, target, mode)
+                                        : enqueue_fields<float>(c, collide, record, target, mode);
 }
 
 int to_double(felbm_ctx* c, const void* src, double* dst_dev, int64_t n) {
@@ -604,6 +635,144 @@ int enqueue_adjoint_step_any(felbm_ctx* c) {
   return c->prm.precision == FELBM_FP64 ? enqueue_adjoint_step<double>(c) : enqueue_adjoint_step<float>(c);
 }
 
+// The precomputed operators of the chemical-potential chain, assembled in FP64
+// from the element geometry: the node rows of the patch Laplacian of C with
+// averaged outer-edge gradients (eqn:lapl_int_mp) divided by the patch
+// volume, the wall edges of each patch (eq. bc2 flux), and the six weights of
+// the element Laplacian of mu (Sec. II.D).  Stored in the working precision.
+template <typename wreal>
+int build_field_operators(felbm_ctx* c, const MeshPrep& m, const std::vector<double>& pvol) {
+  const int64_t N = m.N, Np = m.Np, E = m.E;
+  auto A = [&](int64_t e) { return m.geo[e]; };
+  auto gx = [&](int64_t e, int v) { return m.geo[(1 + 2 * v) * E + e]; };
+  auto gy = [&](int64_t e, int v) { return m.geo[(2 + 2 * v) * E + e]; };
+  // node rows: (column, weight) in first-appearance order, own node dropped
+  std::vector<int32_t> rptr(N + 1, 0), rcol;
+  std::vector<double> rval;
+  std::vector<int32_t> wptr(N + 1, 0);
+  std::vector<int2> wab;
+  std::vector<double> wlen;
+  std::vector<std::pair<int32_t, double>> row;
+  for (int64_t k = 0; k < N; ++k) {
+    row.clear();
+    auto add = [&](int32_t node, double w) {
+      for (auto& pr : row)
+        if (pr.first == node) {
+          pr.second += w;
+          return;
+        }
+      row.push_back({node, w});
+    };
+    const double iv = 1.0 / pvol[k];
+    for (int32_t q = m.n2e_ptr[k]; q < m.n2e_ptr[k + 1]; ++q) {
+      const int64_t e = m.n2e[q] >> 2;
+      const int l = m.n2e[q] & 3;
+      const int64_t nb = m.enbr[l * E + e];
+      if (nb >= 0) {
+        // -2 A_e grad N_l . (grad C_e + grad C_nb) / 2
+        for (int v = 0; v < 3; ++v)
+          add(m.tri[v * E + e], -A(e) * (gx(e, l) * gx(e, v) + gy(e, l) * gy(e, v)) * iv);
+        for (int v = 0; v < 3; ++v)
+          add(m.tri[v * E + nb], -A(e) * (gx(e, l) * gx(nb, v) + gy(e, l) * gy(nb, v)) * iv);
+      } else {
+        const int32_t a = m.tri[((l + 1) % 3) * E + e], b = m.tri[((l + 2) % 3) * E + e];
+        wab.push_back(int2{a, b});
+        wlen.push_back(2.0 * A(e) * std::sqrt(gx(e, l) * gx(e, l) + gy(e, l) * gy(e, l)) * iv);
+      }
+    }
+    for (int w = 0; w < 2; ++w) {
+      const int32_t j = m.wall_nbr[w * N + k];
+      if (j >= 0) {
+        wab.push_back(int2{(int32_t)k, j});
+        wlen.push_back(m.wall_len[w * N + k] * iv);
+      }
+    }
+    wptr[k + 1] = (int32_t)wab.size();
+    for (auto& pr : row)
+      if (pr.first != (int32_t)k) {
+        rcol.push_back(pr.first);
+        rval.push_back(pr.second);
+      }
+    rptr[k + 1] = (int32_t)rcol.size();
+  }
+  // sliced ELL, slice height 64, padded with the node itself and weight 0
+  const int64_t nslices = Np / 64;
+  std::vector<int32_t> sptr(nslices + 1, 0), scol;
+  std::vector<wreal> sval;
+  int64_t true_nnz = 0;
+  for (int64_t sl = 0; sl < nslices; ++sl) {
+    int64_t width = 0;
+    for (int64_t i = sl * 64; i < std::min<int64_t>(N, (sl + 1) * 64); ++i) width = std::max<int64_t>(width, rptr[i + 1] - rptr[i]);
+    const size_t base = scol.size();
+    scol.resize(base + width * 64);
+    sval.resize(base + width * 64);
+    for (int64_t q = 0; q < width; ++q)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int64_t i = sl * 64 + lane, idx = base + q * 64 + lane;
+        const bool real_entry = i < N && q < rptr[i + 1] - rptr[i];
+        scol[idx] = real_entry ? rcol[rptr[i] + q] : (int32_t)std::min<int64_t>(i, N - 1);
+        sval[idx] = real_entry ? (wreal)rval[rptr[i] + q] : (wreal)0;
+        true_nnz += real_entry;
+      }
+    sptr[sl + 1] = (int32_t)scol.size();
+  }
+  // element rows: weights of mu_1 - mu_0, mu_2 - mu_0 and of the three vertices across the edges
+  std::vector<int32_t> eopp(3 * E);
+  std::vector<wreal> ew(5 * E);
+  for (int64_t e = 0; e < E; ++e) {
+    double wv[3] = {0, 0, 0}, wo[3] = {0, 0, 0};
+    int32_t opp[3] = {m.tri[e], m.tri[e], m.tri[e]};
+    for (int l = 0; l < 3; ++l) {
+      const int64_t nb = m.enbr[l * E + e];
+      if (nb < 0) continue;  // zero normal flux of grad mu through a wall (eqn:bc1)
+      for (int v = 0; v < 3; ++v) wv[v] -= gx(e, l) * gx(e, v) + gy(e, l) * gy(e, v);
+      for (int w = 0; w < 3; ++w) {
+        const int32_t node = m.tri[w * E + nb];
+        const double wt = -(gx(e, l) * gx(nb, w) + gy(e, l) * gy(nb, w));
+        int v = 0;
+        while (v < 3 && m.tri[v * E + e] != node) ++v;
+        if (v < 3) {
+          wv[v] += wt;
+        } else {
+          opp[l] = node;
+          wo[l] += wt;
+        }
+      }
+    }
+    ew[e] = (wreal)wv[1];
+    ew[E + e] = (wreal)wv[2];
+    for (int l = 0; l < 3; ++l) {
+      eopp[l * E + e] = opp[l];
+      ew[(2 + l) * E + e] = (wreal)wo[l];
+    }
+  }
+  TRY(dalloc(c, &c->lop_ptr, sptr.size()));
+  TRY(dalloc(c, &c->lop_col, scol.size()));
+  TRY(dalloc_bytes(c, &c->lop_w, sval.size() * sizeof(wreal)));
+  TRY(dalloc(c, &c->wptr, wptr.size()));
+  TRY(dalloc(c, &c->wab, std::max<size_t>(wab.size(), 1)));
+  TRY(dalloc(c, &c->wlen, std::max<size_t>(wlen.size(), 1)));
+  TRY(dalloc(c, &c->eopp, eopp.size()));
+  TRY(dalloc_bytes(c, &c->ew, ew.size() * sizeof(wreal)));
+  TRY(upload(c, c->lop_ptr, sptr));
+  TRY(upload(c, c->lop_col, scol));
+  HIP_OK(c, hipMemcpyAsync(c->lop_w, sval.data(), sval.size() * sizeof(wreal), hipMemcpyHostToDevice, c->stream));
+  TRY(upload(c, c->wptr, wptr));
+  if (!wab.empty()) {
+    TRY(upload(c, c->wab, wab));
+    TRY(upload(c, c->wlen, wlen));
+  }
+  TRY(upload(c, c->eopp, eopp));
+  HIP_OK(c, hipMemcpyAsync(c->ew, ew.data(), ew.size() * sizeof(wreal), hipMemcpyHostToDevice, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));  // host vectors are about to go out of scope
+  // algorithmic bytes: true entries (column + weight), C_k, the wall pointer, mu written;
+  // per element three vertex ids, three opposite ids, five weights, lap mu written
+  const double ws = (double)sizeof(wreal);
+  c->kstat[K_LAPC_OP].bytes = (double)true_nnz * (4 + ws) + (double)N * (8 + 4 + 8) + (double)wab.size() * (8 + 8);
+  c->kstat[K_LAPMU_OP].bytes = (double)E * (12 + 12 + 5 * ws + 8) + (double)N * 8;
+  return FELBM_OK;
+}
+
 // Per-tile incident-element entries of the LDS-staged right-hand side:
 // for node lane of tile t, entry k = (element * 4 + local vertex, LDS slots of
 // the element's three vertices), column-major per tile, padded with -1.  Every
@@ -657,13 +826,12 @@ int build_rhs_tiles(felbm_ctx* c, const MeshPrep& m, const std::vector<int32_t>&
   TRY(upload(c, c->gaos, gaos));
   HIP_OK(c, hipStreamSynchronize(c->stream));
   c->use_rhs_lds = true;
-  // algorithmic bytes: populations and nodal fields once per node (C, mu, u, mass),
-  // f (and, FP32, fC) written, the true entries, element data (FP64 geometry,
-  // grad C, grad p, lap mu)
+  // algorithmic bytes: populations and nodal fields once per node (C, mu, u, p, mass),
+  // f (and, FP32, fC) written, the true entries, element data (FP64 geometry, lap mu)
   const double Nd = (double)N, Ed = (double)E;
   const double s = (double)c->rs, cons = c->prm.precision == FELBM_FP32 ? 8.0 : 0.0;
-  c->kstat[K_RHS].bytes = 2 * 18 * Nd * s + Nd * (8 + 8 + 2 * s + 8 + cons) + (double)true_entries * 8 +
-                          Ed * (56 + 16 + 2 * s + 8) + (double)halo.size() * 4;
+  c->kstat[K_RHS].bytes = 2 * 18 * Nd * s + Nd * (8 + 8 + 3 * s + 8 + cons) + (double)true_entries * 8 +
+                          Ed * (56 + 8) + (double)halo.size() * 4;
   return FELBM_OK;
 }
 
@@ -915,6 +1083,10 @@ int felbm_upload_mesh(felbm_ctx* c, int64_t n_nodes, const double* xy, int64_t n
       for (int32_t q = m.n2e_ptr[k]; q < m.n2e_ptr[k + 1]; ++q) pvol[k] += m.geo[m.n2e[q] >> 2];
     TRY(upload(c, c->pvol, pvol));
     HIP_OK(c, hipStreamSynchronize(c->stream));
+    if (c->prm.precision == FELBM_FP64)
+      TRY(build_field_operators<double>(c, m, pvol));
+    else
+      TRY(build_field_operators<float>(c, m, pvol));
   }
   TRY(upload(c, c->xy, m.xy));
   TRY(upload(c, c->sell_ptr, m.sell_ptr));
@@ -1069,7 +1241,7 @@ int felbm_read(felbm_ctx* c, int32_t field, double* out) {
   if (!c->has_state) return fail(c, FELBM_ESTATE, "read: not initialised");
   if (!out) return fail(c, FELBM_EINVAL, "read: null output");
   if (field < FELBM_FIELD_C || field > FELBM_FIELD_LAPMU) return fail(c, FELBM_EINVAL, "read: unknown field");
-  TRY(enqueue_fields_any(c, false, false, nullptr));
+  TRY(enqueue_fields_any(c, false, false, nullptr, FIELDS_READ));
   const int64_t N = c->N;
   const double* src = nullptr;
   double* tmp = nullptr;
@@ -1111,7 +1283,7 @@ int felbm_step_debug(felbm_ctx* c, double* psi_hat, double* rhs_over_m, double* 
   if (!c->has_state) return fail(c, FELBM_ESTATE, "step_debug: not initialised");
   invalidate_adjoint(c);
   // the step's pipeline, split after the right-hand side to capture psi_hat and b/m
-  TRY(enqueue_fields_any(c, true, true, c->hist + (c->step % c->hist_cap)));
+  TRY(enqueue_fields_any(c, true, true, c->hist + (c->step % c->hist_cap), step_field_mode(c)));
   if (c->prm.precision == FELBM_FP64)
     TRY(enqueue_rhs<double>(c));
   else
@@ -1398,7 +1570,7 @@ int backward_segments(felbm_ctx* c, double* dL_domega_dev) {
     }
     for (int64_t m = m1 - 1; m >= m0; --m) {
       TRY(state_from(c, (const char*)c->seg_buf + (size_t)(m - m0) * sb));
-      TRY(enqueue_fields_any(c, false, false, nullptr));
+      TRY(enqueue_fields_any(c, false, false, nullptr, FIELDS_FULL));
       TRY(enqueue_adjoint_step_any(c));
     }
   }

@@ -381,6 +381,70 @@ __global__ void __launch_bounds__(BLOCK) k_lapC_mu(int N, int E, const int* __re
   mu[k] = 2.0 * P.beta * Ck * (Ck - 1.0) * (2.0 * Ck - 1.0) - P.kappa * L;
 }
 
+// ----------------------------------------------------------------------------
+// a3 and a4 as precomputed linear operators (the time step's path).  The
+// patch Laplacian with averaged outer-edge gradients (eqn:lapl_int_mp) is
+// linear in the nodal C of the node's patch and of the elements across its
+// outer edges; with the weights divided by the patch volume on the host,
+//   lap C_k = sum_j w_kj (C_j - C_k) + sum_{wall edges e of the patch} F_BC(e) / |Omega_k|
+// (difference form: sum_j w_kj = 0, so a constant field gives exactly 0).
+// Rows in sliced-ELL form (slice height 64, column-major), padded with the
+// node itself and weight 0; the wall edges of each patch in a short CSR list
+// (a, b, |e| / |Omega_k|).  The element Laplacian of mu (Sec. II.D) is linear
+// in mu at the element's vertices and at the three vertices across its edges:
+//   lap mu_T = w1 (mu_1 - mu_0) + w2 (mu_2 - mu_0) + sum_l w_opp,l (mu_opp,l - mu_0),
+// where an edge on a wall contributes nothing (eqn:bc1; its opposite slot
+// points at vertex 0 with weight 0).  Weights in the working precision
+// (wreal), arithmetic and values in FP64.
+// ----------------------------------------------------------------------------
+struct FieldOps {
+  const int* lop_ptr;   // [Np/64 + 1] slice offsets
+  const int* lop_col;   // [entries]
+  const void* lop_w;    // [entries] wreal
+  const int* wptr;      // [N+1] wall entries of each patch
+  const int2* wab;      // [wall entries] edge end nodes
+  const double* wlen;   // [wall entries] edge length / patch volume
+  const int* eopp;      // [3][E] vertex across the edge opposite local vertex l (vertex 0 on a wall edge)
+  const void* ew;       // [5][E] wreal
+};
+
+template <typename wreal, bool WRITE_LAPC>
+__global__ void __launch_bounds__(BLOCK) k_lapC_mu_op(int N, FieldOps op, const double* __restrict__ Cn,
+                                                     const double* __restrict__ bc, StepParams P,
+                                                     double* __restrict__ lapC, double* __restrict__ mu) {
+  const int k = xcd_block() * BLOCK + threadIdx.x;
+  if (k >= N) return;
+  const wreal* __restrict__ w = static_cast<const wreal*>(op.lop_w);
+  const double Ck = Cn[k];
+  const int slice = k >> 6, lane = k & 63;
+  const int base = op.lop_ptr[slice], width = (op.lop_ptr[slice + 1] - base) >> 6;
+  double acc = 0.0;
+#pragma unroll 4
+  for (int q = 0; q < width; ++q) {
+    const int idx = base + (q << 6) + lane;
+    acc += (double)w[idx] * (Cn[op.lop_col[idx]] - Ck);
+  }
+  for (int q = op.wptr[k]; q < op.wptr[k + 1]; ++q) {
+    const int2 ab = op.wab[q];
+    acc += wall_flux(Cn[ab.x], Cn[ab.y], bc[ab.x], bc[ab.y], op.wlen[q]);
+  }
+  if (WRITE_LAPC) lapC[k] = acc;
+  mu[k] = 2.0 * P.beta * Ck * (Ck - 1.0) * (2.0 * Ck - 1.0) - P.kappa * acc;
+}
+
+template <typename wreal>
+__global__ void __launch_bounds__(BLOCK) k_lapmu_op(int E, const int* __restrict__ tri, FieldOps op,
+                                                   const double* __restrict__ mu, double* __restrict__ lapmu) {
+  const int e = xcd_block() * BLOCK + threadIdx.x;
+  if (e >= E) return;
+  const wreal* __restrict__ w = static_cast<const wreal*>(op.ew);
+  const double m0 = mu[tri[e]];
+  const double d1 = mu[tri[E + e]] - m0, d2 = mu[tri[2 * E + e]] - m0;
+  const double o0 = mu[op.eopp[e]] - m0, o1 = mu[op.eopp[E + e]] - m0, o2 = mu[op.eopp[2 * E + e]] - m0;
+  lapmu[e] = (double)w[e] * d1 + (double)w[E + e] * d2 + (double)w[2 * E + e] * o0 + (double)w[3 * E + e] * o1 +
+             (double)w[4 * E + e] * o2;
+}
+
 // a4: element gradient of mu (P1) ...
 __global__ void __launch_bounds__(BLOCK) k_elem_gradmu(int E, const int* __restrict__ tri,
                                                       const double* __restrict__ geo, const double* __restrict__ mu,
@@ -421,7 +485,7 @@ template <typename real>
 __global__ void __launch_bounds__(BLOCK) k_rhs(int N, int Np, int E, const int* __restrict__ n2e_ptr,
                                               const int* __restrict__ n2e, const int* __restrict__ tri,
                                               const real* __restrict__ geor, const double* __restrict__ geo,
-                                              const double* __restrict__ gC, const real* __restrict__ gp,
+                                              const real* __restrict__ pn,
                                               const double* __restrict__ lapmu, const double* __restrict__ Cn,
                                               const real* __restrict__ uxn, const real* __restrict__ uyn,
                                               const double* __restrict__ mu, const real* __restrict__ pop,
@@ -460,8 +524,14 @@ __global__ void __launch_bounds__(BLOCK) k_rhs(int N, int Np, int E, const int* 
     const real ubx = (ux0 + ux1 + ux2) / (real)3, uby = (uy0 + uy1 + uy2) / (real)3;
     const double rhobd = Cb * P.rho_l + (1.0 - Cb) * P.rho_v;
     const real rhob = (real)rhobd;
-    const double gCx = gC[e], gCy = gC[E + e];
-    const real gpx = gp[e], gpy = gp[E + e];
+    // element gradients of the P1 fields C (FP64) and p (a2)
+    const double Cv0 = Cn[v[0]], Cv1 = Cn[v[1]], Cv2 = Cn[v[2]];
+    const double g0x = geo[E + e], g0y = geo[2 * E + e], g1x = geo[3 * E + e], g1y = geo[4 * E + e];
+    const double g2x = geo[5 * E + e], g2y = geo[6 * E + e];
+    const double gCx = Cv0 * g0x + Cv1 * g1x + Cv2 * g2x, gCy = Cv0 * g0y + Cv1 * g1y + Cv2 * g2y;
+    const real pv0 = pn[v[0]], pv1 = pn[v[1]], pv2 = pn[v[2]];
+    const real gpx = pv0 * (real)g0x + pv1 * (real)g1x + pv2 * (real)g2x;
+    const real gpy = pv0 * (real)g0y + pv1 * (real)g1y + pv2 * (real)g2y;
     const real ax = drho_cs2 * (real)gCx, ay = drho_cs2 * (real)gCy;          // c_s^2 grad rho
     const real bx = (real)(mub * gCx), by = (real)(mub * gCy);                // mu grad C
     const real coef = (real)Cb / (rhob * (real)CS2);
@@ -705,29 +775,29 @@ __device__ __forceinline__ void st_stream(T v, T* p) {
 // C, mu, u by ordinary loads.  Thread = node; its incident elements are
 // listed per tile column-major (entry k of lane l at ent_off[t] + k*256 + l):
 // x = element * 4 + local vertex (-1 = padding), y = LDS slots of the
-// element's vertices 0, 1, 2 (9 bits each).  Element data (geometry, grad C,
-// grad p, lap mu) is read from global memory; geometry in FP64 and rounded
-// to the working precision.  FP32 only: the FP64 zeroth h-moment uses
+// element's vertices 0, 1, 2 (9 bits each).  Element data (geometry as one
+// FP64 record, lap mu) is read from global memory, the geometry rounded to the
+// working precision where the arithmetic is; the element gradients of C and
+// p come from the staged vertex values.  FP32 only: the FP64 zeroth h-moment uses
 // div J = sum_a s_a, div Pi = sum_a e_a s_a with
 // s_a = sum_v (e_a . grad N_v) h_hat_{a,v}, in a vertex order that does not
 // depend on which vertex gathers, as in k_rhs.
 // ----------------------------------------------------------------------------
 template <typename real>
 constexpr unsigned rhs_lds_bytes() {
-  return NPOP * SLOTS1 * sizeof(real) + SLOTS1 * (8 + 8 + 2 * sizeof(real));
+  return NPOP * SLOTS1 * sizeof(real) + SLOTS1 * (8 + 8 + 3 * sizeof(real));
 }
 struct RhsTile {
   const int* ent_off;   // [ntiles+1]
   const int2* ent;      // [entries]
   const double* gaos;   // [E][8] FP64 element geometry {A, dN0/dx, dN0/dy, dN1/dx, dN1/dy, dN2/dx, dN2/dy, 0}
-  const double* gC;     // [2][E]
-  const void* gp;       // [2][E] in the working precision
   const double* lapmu;  // [E]
 };
 
 template <typename real>
 __global__ void __launch_bounds__(BLOCK) k_rhs_lds(int N, int Np, int E, TileArgs ta, RhsTile rt,
-                                                  const double* __restrict__ Cn, const real* __restrict__ uxn,
+                                                  const double* __restrict__ Cn, const real* __restrict__ pn,
+                                                  const real* __restrict__ uxn,
                                                   const real* __restrict__ uyn, const double* __restrict__ mu,
                                                   const real* __restrict__ pop, const double* __restrict__ mass,
                                                   StepParams P, real* __restrict__ f, double* __restrict__ fC) {
@@ -739,7 +809,7 @@ __global__ void __launch_bounds__(BLOCK) k_rhs_lds(int N, int Np, int E, TileArg
   double* mus = Cs + S;
   real* uxs = reinterpret_cast<real*>(mus + S);
   real* uys = uxs + S;
-  const real* __restrict__ gp = static_cast<const real*>(rt.gp);
+  real* pps = uys + S;
   const int t = xcd_block();
   if (t >= ta.ntiles) return;  // block-uniform
   const int lane = threadIdx.x;
@@ -772,6 +842,7 @@ __global__ void __launch_bounds__(BLOCK) k_rhs_lds(int N, int Np, int E, TileArg
     mus[lane] = mu[i];
     uxs[lane] = uxn[i];
     uys[lane] = uyn[i];
+    pps[lane] = pn[i];
   }
   if (lane < nh) {
     const int j = ta.halo[h0 + lane];
@@ -779,6 +850,7 @@ __global__ void __launch_bounds__(BLOCK) k_rhs_lds(int N, int Np, int E, TileArg
     mus[TILE + lane] = mu[j];
     uxs[TILE + lane] = uxn[j];
     uys[TILE + lane] = uyn[j];
+    pps[TILE + lane] = pn[j];
   }
   const double mi = valid ? mass[i] : 1.0;
   __builtin_amdgcn_s_waitcnt(0);  // this wave's LDS DMA has landed
@@ -824,15 +896,18 @@ __global__ void __launch_bounds__(BLOCK) k_rhs_lds(int N, int Np, int E, TileArg
     const real glb = l == 0 ? gxf[2] : (l == 1 ? gxf[0] : gxf[1]);
     const real hlb = l == 0 ? gyf[2] : (l == 1 ? gyf[0] : gyf[1]);
     // barycentric values of the P1 fields and the element gradients
-    const double Cb = (Cs[s0] + Cs[s1] + Cs[s2]) * (1.0 / 3.0);
+    const double Cb = (Cs[s0] + Cs[s1] + Cs[s2]) * (1.0 / 3.0);  // barycentric values
     const double mub = (mus[s0] + mus[s1] + mus[s2]) * (1.0 / 3.0);
     const real ux0 = uxs[s0], ux1 = uxs[s1], ux2 = uxs[s2];
     const real uy0 = uys[s0], uy1 = uys[s1], uy2 = uys[s2];
     const real ubx = (ux0 + ux1 + ux2) / (real)3, uby = (uy0 + uy1 + uy2) / (real)3;
     const double rhobd = Cb * P.rho_l + (1.0 - Cb) * P.rho_v;
     const real rhob = (real)rhobd;
-    const double gCx = rt.gC[e], gCy = rt.gC[E + e];
-    const real gpx = gp[e], gpy = gp[E + e];
+    // element gradients of the P1 fields C (FP64) and p (a2), from the staged vertex values
+    const double Cv0 = Cs[s0], Cv1 = Cs[s1], Cv2 = Cs[s2];
+    const double gCx = Cv0 * gxd[0] + Cv1 * gxd[1] + Cv2 * gxd[2], gCy = Cv0 * gyd[0] + Cv1 * gyd[1] + Cv2 * gyd[2];
+    const real pv0 = pps[s0], pv1 = pps[s1], pv2 = pps[s2];
+    const real gpx = pv0 * gxf[0] + pv1 * gxf[1] + pv2 * gxf[2], gpy = pv0 * gyf[0] + pv1 * gyf[1] + pv2 * gyf[2];
     const real ax = drho_cs2 * (real)gCx, ay = drho_cs2 * (real)gCy;  // c_s^2 grad rho
     const real bx = (real)(mub * gCx), by = (real)(mub * gCy);        // mu grad C
     const real coef = (real)Cb / (rhob * (real)CS2);
