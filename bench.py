@@ -11,9 +11,22 @@ timed region starts.
 
 Printed: one JSON line with MNUPS (mesh nodes x steps / s / 1e6, each node
 update advancing all 9 directions of both g and h) for the FP32 precision form
-(FP64 islands for the chemical-potential chain and reductions), the FP64 run of
-the same workload beside it, the roofline entry of the dominant kernel (the
-mass-matrix solve sweep) and the CPU oracle timed on a bounded sample.
+(FP64 chemical-potential chain, composition transport and reductions) at
+K = 11 solve sweeps, and beside it:
+  equal_error     FP32 and FP64 after the workload's 2000 steps against a
+                  converged FP64 solve (K = 40): max|u| (the spurious-current
+                  magnitude), band KE, max|C - C_ref|, mass drift and each
+                  droplet's apparent contact angle; FP64 at K = 8..13, the
+                  matched count being the fewest sweeps whose max|u| error is
+                  at most FP32's; the speedup at that count is the headline
+                  ratio;
+  fp64_rounding_floor  FP64 at K = 26 (each precision at its own floor);
+  roofline        the dominant kernel (the middle solve sweep) at the model's
+                  266 B per node, over its HIP-event launch time;
+  model_roofline  the whole step at the model's 2*18*4 + 100 + K (3*18*4 + 50)
+                  B per node over the timed step;
+  cpu_baseline    the CPU oracle timed on a bounded sample, one process and
+                  one process per host CPU.
 """
 import argparse
 import hashlib
@@ -67,6 +80,76 @@ def timed_run(torch, ctx, warmup, steps):
     ms = t0.elapsed_time(t1)
     ctx.step(0)
     return ms
+
+
+def model_bytes(s, K):
+    """Algorithmic HBM bytes per node of the step's model: read and write the 18
+    populations (2 * 18 * s), the mesh data (about 100 B), and per solve sweep
+    the gathered iterate read, the right-hand side read and the new iterate
+    written (3 * 18 * s) plus about 50 B of matrix entries and indices."""
+    return 2 * 18 * s + 100 + K * (3 * 18 * s + 50)
+
+
+def sweep_model_bytes(s):
+    return 3 * 18 * s + 50
+
+
+def droplet_angles(w, ctx):
+    """Apparent contact angle of each droplet of the workload from a circle fitted
+    to its C = 0.5 contour above the wall roughness (analysis.cap_fit_angle),
+    measured against the mean wall line y = 0."""
+    from paper_1708_04678_amd.analysis import cap_fit_angle
+    C = ctx.read("C")
+    out = []
+    for (xc, yc, R) in w.droplets:
+        out.append(cap_fit_angle(w.mesh.xy, w.mesh.tri, C, w.mesh.period_x, x_window=(xc - 2 * R, xc + 2 * R),
+                                 y_min=10.0)[0])
+    return out, C
+
+
+def precision_comparison(felbm, w, stream, sweeps32, k64_candidates, ref_sweeps=40, steps=None):
+    """FP32 and FP64 against a converged FP64 solve after the workload's stated
+    step count: max|u| (the spurious-current magnitude), band KE, mass drift,
+    each droplet's apparent contact angle and max|C - C_ref|.  FP64 runs at each
+    candidate sweep count; the matched count is the fewest sweeps whose max|u|
+    error is at most FP32's."""
+    import numpy as np
+    steps = w.steps if steps is None else steps
+
+    def run(prec, K):
+        log(f"  {prec} K={K}: {steps} steps")
+        ctx, d0 = make_ctx(felbm, w, prec, K, stream)
+        ctx.step(steps)
+        d = ctx.diagnostics()
+        ang, C = droplet_angles(w, ctx)
+        ctx.close()
+        return {"d": d, "d0": d0, "angles": ang, "C": C}
+
+    ref = run("fp64", ref_sweeps)
+
+    def errors(r):
+        return {"max_u": r["d"]["max_u"],
+                "max_u_rel_err": abs(r["d"]["max_u"] - ref["d"]["max_u"]) / ref["d"]["max_u"],
+                "band_ke_rel_err": abs(r["d"]["band_ke"] - ref["d"]["band_ke"]) / max(ref["d"]["band_ke"], 1e-300),
+                "max_C_err": float(np.abs(r["C"] - ref["C"]).max()),
+                "theta_deg": [round(a, 4) for a in r["angles"]],
+                "theta_err_deg": [round(a - b, 5) for a, b in zip(r["angles"], ref["angles"])],
+                "mass_drift": abs(r["d"]["mass"] - r["d0"]["mass"]) / r["d0"]["mass"]}
+
+    e32 = errors(run("fp32", sweeps32))
+    e32["K"] = sweeps32
+    e64 = []
+    for K in k64_candidates:
+        e = errors(run("fp64", K))
+        e["K"] = K
+        e64.append(e)
+    ok = [e for e in e64 if e["max_u_rel_err"] <= e32["max_u_rel_err"]]
+    matched = min(ok, key=lambda e: e["K"]) if ok else max(e64, key=lambda e: e["K"])
+    return {"steps": steps, "reference": {"precision": "fp64", "K": ref_sweeps, "max_u": ref["d"]["max_u"],
+                                          "theta_deg": [round(a, 4) for a in ref["angles"]]},
+            "fp32": e32, "fp64": e64, "matched_fp64_K": matched["K"],
+            "rule": "FP64 at the fewest sweeps whose max|u| error against the converged FP64 solve is at most "
+                    "FP32's, both after the workload's stated step count"}
 
 
 def kernel_pass(ctx, steps):
@@ -340,32 +423,88 @@ def capillary_study(felbm, stream, sweeps32, samples=40, fill=0.75):
     return rows
 
 
-def cpu_baseline(cfg, rows, steps=2):
-    """The FP64 CPU oracle, as it stands, on the bottom `rows` node rows of the
-    same mesh (`steps` steps after one warm-up step)."""
+def _host_cpu():
+    """Host CPU description: /proc/cpuinfo model name, lscpu's model, sockets
+    and cores, nproc and the CPUs this process may run on."""
+    import subprocess
+    info = {"nproc": os.cpu_count()}
+    try:
+        info["cpus_allowed"] = len(os.sched_getaffinity(0))
+    except AttributeError:
+        info["cpus_allowed"] = os.cpu_count()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            info["model_name"] = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        info["model_name"] = ""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            k, _, v = ln.partition(":")
+            if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU max MHz"):
+                info["lscpu_" + k.strip().lower().replace(" ", "_").replace("(s)", "s")] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return info
+
+
+def _oracle_worker(cfg, rows, steps, barrier, out):
+    """One oracle process: build the bounded sample, one warm-up step, then
+    `steps` timed steps that start together with the other workers."""
     from oracle import Oracle
     from workloads import config
-    full_rows = config(cfg).mesh.nrows
     w = config(cfg, row_limit=rows)
     o = Oracle(w.mesh, w.phys, w.omega_c)
     g, h = o.init_state(w.C0)
     g, h = o.step(g, h)
+    if barrier is not None:
+        barrier.wait(timeout=900)
     c0, t0 = time.process_time(), time.perf_counter()
     for _ in range(steps):
         g, h = o.step(g, h)
-    wall = time.perf_counter() - t0
-    cpu = time.process_time() - c0
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as fh:
-            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
-    except OSError:
-        pass
-    return {"value": w.mesh.n_nodes * steps / wall / 1e6, "unit": "MNUPS", "cores": max(1, round(cpu / wall)),
-            "kind": "oracle", "seconds": round(wall, 2), "host_cpu": model,
-            "host_cpus_visible": os.cpu_count(),
-            "sample": f"{steps} steps (after 1 warm-up step) of the FP64 numpy/scipy oracle on the bottom {rows} of the "
-                      f"{full_rows} node rows of the same mesh ({w.mesh.n_nodes} nodes, same droplets and walls)"}
+    out.put((time.perf_counter() - t0, time.process_time() - c0, w.mesh.n_nodes))
+
+
+def _run_oracle_processes(ctx, n, cfg, rows, steps):
+    """n concurrent oracle processes (one task each), their timed steps started together."""
+    out = ctx.Queue()
+    barrier = ctx.Barrier(n) if n > 1 else None
+    ps = [ctx.Process(target=_oracle_worker, args=(cfg, rows, steps, barrier, out)) for _ in range(n)]
+    for p in ps:
+        p.start()
+    res = [out.get(timeout=1800) for _ in range(n)]
+    for p in ps:
+        p.join()
+    return res
+
+
+def cpu_baseline(cfg, rows, steps=2, max_procs=16):
+    """The FP64 CPU oracle, as it stands (numpy/scipy, one thread per process),
+    on a bounded sample: the bottom `rows` node rows of the same mesh.  First
+    one process alone (the one-thread figure), then one process per allowed
+    CPU (at most max_procs) running the same sample concurrently, with their
+    timed steps started together; the all-core throughput is the summed node
+    updates over the slowest process's time."""
+    import multiprocessing as mp
+    from workloads import config
+    full_rows = config(cfg).mesh.nrows
+    host = _host_cpu()
+    os.environ["OMP_NUM_THREADS"] = "1"       # one thread per oracle process
+    os.environ["OPENBLAS_NUM_THREADS"] = "1"
+    ctx = mp.get_context("spawn")
+    wall1, cpu1, nodes = _run_oracle_processes(ctx, 1, cfg, rows, steps)[0]
+    procs = max(1, min(max_procs, host.get("cpus_allowed") or 1))
+    res = _run_oracle_processes(ctx, procs, cfg, rows, steps)
+    wall_n = max(r[0] for r in res)
+    one = nodes * steps / wall1 / 1e6
+    allc = procs * nodes * steps / wall_n / 1e6
+    return {"value": allc, "unit": "MNUPS", "cores": procs, "kind": "oracle",
+            "one_thread_value": one, "one_thread_seconds": round(wall1, 2),
+            "seconds": round(wall_n, 2), "cpu_seconds_total": round(sum(r[1] for r in res) + cpu1, 1),
+            "host": host,
+            "sample": f"{steps} steps (after 1 warm-up step) of the FP64 numpy/scipy oracle on the bottom {rows} of "
+                      f"the {full_rows} node rows of the same mesh ({nodes} nodes, same droplets and walls); "
+                      f"one process alone, then {procs} concurrent processes (one thread each) on the same sample"}
 
 
 def main():
@@ -380,9 +519,11 @@ def main():
     ap.add_argument("--sweeps32", type=int, default=11, help="solver sweeps per step in FP32")
     ap.add_argument("--sweeps64", type=int, default=26, help="solver sweeps per step in FP64")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--compare-steps", type=int, default=0,
+                    help="steps of the FP32-vs-FP64 error comparison (default: the workload's stated count)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=349)
+    ap.add_argument("--cpu-rows", type=int, default=65)
     ap.add_argument("--spurious-table", type=float, default=0.0, metavar="T",
                     help="only run the parasitic-current comparison (mixed vs nodal forces, three resolutions) "
                          "up to physical time T and print it")
@@ -463,11 +604,14 @@ def main():
     d32 = c32.diagnostics()
     info = c32.mesh_info()
 
-    # dominant kernel: the launch type with the largest total time
+    # dominant kernel: the launch type with the largest total time, priced with
+    # the model's per-node sweep bytes (3 * 18 * 4 + 50 B in FP32) x nodes
     dom_name = max(stats, key=lambda k: stats[k]["total_ms"])
     dom = stats[dom_name]
     avg_ms = dom["total_ms"] / max(dom["launches"], 1)
-    achieved = dom["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
+    sweep_kernel = dom_name.startswith("sweep")
+    dom_bytes = sweep_model_bytes(4) * N if sweep_kernel else dom["bytes_per_launch"]
+    achieved = dom_bytes / (avg_ms * 1e-3) / 1e9
     traffic = None
     tfile = os.path.join(ROOT, "profiles", f"{dom_name}_traffic.json")
     if os.path.exists(tfile):
@@ -477,8 +621,16 @@ def main():
             traffic = t.get("hbm_bytes_per_launch")
     roofline = {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "avg_launch_us": round(avg_ms * 1e3, 2), "algorithmic_bytes_per_launch": dom["bytes_per_launch"]}
-    # whole step: the algorithmic bytes of every kernel of a step over the timed step
+                "avg_launch_us": round(avg_ms * 1e3, 2), "algorithmic_bytes_per_launch": dom_bytes,
+                "bytes_rule": ("model sweep bytes 3*18*4 + 50 = 266 B per node x nodes" if sweep_kernel
+                               else "the kernel's own byte count"),
+                "detailed_bytes_per_launch": dom["bytes_per_launch"]}
+    # whole step against the model's bytes (2*18*s + 100 + K (3*18*s + 50) per node)
+    b32 = model_bytes(4, args.sweeps32)
+    m_gbs = b32 * N / (ms32 / args.steps * 1e-3) / 1e9
+    model_roofline = {"bound": "hbm", "bytes_per_node_step": b32, "achieved": round(m_gbs, 1), "peak": HBM_PEAK_GBS,
+                      "unit": "GB/s", "frac": round(m_gbs / HBM_PEAK_GBS, 4)}
+    # and against the sum of every kernel's own byte count (includes the FP64 chain and composition transport)
     step_bytes = sum(v["bytes_per_launch"] * v["launches"] for v in stats.values()) / args.steps
     step_gbs = step_bytes / (ms32 / args.steps * 1e-3) / 1e9
     step_roofline = {"bound": "hbm", "algorithmic_bytes_per_step": round(step_bytes),
@@ -506,37 +658,48 @@ def main():
                    "solver_sweeps": args.sweeps32, "population_updates_per_s": round(18 * N * args.steps / (ms32 * 1e-3)),
                    "parallelism": "single GPU"},
         "roofline": roofline,
+        "model_roofline": model_roofline,
         "step_roofline": step_roofline,
         "kernels": kernels,
     }
-
-    if not args.no_fp64:
-        log("fp64 context")
-        c64, _ = make_ctx(felbm, w, "fp64", args.sweeps64, stream)
-        ms64 = timed_run(torch, c64, args.warmup, args.steps)
-        log(f"fp64 {ms64 / args.steps:.3f} ms/step")
-        c64.step(args.steps)  # same step count as the fp32 context (its kernel pass)
-        d64 = c64.diagnostics()
-        out["fp64"] = {"value": round(N * args.steps / (ms64 * 1e-3) / 1e6, 2), "ms_per_step": round(ms64 / args.steps, 4),
-                       "solver_sweeps": args.sweeps64}
-        out["fp32_vs_fp64"] = {
-            "speedup": round(ms64 / ms32, 3),
-            "step": d32["step"],
-            "max_u_fp32": d32["max_u"], "max_u_fp64": d64["max_u"],
-            "max_u_rel_diff": abs(d32["max_u"] - d64["max_u"]) / max(d64["max_u"], 1e-300),
-            "band_ke_rel_diff": abs(d32["band_ke"] - d64["band_ke"]) / max(d64["band_ke"], 1e-300),
-            "mass_rel_diff": abs(d32["mass"] - d64["mass"]) / d64["mass"],
-        }
-        c64.close()
     out["mass_drift_fp32"] = abs(d32["mass"] - d0["mass"]) / d0["mass"]
     c32.close()
+
+    if not args.no_fp64:
+        # equal spurious-current error: FP32 and FP64 against a converged FP64 solve after the
+        # workload's stated step count, FP64 at the fewest sweeps that match FP32's max|u| error
+        csteps = args.compare_steps or w.steps
+        log(f"precision comparison ({csteps} steps)")
+        cmp = precision_comparison(felbm, w, stream, args.sweeps32, list(range(args.sweeps32 - 3, args.sweeps32 + 3)),
+                                   steps=csteps)
+        k_eq = cmp["matched_fp64_K"]
+        timing64 = {}
+        for K in sorted({k_eq, args.sweeps64}):
+            log(f"fp64 context K={K}")
+            c64, _ = make_ctx(felbm, w, "fp64", K, stream)
+            ms64 = timed_run(torch, c64, args.warmup, args.steps)
+            log(f"fp64 K={K} {ms64 / args.steps:.3f} ms/step")
+            c64.close()
+            timing64[K] = ms64
+        out["equal_error"] = dict(cmp)
+        out["equal_error"].update({
+            "fp32_MNUPS": out["value"], "fp64_K": k_eq,
+            "fp64_MNUPS": round(N * args.steps / (timing64[k_eq] * 1e-3) / 1e6, 2),
+            "fp64_ms_per_step": round(timing64[k_eq] / args.steps, 4),
+            "speedup": round(timing64[k_eq] / ms32, 3)})
+        out["fp64_rounding_floor"] = {
+            "K": args.sweeps64, "MNUPS": round(N * args.steps / (timing64[args.sweeps64] * 1e-3) / 1e6, 2),
+            "ms_per_step": round(timing64[args.sweeps64] / args.steps, 4),
+            "speedup": round(timing64[args.sweeps64] / ms32, 3),
+            "model_bytes_per_node_step": model_bytes(8, args.sweeps64),
+            "note": "each precision at its own rounding floor (FP32 K = 11, FP64 K = 26): a secondary reading"}
 
     if not args.no_adjoint:
         log("adjoint (graded 1024x512, 2000 steps)")
         out["adjoint"] = adjoint_run(felbm, stream, args.sweeps32)
 
     if not args.no_cpu_baseline:
-        log(f"cpu baseline (oracle, bottom {args.cpu_rows} rows)")
+        log(f"cpu baseline (oracle, bottom {args.cpu_rows} rows, one process, then one per CPU)")
         out["cpu_baseline"] = cpu_baseline(args.config, args.cpu_rows)
     print(json.dumps(out), flush=True)
 
