@@ -54,6 +54,27 @@ Sec. III.A; force_scheme="nodal") is not specified in the paper beyond
   N3  nodal lap mu: the vertex-patch operator of eqn:lapl_int_mp applied to
       mu, with zero flux through wall edges (eqn:bc1);
   N4  F at node i: eq:G and eq:H with the nodal values of the fields.
+
+The comparison scheme of the authors' earlier work integrates the nodal force
+locally in the collision step instead (force_scheme="nodal_collide"):
+  NC1 the trapezoid rule of eqn::integrated is applied to F as to the BGK
+      term, and the new variable absorbs both: psi_bar = psi + dt/2 (Omega - F).
+      Then psi_bar(x + dt e, t + dt) = psi_hat(x, t) with the collision
+      psi_hat = psi_bar - (psi_bar - psi_eq + dt/2 F)/(tau + 1/2) + dt F,
+      and the streaming is eqn::stream without the force;
+  NC2 F at the nodes as in N2-N4;
+  NC3 the moments of psi_bar then carry half the force's moments:
+      rho u = sum e g_bar / c_s^2 + dt/2 mu grad C (first moment of F_g),
+      p = sum g_bar + dt/2 c_s^2 u . grad rho (zeroth moment of F_g);
+      C = sum h_bar + dt/2 M lap mu would make the composition implicit, so
+      the fields use C = sum h_bar and only the h equilibrium of the
+      collision uses C* = C + dt/2 M lap mu, which gives
+      sum_a h_hat = sum_a h_bar + dt M lap mu exactly (mass conserving);
+  NC4 wall nodes are at rest (the wall operator zeroes the first moments):
+      u = 0 there, F_g = 0 and F_h keeps its even part M lap mu w_a only;
+  NC5 initial state: at equilibrium Omega = 0, so psi_bar^0 = psi_eq - dt/2 F
+      with F from the given (C, u, p); for h only the part of F_h with zero
+      sum (the (e - u) . X Gamma term) is subtracted, so that sum h_bar^0 = C.
 """
 from __future__ import annotations
 
@@ -260,6 +281,12 @@ def collide(psi, psi_eq, tau):
     return psi - (psi - psi_eq) / (tau[:, None] + 0.5)
 
 
+def collide_with_force(psi, psi_eq, F, tau, dt):
+    """Collision with the force integrated locally (reading NC1):
+    psi_hat = psi_bar - (psi_bar - psi_eq + dt/2 F)/(tau + 0.5) + dt F."""
+    return psi - (psi - psi_eq + 0.5 * dt * F) / (tau[:, None] + 0.5) + dt * F
+
+
 def wall_operator(geo: Geometry, psi):
     """Reading R4: replace each opposite pair at wall nodes by the pair mean."""
     out = psi.copy()
@@ -441,8 +468,9 @@ def pcg(M, m, b, tol=1e-13, max_it=100):
 # ---------------------------------------------------------------------------
 class Oracle:
     def __init__(self, mesh, phys, omega_c, tol=1e-13, force_scheme="mixed"):
-        if force_scheme not in ("mixed", "nodal"):
-            raise ValueError("force_scheme is 'mixed' (P0 element forces) or 'nodal' (P1 nodal forces)")
+        if force_scheme not in ("mixed", "nodal", "nodal_collide"):
+            raise ValueError("force_scheme is 'mixed' (P0 element forces), 'nodal' (P1 nodal forces in the streaming "
+                             "step) or 'nodal_collide' (nodal forces integrated in the collision step)")
         self.force_scheme = force_scheme
         self.geo = Geometry(mesh)
         self.mat = Matrices(self.geo)
@@ -470,8 +498,32 @@ class Oracle:
         C = np.asarray(C)
         u = np.zeros((N, 2)) if u is None else np.asarray(u)
         p = np.zeros(N) if p is None else np.asarray(p)
-        g, h = equilibria(C, p, density(C, self.prm), u)
+        rho = density(C, self.prm)
+        g, h = equilibria(C, p, rho, u)
+        if self.force_scheme == "nodal_collide":
+            # reading NC5: psi_bar^0 = psi_eq - dt/2 F, with F from the given fields
+            geo, prm = self.geo, self.prm
+            gradC = element_gradient(geo, C)
+            mu = chemical_potential(prm, C, laplacian_C(geo, C, gradC, self.bc))
+            f = self._collision_forces(C, rho, u, mu, gradC, element_gradient(geo, p), element_gradient(geo, rho),
+                                       element_gradient(geo, mu))
+            odd_h = f["F_h"] - prm.mobility * f["lapmu_n"][:, None] * gamma(u)
+            odd_h[geo.is_wall_node] = 0.0
+            g = g - 0.5 * prm.dt * f["F_g"]
+            h = h - 0.5 * prm.dt * odd_h
         return wall_operator(self.geo, g), wall_operator(self.geo, h)
+
+    def _collision_forces(self, C, rho, u, mu, gradC, gradp, gradrho, gradmu):
+        """Nodal forces of the collision-step scheme (readings NC2, NC4)."""
+        geo, prm = self.geo, self.prm
+        wall = geo.is_wall_node
+        gradC_n, gradp_n, gradrho_n = (nodal_average(geo, x) for x in (gradC, gradp, gradrho))
+        lapmu_n = nodal_laplacian_mu(geo, mu, gradmu)
+        F_g, F_h = point_forces(prm, C, rho, u, mu, gradC_n, gradp_n, gradrho_n, lapmu_n)
+        F_g[wall] = 0.0
+        F_h[wall] = prm.mobility * lapmu_n[wall, None] * W[None, :]
+        return dict(gradC_n=gradC_n, gradp_n=gradp_n, gradrho_n=gradrho_n, lapmu_n=lapmu_n, F_g=F_g, F_h=F_h,
+                    C_star=C + 0.5 * prm.dt * prm.mobility * lapmu_n)
 
     def fields(self, g, h):
         """Everything the step derives from (g, h) before streaming."""
@@ -488,6 +540,16 @@ class Oracle:
                    gradp=gradp, gradrho=gradrho, tau=relaxation_time(C, prm))
         if self.force_scheme == "mixed":
             out["Phi_g"], out["Phi_h"] = element_forces(geo, prm, C, rho, u, mu, gradC, gradp, gradrho, lapmu)
+        elif self.force_scheme == "nodal_collide":
+            # reading NC3: the half-force moments of psi_bar; walls at rest (NC4)
+            wall = geo.is_wall_node
+            gradC_n, gradrho_n = nodal_average(geo, gradC), nodal_average(geo, gradrho)
+            u = u + (0.5 * prm.dt * mu / rho)[:, None] * gradC_n
+            u[wall] = 0.0
+            p = p + 0.5 * prm.dt * CS2 * (u[:, 0] * gradrho_n[:, 0] + u[:, 1] * gradrho_n[:, 1])
+            gradp = element_gradient(geo, p)
+            out.update(u=u, p=p, gradp=gradp)
+            out.update(self._collision_forces(C, rho, u, mu, gradC, gradp, gradrho, gradmu))
         else:
             gradC_n, gradp_n, gradrho_n = (nodal_average(geo, x) for x in (gradC, gradp, gradrho))
             lapmu_n = nodal_laplacian_mu(geo, mu, gradmu)
@@ -501,13 +563,22 @@ class Oracle:
         of readings N1-N4 for force_scheme="nodal"), the mass matrix solve and
         the wall operator."""
         f = self.fields(g, h)
-        g_eq, h_eq = equilibria(f["C"], f["p"], f["rho"], f["u"])
-        g_hat = collide(g, g_eq, f["tau"])
-        h_hat = collide(h, h_eq, f["tau"])
         dt = self.prm.dt
+        if self.force_scheme == "nodal_collide":
+            g_eq, h_eq = equilibria(f["C_star"], f["p"], f["rho"], f["u"])
+            g_hat = collide_with_force(g, g_eq, f["F_g"], f["tau"], dt)
+            h_hat = collide_with_force(h, h_eq, f["F_h"], f["tau"], dt)
+        else:
+            g_eq, h_eq = equilibria(f["C"], f["p"], f["rho"], f["u"])
+            g_hat = collide(g, g_eq, f["tau"])
+            h_hat = collide(h, h_eq, f["tau"])
         if self.force_scheme == "mixed":
             b_g = rhs(self.mat, dt, g_hat, f["Phi_g"])
             b_h = rhs(self.mat, dt, h_hat, f["Phi_h"])
+        elif self.force_scheme == "nodal_collide":
+            zero = np.zeros((self.geo.NT, Q))
+            b_g = rhs(self.mat, dt, g_hat, zero)
+            b_h = rhs(self.mat, dt, h_hat, zero)
         else:
             b_g = rhs_nodal(self.mat, dt, g_hat, f["F_g"])
             b_h = rhs_nodal(self.mat, dt, h_hat, f["F_h"])
@@ -538,6 +609,8 @@ class Oracle:
 
     def diagnostics(self, g, h, band=None):
         C, p, rho, u = moments(g.real, h.real, self.prm)
+        if self.force_scheme == "nodal_collide":
+            u = self.fields(g.real, h.real)["u"]
         uu = u[:, 0] ** 2 + u[:, 1] ** 2
         out = dict(mass=float(np.sum(self.mat.lumped * C)), mean_ke=float(0.5 * np.sum(rho * uu) / self.geo.N),
                    max_u=float(np.sqrt(uu.max())))

@@ -488,7 +488,7 @@ def relaxation_time_cases() -> float:
     return float(abs(t - ref).max())
 
 
-def shear_wave_viscosity_ratio(tau=2.0, n_steps=600) -> float:
+def shear_wave_viscosity_ratio(tau=2.0, n_steps=600, force_scheme="mixed") -> float:
     """Lowest channel shear mode u_x = U sin(pi y / H) between no-slip walls in
     single-phase liquid (C = 1): it decays at rate nu (pi/H)^2 with
     nu = c_s^2 tau dt (Sec. II.A).  Returns measured rate / nu (pi/H)^2."""
@@ -497,7 +497,7 @@ def shear_wave_viscosity_ratio(tau=2.0, n_steps=600) -> float:
     dt = 0.1
     phys = make_physics(sigma=0.01, m_rho=10, m_nu=1, dt=dt)
     phys.nu_l = fo.CS2 * tau * dt
-    o = fo.Oracle(mesh, phys, np.zeros(mesh.n_nodes))
+    o = fo.Oracle(mesh, phys, np.zeros(mesh.n_nodes), force_scheme=force_scheme)
     k = np.pi / H
     y = mesh.xy[:, 1]
     u = np.zeros((mesh.n_nodes, 2)); u[:, 0] = 1e-3 * np.sin(k * y)
@@ -650,7 +650,8 @@ def second_moment_error() -> float:
     return float(max(errs))
 
 
-def first_step_composition_error(h: float, rho_l: float = 3.0, rho_v: float = 1.0, p0: float = 2e-3) -> float:
+def first_step_composition_error(h: float, rho_l: float = 3.0, rho_v: float = 1.0, p0: float = 2e-3,
+                                 force_scheme: str = "mixed") -> float:
     """Composition change over the first step from rest (u = 0, populations at
     equilibrium) with mobility M = 0.  The continuum equations of Sec. II give
     dC/dt = -div(C u) and, with rho du/dt = -grad p + mu grad C at rest,
@@ -665,7 +666,7 @@ def first_step_composition_error(h: float, rho_l: float = 3.0, rho_v: float = 1.
     n = int(round(L / h))
     mesh = split_grid_mesh(8.0, uniform_rows(L, n + 1), int(round(8 / h)), seed=[5], jitter=0.0, diag="up")
     phys = make_physics(sigma=0.01, m_rho=rho_l / rho_v, m_nu=1, dt=0.1, mobility=0.0, rho_l=rho_l)
-    o = fo.Oracle(mesh, phys, np.zeros(mesh.n_nodes))
+    o = fo.Oracle(mesh, phys, np.zeros(mesh.n_nodes), force_scheme=force_scheme)
     k = 2 * np.pi / L
     y = mesh.xy[:, 1]
     g, hh = o.init_state(0.5 + 0.3 * np.cos(k * y), p=p0 * np.sin(k * y))
@@ -765,3 +766,57 @@ def band_energy_error() -> float:
     errs = [abs(d["band_ke"] - band_ref) / band_ref, abs(d["mean_ke"] - 0.5 * total / (17 * 32)) / (0.5 * total / (17 * 32)),
             abs(d["max_u"] - peak) / peak]
     return float(max(errs))
+
+
+# ---------------------------------------------------------------------------
+# Nodal forces integrated in the collision step (readings NC1-NC5)
+# ---------------------------------------------------------------------------
+def collision_step_moment_error() -> float:
+    """Trapezoid rule on the force (NC1) with the half-force moments of psi_bar
+    (NC3): over one collision the populations' moments change by dt times the
+    force's moments, sum_a (h_hat - h_bar) = dt M lap mu_n,
+    sum_a (g_hat - g_bar) = dt c_s^2 u . grad rho_n and
+    sum_a e_a (g_hat - g_bar) = dt c_s^2 mu grad C_n at every node off the walls
+    (the moments of eq:G and eq:H with sum Gamma = 1, sum (e - u) Gamma = 0,
+    sum e (e - u) Gamma = c_s^2 I); at wall nodes the first moment of g_hat
+    stays zero (NC4)."""
+    mesh = small_mesh()
+    phys = make_physics(sigma=0.01, m_rho=10, m_nu=2, dt=0.1)
+    from workloads import droplet_field, wetting_from_angles
+    o = fo.Oracle(mesh, phys, wetting_from_angles(mesh, 60.0), force_scheme="nodal_collide")
+    rng = np.random.default_rng(4)
+    C = droplet_field(mesh, [(8.0, 0.0, 4.0)], phys.xi)
+    g, h = o.init_state(C, u=rng.normal(0, 0.01, (mesh.n_nodes, 2)), p=rng.normal(0, 1e-3, mesh.n_nodes))
+    g, h = o.step(g, h)
+    _, _, f = o.step(g, h, return_fields=True)
+    dt, wall = phys.dt, o.geo.is_wall_node
+    inner = ~wall
+    e1 = abs((f["h_hat"] - h).sum(1) - dt * o.prm.mobility * f["lapmu_n"])[inner].max()
+    e2 = abs((f["g_hat"] - g).sum(1) - dt * fo.CS2 * (f["u"] * f["gradrho_n"]).sum(1))[inner].max()
+    first = np.stack([(f["g_hat"] - g) @ fo.E[:, 0], (f["g_hat"] - g) @ fo.E[:, 1]], 1)
+    e3 = abs(first - dt * fo.CS2 * f["mu"][:, None] * f["gradC_n"])[inner].max()
+    e4 = abs(np.stack([f["g_hat"] @ fo.E[:, 0], f["g_hat"] @ fo.E[:, 1]], 1)[wall]).max()
+    return float(max(e1, e2, e3, e4))
+
+
+def collision_step_mass_drift(steps=20) -> float:
+    mesh = small_mesh()
+    phys = make_physics(sigma=0.01, m_rho=10, m_nu=1, dt=0.1)
+    from workloads import droplet_field, wetting_from_angles
+    o = fo.Oracle(mesh, phys, wetting_from_angles(mesh, 60.0, 110.0), force_scheme="nodal_collide")
+    g, h = o.init_state(droplet_field(mesh, [(8.0, 0.0, 4.0)], phys.xi))
+    m0 = o.mass(h)
+    g, h = o.run(g, h, steps)
+    return float(abs(o.mass(h) - m0) / m0)
+
+
+def collision_step_static_drift(seed=3) -> float:
+    """The static interface of Sec. II.C with the collision-step nodal force: not
+    balanced (compare static_balance_drift)."""
+    mesh = small_mesh(seed=seed)
+    phys = make_physics(sigma=0.0, m_rho=10, m_nu=1, dt=0.1, mobility=0.0)
+    o = fo.Oracle(mesh, phys, np.zeros(mesh.n_nodes), force_scheme="nodal_collide")
+    rng = np.random.default_rng(seed)
+    g, h = o.init_state(rng.uniform(0.0, 1.0, mesh.n_nodes))
+    g1, h1 = o.step(g, h)
+    return float(max(abs(h1 - h).max(), abs(g1 - g).max()) / abs(h).max())

@@ -180,6 +180,38 @@ def band_ke_doubled(self, g, h, band=None):
     return out
 
 
+_cwf = fo.collide_with_force
+
+
+def collide_force_no_half_shift(psi, psi_eq, F, tau, dt):
+    # the BGK term without the dt/2 F of the variable change (NC1)
+    return psi - (psi - psi_eq) / (tau[:, None] + 0.5) + dt * F
+
+
+_cforces = fo.Oracle._collision_forces
+
+
+def collision_forces_no_c_star(self, C, rho, u, mu, gradC, gradp, gradrho, gradmu):
+    out = _cforces(self, C, rho, u, mu, gradC, gradp, gradrho, gradmu)
+    out["C_star"] = C
+    return out
+
+
+def collision_forces_full_at_walls(self, C, rho, u, mu, gradC, gradp, gradrho, gradmu):
+    out = _cforces(self, C, rho, u, mu, gradC, gradp, gradrho, gradmu)
+    out["F_g"], out["F_h"] = fo.point_forces(self.prm, C, rho, u, mu, out["gradC_n"], out["gradp_n"],
+                                             out["gradrho_n"], out["lapmu_n"])
+    return out
+
+
+def init_without_half_force(self, C, u=None, p=None):
+    N = self.geo.N
+    u = np.zeros((N, 2)) if u is None else np.asarray(u)
+    p = np.zeros(N) if p is None else np.asarray(p)
+    g, h = fo.equilibria(np.asarray(C), p, fo.density(np.asarray(C), self.prm), u)
+    return fo.wall_operator(self.geo, g), fo.wall_operator(self.geo, h)
+
+
 MUTATIONS = [
     ("printed M10 sign", "rhs", rhs_printed_sign, lambda: pins.static_balance_drift() > 1e-8),
     ("dropped D term", "rhs", rhs_no_D, lambda: pins.advection_error() > 0.05),
@@ -213,6 +245,14 @@ MUTATIONS = [
     ("contact angle pi - theta", "contact_angle", contact_angle_supplement,
      lambda: abs(pins.contact_angle_cap_errors(lambda m, C: fo.contact_angle(m, C)[0], 0.5)).max() > 0.5),
     ("band energy doubled", "Oracle.diagnostics", band_ke_doubled, lambda: pins.band_energy_error() > 1e-6),
+    ("collision force without the dt/2 F shift", "collide_with_force", collide_force_no_half_shift,
+     lambda: pins.collision_step_moment_error() > 1e-8),
+    ("collision-step h equilibrium at C, not C*", "Oracle._collision_forces", collision_forces_no_c_star,
+     lambda: pins.collision_step_moment_error() > 1e-8),
+    ("collision-step force kept at wall nodes", "Oracle._collision_forces", collision_forces_full_at_walls,
+     lambda: pins.collision_step_moment_error() > 1e-8),
+    ("collision-step initial state without -dt/2 F", "Oracle.init_state", init_without_half_force,
+     lambda: pins.first_step_composition_error(0.25, force_scheme="nodal_collide") > 0.5),
 ]
 
 

@@ -185,3 +185,27 @@ def test_cap_fit_angle_on_exact_caps(rough):
 
 def test_band_energy_against_hand_count():
     assert pins.band_energy_error() < 1e-13
+
+
+def test_collision_step_force_moments():
+    # readings NC1, NC3, NC4: the collision adds dt times the force's moments
+    assert pins.collision_step_moment_error() < 1e-15
+
+
+def test_collision_step_scheme_conserves_mass():
+    assert pins.collision_step_mass_drift() < 1e-13
+
+
+def test_collision_step_scheme_first_step_converges():
+    # the same continuum first step as the mixed scheme; the nodal forces converge at second order
+    e1, e2 = pins.first_step_composition_error(0.5, force_scheme="nodal_collide"), \
+        pins.first_step_composition_error(0.25, force_scheme="nodal_collide")
+    assert e2 < 0.1 and e1 / e2 > 3.0
+
+
+def test_collision_step_forces_do_not_balance_static_interface():
+    assert pins.collision_step_static_drift() > 1e-4
+
+
+def test_collision_step_scheme_viscosity():
+    assert 0.98 < pins.shear_wave_viscosity_ratio(force_scheme="nodal_collide") < 1.08
