@@ -219,7 +219,12 @@ def comoving_band_ke(ctx, w, m, R, xi):
     return float(np.mean(rho[band] * (du[band] ** 2).sum(1))), (float(xc), float(yc)), (float(uc[0]), float(uc[1]))
 
 
-def spurious_table(felbm, stream, t_end, sweeps32, sweeps64, samples=16):
+SPURIOUS_RUNS = {"nodal_collide": ("nodal_collide", "fp64"), "nodal": ("nodal", "fp64"), "mixed": ("mixed", "fp64"),
+                 "mixed32": ("mixed", "fp32")}
+
+
+def spurious_table(felbm, stream, t_end, sweeps32, sweeps64, samples=16, runs=("nodal_collide", "nodal", "mixed",
+                                                                              "mixed32")):
     """Parasitic kinetic energy <rho u.u> in the band R +- xi of a static
     droplet (density ratio 2, equal viscosities) at three mesh resolutions,
     mixed (P0) against nodal (P1) forces: the 2-D analogue of the table of
@@ -228,14 +233,17 @@ def spurious_table(felbm, stream, t_end, sweeps32, sweeps64, samples=16):
     relaxation of the tanh profile), both in the fixed band about the initial
     centre and in the droplet's own frame (band about the current centroid,
     velocity relative to the droplet's mean velocity).  FP64 with 26 sweeps
-    for both schemes, plus the FP32 precision form of the mixed scheme."""
+    for the nodal force in the collision step (the scheme the paper compares
+    against), the nodal force in the streaming step and the mixed scheme,
+    plus the FP32 precision form of the mixed scheme."""
     from workloads import free_droplet
     rows = []
     for level in range(3):
         w = free_droplet(level, t_end)
         chunk = max(1, w.steps // samples)
         xc, yc, R = w.droplets[0]
-        for scheme, prec, k in (("nodal", "fp64", sweeps64), ("mixed", "fp64", sweeps64), ("mixed", "fp32", sweeps32)):
+        for scheme, prec in (SPURIOUS_RUNS[r] for r in runs):
+            k = sweeps64 if prec == "fp64" else sweeps32
             log(f"spurious-current table: level {level} ({w.mesh.n_nodes} nodes, {w.steps} steps), {scheme} {prec}")
             ctx, d0 = make_ctx(felbm, w, prec, k, stream, force_scheme=scheme)
             m = ctx.lumped_mass()
@@ -527,6 +535,8 @@ def main():
     ap.add_argument("--spurious-table", type=float, default=0.0, metavar="T",
                     help="only run the parasitic-current comparison (mixed vs nodal forces, three resolutions) "
                          "up to physical time T and print it")
+    ap.add_argument("--spurious-runs", default="nodal_collide,nodal,mixed,mixed32",
+                    help="comma-separated runs of --spurious-table: nodal_collide, nodal, mixed, mixed32")
     ap.add_argument("--contact-angle-sweep", type=float, default=0.0, metavar="T",
                     help="only run the equilibrium contact angle against the imposed wetting potential "
                          "(two contrasts, 30-150 deg, and a mesh-resolution study) up to physical time T")
@@ -567,7 +577,8 @@ def main():
     if args.spurious_table:
         tstream = torch.cuda.Stream()
         torch.cuda.set_stream(tstream)
-        rows = spurious_table(felbm, tstream.cuda_stream, args.spurious_table, args.sweeps32, args.sweeps64)
+        rows = spurious_table(felbm, tstream.cuda_stream, args.spurious_table, args.sweeps32, args.sweeps64,
+                              runs=tuple(args.spurious_runs.split(",")))
         print(json.dumps({"spurious_current_table": rows}))
         return
     if args.contact_angle_sweep:

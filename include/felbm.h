@@ -87,9 +87,19 @@ enum { FELBM_FP64 = 0, FELBM_FP32 = 1 };
  *                  parasitic-current table (Sec. III.A), forces as P1 fields
  *                  from nodal values and area-weighted nodal gradients, nodal
  *                  lap mu by the vertex-patch operator with zero wall flux;
- *                  FP64 only, no adjoint.                                    */
+ *                  FP64 only, no adjoint.  FELBM_FORCES_NODAL_COLLIDE: the
+ *                  same nodal forces integrated locally in the collision step
+ *                  (the authors' earlier scheme, Sec. II.C): trapezoid rule on
+ *                  the force, psi_bar = psi + dt/2 (Omega - F), collision
+ *                  psi_hat = psi_bar - (psi_bar - psi_eq + dt/2 F)/(tau + 1/2)
+ *                  + dt F, streaming without force; the velocity and pressure
+ *                  carry half the force's moments (rho u += dt/2 mu grad C,
+ *                  p += dt/2 c_s^2 u . grad rho), the h equilibrium uses
+ *                  C + dt/2 M lap mu, wall nodes are at rest, and felbm_init
+ *                  sets psi_bar = psi_eq - dt/2 F.  FP64 only, no adjoint, not
+ *                  for felbm_diagnostics_noalloc.                            */
 enum { FELBM_KERNELS_AUTO = 0, FELBM_KERNELS_GLOBAL = 1 };
-enum { FELBM_FORCES_MIXED = 0, FELBM_FORCES_NODAL = 1 };
+enum { FELBM_FORCES_MIXED = 0, FELBM_FORCES_NODAL = 1, FELBM_FORCES_NODAL_COLLIDE = 2 };
 
 typedef struct {
   double sigma, xi, mobility;
@@ -229,8 +239,8 @@ int felbm_set_residual_sampling(felbm_ctx* ctx, int64_t every);
  * device shares that device's scratch, so calls that overlap on one device
  * (several host threads, or streams not ordered against each other) race.
  * The last call's contents stay in the scratch.
- * Errors: EINVAL (null output, or more than 8,388,608 nodes), ESTATE,
- * EDEVICE. */
+ * Errors: EINVAL (null output, more than 8,388,608 nodes, or the
+ * collision-step nodal force scheme), ESTATE, EDEVICE. */
 int felbm_diagnostics_noalloc(felbm_ctx* ctx, felbm_diag* out);
 
 /* Per-step history of the FP64 reductions computed inside the step (mass,

@@ -123,6 +123,7 @@ struct felbm_ctx {
   double *geo = nullptr, *wall_len = nullptr, *bc = nullptr, *mass = nullptr, *xy = nullptr;
   double *pvol = nullptr, *eflux = nullptr;  // patch volume per node; edge fluxes [3][E]
   void* Fn = nullptr;                         // nodal forces [18][Np] (nodal force scheme)
+  double* lapmu_n = nullptr;                  // nodal lap mu [N] (collision-step nodal scheme)
   void *geor = nullptr, *sell_val = nullptr;
   uint8_t* is_wall = nullptr;
   // state and work buffers (device)
@@ -317,13 +318,15 @@ int enqueue_fields(felbm_ctx* c, bool collide, bool record, DiagRecord* rec_targ
   const int gN = grid_for(c->N), gE = grid_for(c->E);
   const int N = (int)c->N, Np = (int)c->Np, E = (int)c->E;
   real* pop = (real*)c->pop;
-  if (collide)
+  // the collision-step nodal scheme collides after its force fields (k_nc_collide)
+  const bool nc = c->prm.force_scheme == FELBM_FORCES_NODAL_COLLIDE;
+  if (collide && !nc)
     TRY(launch(c, K_MOMENTS, k_moments<real, true>, gN, pop, N, Np, c->sp, c->Cn, (real*)c->pn, (real*)c->uxn,
                (real*)c->uyn, (const double*)c->mass, (const double*)c->xy, c->band, (const double*)c->rC, c->partials));
   else
     TRY(launch(c, K_MOMENTS, k_moments<real, false>, gN, pop, N, Np, c->sp, c->Cn, (real*)c->pn, (real*)c->uxn,
                (real*)c->uyn, (const double*)c->mass, (const double*)c->xy, c->band, (const double*)c->rC, c->partials));
-  if (record)
+  if (record && !nc)
     TRY(launch_bs(c, K_REDUCE, k_reduce_final, 1, RBLOCK, (const double*)c->partials, gN, N, (int64_t)c->step, rec_target,
                c->first_bad));
   if (mode != FIELDS_FULL) {
@@ -350,6 +353,26 @@ int enqueue_fields(felbm_ctx* c, bool collide, bool record, DiagRecord* rec_targ
                   (const int*)c->enbr, (const double*)c->geo, (const double*)c->pvol, (const double*)c->gC,
                   (const real*)c->gp, (const double*)c->gmu, (const double*)c->Cn, (const real*)c->uxn,
                   (const real*)c->uyn, (const double*)c->mu, c->sp, (real*)c->Fn);
+  if (nc) {
+    // half-force moments of psi_bar (velocity and pressure), nodal lap mu, the
+    // reductions of the corrected fields; then grad p of the corrected pressure
+    TRY(launch(c, K_NODEF, k_nc_fields<real, true>, gN, N, E, (const int*)c->n2e_ptr, (const int*)c->n2e,
+               (const int*)c->enbr, (const double*)c->geo, (const double*)c->pvol, (const double*)c->gC,
+               (const double*)c->gmu, (const double*)c->Cn, (const double*)c->mu, (const uint8_t*)c->is_wall, c->sp,
+               (real*)c->pn, (real*)c->uxn, (real*)c->uyn, c->lapmu_n, (const double*)c->mass, (const double*)c->xy,
+               c->band, c->partials));
+    if (record)
+      TRY(launch_bs(c, K_REDUCE, k_reduce_final, 1, RBLOCK, (const double*)c->partials, gN, N, (int64_t)c->step,
+                    rec_target, c->first_bad));
+    TRY(launch(c, K_GRAD, k_elem_grad<real>, gE, E, (const int*)c->tri, (const double*)c->geo, (const double*)c->Cn,
+               (const real*)c->pn, c->gC, (real*)c->gp));
+    if (collide)
+      TRY(launch(c, K_NODEF, k_nc_collide<real, false>, gN, N, Np, E, (const int*)c->n2e_ptr, (const int*)c->n2e,
+                 (const double*)c->geo, (const double*)c->pvol, (const double*)c->gC, (const real*)c->gp,
+                 (const double*)c->Cn, (const real*)c->pn, (const real*)c->uxn, (const real*)c->uyn,
+                 (const double*)c->mu, (const double*)c->lapmu_n, (const uint8_t*)c->is_wall, c->sp, pop));
+    return FELBM_OK;
+  }
   TRY(launch(c, K_LAPMU, k_elem_lapmu, gE, E, (const int*)c->enbr, (const double*)c->geo, (const double*)c->gmu,
              c->lapmu));
   return FELBM_OK;
@@ -360,8 +383,12 @@ int enqueue_rhs(felbm_ctx* c) {
   const int gN = grid_for(c->N);
   const int N = (int)c->N, Np = (int)c->Np, E = (int)c->E;
   if (c->prm.force_scheme == FELBM_FORCES_NODAL)
-    return launch(c, K_RHS, k_rhs_nodal<real>, gN, N, Np, E, (const int*)c->n2e_ptr, (const int*)c->n2e,
+    return launch(c, K_RHS, k_rhs_nodal<real, true>, gN, N, Np, E, (const int*)c->n2e_ptr, (const int*)c->n2e,
                   (const int*)c->tri, (const double*)c->geo, (const real*)c->Fn, (const real*)c->pop,
+                  (const double*)c->mass, c->sp, (real*)c->f);
+  if (c->prm.force_scheme == FELBM_FORCES_NODAL_COLLIDE)  // the force acted in the collision
+    return launch(c, K_RHS, k_rhs_nodal<real, false>, gN, N, Np, E, (const int*)c->n2e_ptr, (const int*)c->n2e,
+                  (const int*)c->tri, (const double*)c->geo, (const real*)nullptr, (const real*)c->pop,
                   (const double*)c->mass, c->sp, (real*)c->f);
   if (c->use_rhs_lds) {
     TileArgs ta{c->tile_off, c->tslot, c->halo_off, c->halo, c->ntiles, c->tile_slots};
@@ -467,7 +494,40 @@ int enqueue_solve(felbm_ctx* c) {
 }
 
 int step_field_mode(const felbm_ctx* c) {
-  return c->prm.force_scheme == FELBM_FORCES_NODAL ? FIELDS_FULL : FIELDS_STEP;
+  return c->prm.force_scheme == FELBM_FORCES_MIXED ? FIELDS_STEP : FIELDS_FULL;
+}
+
+int read_field_mode(const felbm_ctx* c) {
+  return c->prm.force_scheme == FELBM_FORCES_MIXED ? FIELDS_READ : FIELDS_FULL;
+}
+
+// Initial state of the collision-step nodal scheme: psi_bar^0 = psi_eq - dt/2 F
+// with F from the initial fields (the populations hold psi_eq on entry).
+template <typename real>
+int enqueue_nc_init(felbm_ctx* c) {
+  const int gN = grid_for(c->N), gE = grid_for(c->E);
+  const int N = (int)c->N, Np = (int)c->Np, E = (int)c->E;
+  real* pop = (real*)c->pop;
+  TRY(launch(c, K_MOMENTS, k_moments<real, false>, gN, pop, N, Np, c->sp, c->Cn, (real*)c->pn, (real*)c->uxn,
+             (real*)c->uyn, (const double*)c->mass, (const double*)c->xy, c->band, (const double*)c->rC, c->partials));
+  TRY(launch(c, K_GRAD, k_elem_grad<real>, gE, E, (const int*)c->tri, (const double*)c->geo, (const double*)c->Cn,
+             (const real*)c->pn, c->gC, (real*)c->gp));
+  TRY(launch(c, K_EFLUX, k_edge_flux, gE, E, (const int*)c->tri, (const int*)c->enbr, (const double*)c->geo,
+             (const double*)c->gC, (const double*)c->Cn, (const double*)c->bc, c->eflux));
+  TRY(launch(c, K_LAPC, k_lapC_mu, gN, N, E, (const int*)c->n2e_ptr, (const int*)c->n2e, (const double*)c->eflux,
+             (const double*)c->pvol, (const double*)c->Cn, (const double*)c->bc, (const int*)c->wall_nbr,
+             (const double*)c->wall_len, c->sp, c->lapC, c->mu));
+  TRY(launch(c, K_GRADMU, k_elem_gradmu, gE, E, (const int*)c->tri, (const double*)c->geo, (const double*)c->mu,
+             c->gmu));
+  TRY(launch(c, K_NODEF, k_nc_fields<real, false>, gN, N, E, (const int*)c->n2e_ptr, (const int*)c->n2e,
+             (const int*)c->enbr, (const double*)c->geo, (const double*)c->pvol, (const double*)c->gC,
+             (const double*)c->gmu, (const double*)c->Cn, (const double*)c->mu, (const uint8_t*)c->is_wall, c->sp,
+             (real*)c->pn, (real*)c->uxn, (real*)c->uyn, c->lapmu_n, (const double*)c->mass, (const double*)c->xy,
+             c->band, c->partials));
+  return launch(c, K_NODEF, k_nc_collide<real, true>, gN, N, Np, E, (const int*)c->n2e_ptr, (const int*)c->n2e,
+                (const double*)c->geo, (const double*)c->pvol, (const double*)c->gC, (const real*)c->gp,
+                (const double*)c->Cn, (const real*)c->pn, (const real*)c->uxn, (const real*)c->uyn,
+                (const double*)c->mu, (const double*)c->lapmu_n, (const uint8_t*)c->is_wall, c->sp, pop);
 }
 
 template <typename real>
@@ -954,12 +1014,13 @@ int felbm_create(const felbm_params* p, felbm_ctx** out) {
     g_create_error = "create: kernels must be FELBM_KERNELS_AUTO or FELBM_KERNELS_GLOBAL";
     return FELBM_EINVAL;
   }
-  if (p->force_scheme != FELBM_FORCES_MIXED && p->force_scheme != FELBM_FORCES_NODAL) {
-    g_create_error = "create: force_scheme must be FELBM_FORCES_MIXED or FELBM_FORCES_NODAL";
+  if (p->force_scheme != FELBM_FORCES_MIXED && p->force_scheme != FELBM_FORCES_NODAL &&
+      p->force_scheme != FELBM_FORCES_NODAL_COLLIDE) {
+    g_create_error = "create: force_scheme must be FELBM_FORCES_MIXED, _NODAL or _NODAL_COLLIDE";
     return FELBM_EINVAL;
   }
-  if (p->force_scheme == FELBM_FORCES_NODAL && p->precision != FELBM_FP64) {
-    g_create_error = "create: the nodal force scheme is available in FP64 only";
+  if (p->force_scheme != FELBM_FORCES_MIXED && p->precision != FELBM_FP64) {
+    g_create_error = "create: the nodal force schemes are available in FP64 only";
     return FELBM_EINVAL;
   }
   if (p->solver_sweeps < 0 || p->solver_sweeps > 256) {
@@ -1054,6 +1115,7 @@ int felbm_upload_mesh(felbm_ctx* c, int64_t n_nodes, const double* xy, int64_t n
   TRY(dalloc(c, &c->lapmu, E));
   TRY(dalloc_bytes(c, &c->gp, 2 * E * rs));
   if (c->prm.force_scheme == FELBM_FORCES_NODAL) TRY(dalloc_bytes(c, &c->Fn, 18 * Np * rs));
+  if (c->prm.force_scheme == FELBM_FORCES_NODAL_COLLIDE) TRY(dalloc(c, &c->lapmu_n, N));
   if (c->prm.precision == FELBM_FP32) {
     TRY(dalloc(c, &c->rC, Np));
     TRY(dalloc(c, &c->fC, Np));
@@ -1207,6 +1269,7 @@ int felbm_init(felbm_ctx* c, const double* C, const double* u, const double* p) 
     hipLaunchKernelGGL(k_init<float>, dim3(g), dim3(BLOCK), 0, c->stream, (int)N, (int)c->Np, c->sp, (const double*)dC,
                        (const double*)dU, (const double*)dP, (const uint8_t*)c->is_wall, (float*)c->pop, c->rC);
   HIP_OK(c, hipGetLastError());
+  if (c->prm.force_scheme == FELBM_FORCES_NODAL_COLLIDE) TRY(enqueue_nc_init<double>(c));
   HIP_OK(c, hipFreeAsync(dC, c->stream));
   HIP_OK(c, hipFreeAsync(dU, c->stream));
   HIP_OK(c, hipFreeAsync(dP, c->stream));
@@ -1241,7 +1304,7 @@ int felbm_read(felbm_ctx* c, int32_t field, double* out) {
   if (!c->has_state) return fail(c, FELBM_ESTATE, "read: not initialised");
   if (!out) return fail(c, FELBM_EINVAL, "read: null output");
   if (field < FELBM_FIELD_C || field > FELBM_FIELD_LAPMU) return fail(c, FELBM_EINVAL, "read: unknown field");
-  TRY(enqueue_fields_any(c, false, false, nullptr, FIELDS_READ));
+  TRY(enqueue_fields_any(c, false, false, nullptr, read_field_mode(c)));
   const int64_t N = c->N;
   const double* src = nullptr;
   double* tmp = nullptr;
@@ -1342,7 +1405,10 @@ int felbm_diagnostics(felbm_ctx* c, felbm_diag* out) {
   HIP_OK(c, hipMallocAsync((void**)&scratch_bad, sizeof(int32_t), c->stream));
   const int32_t zero = 0;
   HIP_OK(c, hipMemcpyAsync(scratch_bad, &zero, sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
-  if (c->prm.precision == FELBM_FP64)
+  if (c->prm.force_scheme == FELBM_FORCES_NODAL_COLLIDE)
+    // the velocity carries half the force's first moment: reduce the corrected fields
+    TRY(enqueue_fields_any(c, false, false, nullptr, FIELDS_FULL));
+  else if (c->prm.precision == FELBM_FP64)
     TRY(launch(c, K_MOMENTS, k_moments<double, false>, gN, (double*)c->pop, N, Np, c->sp, c->Cn, (double*)c->pn,
                (double*)c->uxn, (double*)c->uyn, (const double*)c->mass, (const double*)c->xy, c->band, (const double*)c->rC, c->partials));
   else
@@ -1365,6 +1431,8 @@ int felbm_diagnostics_noalloc(felbm_ctx* c, felbm_diag* out) {
   if (!c) return FELBM_EINVAL;
   if (!c->has_state) return fail(c, FELBM_ESTATE, "diagnostics_noalloc: not initialised");
   if (!out) return fail(c, FELBM_EINVAL, "diagnostics_noalloc: null output");
+  if (c->prm.force_scheme == FELBM_FORCES_NODAL_COLLIDE)
+    return fail(c, FELBM_EINVAL, "diagnostics_noalloc: not available for the collision-step nodal scheme");
   const int gN = grid_for(c->N);
   if (gN > kNoAllocMaxBlocks)
     return fail(c, FELBM_EINVAL, "diagnostics_noalloc: " + std::to_string(c->N) + " nodes exceed the no-alloc scratch (at most " +

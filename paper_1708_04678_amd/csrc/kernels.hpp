@@ -683,7 +683,7 @@ __global__ void __launch_bounds__(BLOCK) k_node_forces(int N, int Np, int E, con
 //   b_{a,i} += -A (dt/3 + dt^2/2 e_a . grad N_i) e_a . sum_v psi_hat_{a,v} grad N_v
 //            + dt A/12 (F_{a,i} + sum_v F_{a,v}) + dt^2/2 (e_a . grad N_i) A/3 sum_v F_{a,v}
 // (the consistent P1 mass and 1/2 int (e . grad phi_i) phi_j); f = b / m.
-template <typename real>
+template <typename real, bool FORCE>
 __global__ void __launch_bounds__(BLOCK) k_rhs_nodal(int N, int Np, int E, const int* __restrict__ n2e_ptr,
                                                     const int* __restrict__ n2e, const int* __restrict__ tri,
                                                     const double* __restrict__ geo, const real* __restrict__ Fn,
@@ -715,15 +715,166 @@ __global__ void __launch_bounds__(BLOCK) k_rhs_nodal(int N, int Np, int E, const
       const real s = pop[a * Np + v0] * (exa * gx[0] + eya * gy[0]) + pop[a * Np + v1] * (exa * gx[1] + eya * gy[1]) +
                      pop[a * Np + v2] * (exa * gx[2] + eya * gy[2]);
       const real enl = exa * gxl + eya * gyl;
-      const real F0 = Fn[a * Np + v0], F1 = Fn[a * Np + v1], F2 = Fn[a * Np + v2];
-      const real Fi = Fn[a * Np + i];
-      const real fsum = F0 + F1 + F2;
-      b[a] += -A * (c1 + c2 * enl) * s + dt * (A / (real)12) * (Fi + fsum) + c2 * enl * (A / (real)3) * fsum;
+      b[a] += -A * (c1 + c2 * enl) * s;
+      if (FORCE) {
+        const real F0 = Fn[a * Np + v0], F1 = Fn[a * Np + v1], F2 = Fn[a * Np + v2];
+        const real Fi = Fn[a * Np + i];
+        const real fsum = F0 + F1 + F2;
+        b[a] += dt * (A / (real)12) * (Fi + fsum) + c2 * enl * (A / (real)3) * fsum;
+      }
     }
   }
   const real inv_m = (real)(1.0 / mass[i]);
 #pragma unroll
   for (int a = 0; a < NPOP; ++a) f[a * Np + i] = b[a] * inv_m;
+}
+
+// ----------------------------------------------------------------------------
+// Nodal forces integrated in the collision step, the comparison scheme of the
+// authors' earlier work (parasitic-current table, Sec. III.A; Sec. II.C names
+// it).  The trapezoid rule of eqn::integrated is applied to the force as to
+// the BGK term, with psi_bar = psi + dt/2 (Omega - F), so that
+//   psi_hat = psi_bar - (psi_bar - psi_eq + dt/2 F)/(tau + 1/2) + dt F
+// and the streaming carries no force.  The moments of psi_bar then carry half
+// the force's: rho u = sum e g / c_s^2 + dt/2 mu grad C and
+// p = sum g + dt/2 c_s^2 u . grad rho; the fields use C = sum h, the h
+// equilibrium C* = C + dt/2 M lap mu (so sum h_hat = sum h_bar + dt M lap mu).
+// Nodal gradients are area-weighted patch means of the element gradients,
+// nodal lap mu the patch operator of eqn:lapl_int_mp with zero wall flux; wall
+// nodes are at rest: u = 0, F_g = 0, F_h = M lap mu w.  FP64.
+// ----------------------------------------------------------------------------
+template <typename real, bool CORRECT>
+__global__ void __launch_bounds__(BLOCK) k_nc_fields(int N, int E, const int* __restrict__ n2e_ptr, const int* __restrict__ n2e,
+                                                    const int* __restrict__ enbr, const double* __restrict__ geo,
+                                                    const double* __restrict__ pvol, const double* __restrict__ gC,
+                                                    const double* __restrict__ gmu, const double* __restrict__ Cn,
+                                                    const double* __restrict__ mu, const uint8_t* __restrict__ is_wall,
+                                                    StepParams P, real* __restrict__ pn, real* __restrict__ uxn,
+                                                    real* __restrict__ uyn, double* __restrict__ lapmu_n,
+                                                    const double* __restrict__ mass, const double* __restrict__ xy,
+                                                    Band band, double* __restrict__ partials) {
+  const int blk = xcd_block();
+  const int i = blk * BLOCK + threadIdx.x;
+  double red[NRED] = {0, 0, 0, 0, 0, 0};
+  if (i < N) {
+    double sCx = 0.0, sCy = 0.0, flux = 0.0;
+    for (int q = n2e_ptr[i]; q < n2e_ptr[i + 1]; ++q) {
+      const int packed = n2e[q];
+      const int e = packed >> 2, l = packed & 3;
+      const double A = geo[e];
+      sCx += A * gC[e];
+      sCy += A * gC[E + e];
+      const int nb = enbr[l * E + e];
+      if (nb >= 0) {
+        const double Gx = 0.5 * (gmu[e] + gmu[nb]), Gy = 0.5 * (gmu[E + e] + gmu[E + nb]);
+        flux += -2.0 * A * (geo[(1 + 2 * l) * E + e] * Gx + geo[(2 + 2 * l) * E + e] * Gy);
+      }
+    }
+    const double vol = pvol[i];
+    const double gCx = sCx / vol, gCy = sCy / vol;
+    lapmu_n[i] = flux / vol;
+    const double C = Cn[i];
+    const double rho = C * P.rho_l + (1.0 - C) * P.rho_v;
+    double ux = (double)uxn[i], uy = (double)uyn[i], p = (double)pn[i];
+    if (CORRECT) {
+      if (is_wall[i]) {
+        ux = 0.0;
+        uy = 0.0;
+      } else {
+        const double s = 0.5 * P.dt * mu[i] / rho;
+        ux += s * gCx;
+        uy += s * gCy;
+      }
+      p += 0.5 * P.dt * CS2 * (P.rho_l - P.rho_v) * (ux * gCx + uy * gCy);
+      uxn[i] = (real)ux;
+      uyn[i] = (real)uy;
+      pn[i] = (real)p;
+    }
+    const double uu = ux * ux + uy * uy;
+    red[0] = mass[i] * C;
+    red[1] = rho * uu;
+    red[2] = sqrt(uu);
+    if (band.enabled) {
+      double dx = xy[i] - band.xc;
+      if (band.period > 0) dx -= band.period * rint(dx / band.period);
+      const double dy = xy[N + i] - band.yc, d2 = dx * dx + dy * dy;
+      if (d2 >= band.r_lo2 && d2 <= band.r_hi2) {
+        red[3] = rho * uu;
+        red[4] = 1.0;
+      }
+    }
+    red[5] = (isfinite(C) && isfinite(p) && isfinite(uu)) ? 0.0 : 1.0;
+    if (red[5] != 0.0) red[2] = 0.0;
+  }
+  block_reduce_store<NRED>(red, 2, partials, gridDim.x, blk);
+}
+
+// INIT = false: the collision with the force.  INIT = true: the initial state
+// psi_bar^0 = psi_eq - dt/2 F (populations at equilibrium on entry); for h only
+// the part of F_h with zero sum, so that sum h_bar^0 = C.
+template <typename real, bool INIT>
+__global__ void __launch_bounds__(BLOCK) k_nc_collide(int N, int Np, int E, const int* __restrict__ n2e_ptr,
+                                                     const int* __restrict__ n2e, const double* __restrict__ geo,
+                                                     const double* __restrict__ pvol, const double* __restrict__ gC,
+                                                     const real* __restrict__ gp, const double* __restrict__ Cn,
+                                                     const real* __restrict__ pn, const real* __restrict__ uxn,
+                                                     const real* __restrict__ uyn, const double* __restrict__ mu,
+                                                     const double* __restrict__ lapmu_n,
+                                                     const uint8_t* __restrict__ is_wall, StepParams P,
+                                                     real* __restrict__ pop) {
+  const int i = xcd_block() * BLOCK + threadIdx.x;
+  if (i >= N) return;
+  double sCx = 0.0, sCy = 0.0, spx = 0.0, spy = 0.0;
+  for (int q = n2e_ptr[i]; q < n2e_ptr[i + 1]; ++q) {
+    const int e = n2e[q] >> 2;
+    const double A = geo[e];
+    sCx += A * gC[e];
+    sCy += A * gC[E + e];
+    spx += A * (double)gp[e];
+    spy += A * (double)gp[E + e];
+  }
+  const double vol = pvol[i];
+  const double gCx = sCx / vol, gCy = sCy / vol, gpx = spx / vol, gpy = spy / vol;
+  const double C = Cn[i], m = mu[i], lm = lapmu_n[i], p = (double)pn[i];
+  const double ux = (double)uxn[i], uy = (double)uyn[i];
+  const double rho = C * P.rho_l + (1.0 - C) * P.rho_v;
+  const double drho = P.rho_l - P.rho_v;
+  const double ax = CS2 * drho * gCx, ay = CS2 * drho * gCy;  // c_s^2 grad rho
+  const double bx = m * gCx, by = m * gCy;                    // mu grad C
+  const double cf = C / (rho * CS2);
+  const double Xx = gCx - cf * (gpx - bx), Xy = gCy - cf * (gpy - by);
+  const double d = P.mobility * lm;
+  const double uu = ux * ux + uy * uy;
+  const bool wall = is_wall[i] != 0;
+  const double tau = 1.0 / (C * P.inv_tau_l + (1.0 - C) * P.inv_tau_v);
+  const double om = 1.0 / (tau + 0.5);
+  const double Cs = C + 0.5 * P.dt * d;
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const double eu = ex(a) * ux + ey(a) * uy;
+    const double G = wq(a) * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+    double Fg, Fh, odd;
+    if (wall) {
+      Fg = 0.0;
+      Fh = d * wq(a);
+      odd = 0.0;
+    } else {
+      Fg = ((ex(a) - ux) * ax + (ey(a) - uy) * ay) * (G - wq(a)) + ((ex(a) - ux) * bx + (ey(a) - uy) * by) * G;
+      odd = ((ex(a) - ux) * Xx + (ey(a) - uy) * Xy) * G;
+      Fh = odd + d * G;
+    }
+    const double g = (double)pop[a * Np + i], h = (double)pop[(Q + a) * Np + i];
+    if (INIT) {
+      pop[a * Np + i] = (real)(g - 0.5 * P.dt * Fg);
+      pop[(Q + a) * Np + i] = (real)(h - 0.5 * P.dt * odd);
+    } else {
+      const double poly = eu + 1.5 * eu * eu - 0.5 * uu;
+      const double geq = wq(a) * (p + rho * poly);
+      const double heq = wq(a) * Cs * (1.0 + 3.0 * poly);
+      pop[a * Np + i] = (real)(g - om * (g - geq + 0.5 * P.dt * Fg) + P.dt * Fg);
+      pop[(Q + a) * Np + i] = (real)(h - om * (h - heq + 0.5 * P.dt * Fh) + P.dt * Fh);
+    }
+  }
 }
 
 // ----------------------------------------------------------------------------

@@ -144,7 +144,8 @@ class Context:
         lib = load_library()
         prec = {"fp64": FP64, "fp32": FP32}[precision] if isinstance(precision, str) else int(precision)
         kern = {"auto": 0, "global": 1}[kernels] if isinstance(kernels, str) else int(kernels)
-        forces = {"mixed": 0, "nodal": 1}[force_scheme] if isinstance(force_scheme, str) else int(force_scheme)
+        forces = ({"mixed": 0, "nodal": 1, "nodal_collide": 2}[force_scheme] if isinstance(force_scheme, str)
+                  else int(force_scheme))
         self.params = Params(sigma, xi, mobility, rho_l, rho_v, nu_l, nu_v, dt, prec, int(solver_sweeps),
                              lambda_min, lambda_max, kern, forces)
         h = _P()
