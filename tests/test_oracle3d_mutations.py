@@ -1,0 +1,87 @@
+"""Plant plausible mistakes in the 3-D oracle (on the CPU, in the oracle only)
+and check that a pin catches each."""
+import numpy as np
+import pytest
+
+import pins3d
+from oracle import felbm3d_oracle as fo3
+
+_lapC, _lapmu, _wall, _rhs, _pf, _eq = fo3.laplacian_C, fo3.laplacian_mu, fo3.wall_flux, fo3.rhs, fo3.point_forces, \
+    fo3.equilibria
+_Geometry = fo3.Geometry
+
+
+class GeometryTwoThirds(_Geometry):
+    """|f| n = -2 V grad N (the triangle's factor) instead of -3 V grad N."""
+
+    def __init__(self, mesh):
+        super().__init__(mesh)
+        self.face_area_vec = self.face_area_vec * (2.0 / 3.0)
+
+
+def lapmu_doubled(geo, gradmu):
+    return 2.0 * _lapmu(geo, gradmu)
+
+
+def lapC_no_average(geo, C, gradC, bc):
+    saved = geo.face_nbr.copy()
+    geo.face_nbr[:] = np.where(saved >= 0, np.arange(geo.NT)[:, None], saved)
+    try:
+        return _lapC(geo, C, gradC, bc)
+    finally:
+        geo.face_nbr[:] = saved
+
+
+def wall_flux_trapezoid(Cf, rf, area):
+    # the cubic integrand by the vertex rule instead of exactly
+    return -area / 3.0 * sum(rf[i] * (Cf[i] - Cf[i] * Cf[i]) for i in range(3))
+
+
+def lapC_no_incident_wall_faces(geo, C, gradC, bc):
+    saved, sa = geo.wall_faces, geo.wall_area
+    geo.wall_faces, geo.wall_area = saved[:0], sa[:0]
+    try:
+        return _lapC(geo, C, gradC, bc)
+    finally:
+        geo.wall_faces, geo.wall_area = saved, sa
+
+
+def rhs_printed_sign(mat, dt, psi_hat, Phi):
+    out = _rhs(mat, dt, psi_hat, np.zeros_like(Phi))
+    return out + np.stack([-dt * (mat.M10 @ Phi[:, a]) + dt * dt * (mat.Ka[a] @ Phi[:, a]) for a in range(fo3.Q)], 1)
+
+
+def forces_no_mobility(prm, C, rho, u, mu, gradC, gradp, gradrho, lapmu):
+    return _pf(prm, C, rho, u, mu, gradC, gradp, gradrho, 0 * lapmu)
+
+
+_W = fo3.W.copy()
+
+MUTATIONS = [
+    ("face area -2V", "Geometry", GeometryTwoThirds, lambda: pins3d.laplacian_quadratic_error() > 1e-3),
+    ("element lap mu doubled", "laplacian_mu", lapmu_doubled, lambda: pins3d.laplacian_quadratic_error() > 1e-3),
+    ("no gradient averaging", "laplacian_C", lapC_no_average, lambda: pins3d.laplacian_quadratic_error() > 1e-3),
+    ("wetting flux by the vertex rule", "wall_flux", wall_flux_trapezoid,
+     lambda: pins3d.face_flux_quadrature_error() > 1e-6),
+    ("missing incident wall faces", "laplacian_C", lapC_no_incident_wall_faces,
+     lambda: pins3d.wall_linear_laplacian_error() > 1e-6),
+    ("printed M10 sign", "rhs", rhs_printed_sign, lambda: pins3d.static_balance_drift() > 1e-8),
+    ("dropped mobility term", "point_forces", forces_no_mobility, lambda: pins3d.force_moments_error() > 1e-8),
+]
+
+
+@pytest.mark.parametrize("name,attr,fn,caught", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pin_catches_planted_mistake_3d(monkeypatch, name, attr, fn, caught):
+    monkeypatch.setattr(fo3, attr, fn)
+    assert caught(), f"no pin caught the planted mistake: {name}"
+
+
+def test_wrong_d3q19_weight_is_caught(monkeypatch):
+    w = _W.copy()
+    w[7:] *= 1.01
+    monkeypatch.setattr(fo3, "W", w)
+    assert pins3d.lattice_identities_error() > 1e-4
+
+
+def test_unmutated_3d_oracle_passes_the_same_predicates():
+    assert not any(m[3]() for m in MUTATIONS)
