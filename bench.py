@@ -269,8 +269,23 @@ def spurious_table(felbm, stream, t_end, sweeps32, sweeps64, samples=16, runs=("
 
 def angle_run(felbm, stream, w, sweeps32, samples):
     """One sessile droplet in FP32 up to w.steps, the contact angle measured
-    on the C = 0.5 contour `samples` times."""
-    from paper_1708_04678_amd.analysis import contact_angle
+    on the C = 0.5 contour `samples` times: from the cap height and base
+    (tan(theta/2) = 2h/b) and from a circle fitted to the contour above
+    y = 2 xi (cos(theta) = -y_c/r), which needs no wall crossings (a droplet
+    on a fully non-wetting wall may touch it at one point only)."""
+    import numpy as np
+    from paper_1708_04678_amd.analysis import cap_fit_angle, contact_angle
+
+    def measure(C):
+        try:
+            th, hgt, base = contact_angle(w.mesh.xy, w.mesh.tri, w.mesh.wall_nodes(0), C, w.mesh.period_x)
+        except ValueError:
+            th, hgt, base = float("nan"), float("nan"), float("nan")
+        try:
+            th_fit = cap_fit_angle(w.mesh.xy, w.mesh.tri, C, w.mesh.period_x, y_min=2 * w.phys.xi)[0]
+        except (ValueError, np.linalg.LinAlgError):
+            th_fit = float("nan")
+        return th, hgt, base, th_fit
     ctx, d0 = make_ctx(felbm, w, "fp32", sweeps32, stream)
     chunk = max(1, w.steps // samples)
     trace = []
@@ -283,18 +298,24 @@ def angle_run(felbm, stream, w, sweeps32, samples):
             return {"nodes": w.mesh.n_nodes, "xi": w.phys.xi, "dt": w.phys.dt, "mobility": w.phys.mobility,
                     "diverged": str(e), "trace": trace}
         d = ctx.diagnostics()
-        th, hgt, base = contact_angle(w.mesh.xy, w.mesh.tri, w.mesh.wall_nodes(0), ctx.read("C"), w.mesh.period_x)
-        trace.append((round((s + 1) * chunk * w.phys.dt, 3), round(th, 3), d["max_u"]))
-        log(f"  t {trace[-1][0]:.0f}  theta {th:.2f} deg (h {hgt:.2f}, b {base:.2f})  max|u| {d['max_u']:.3e}")
+        th, hgt, base, th_fit = measure(ctx.read("C"))
+        trace.append((round((s + 1) * chunk * w.phys.dt, 3), round(th, 3), d["max_u"], round(th_fit, 3)))
+        log(f"  t {trace[-1][0]:.0f}  theta {th:.2f} deg (h {hgt:.2f}, b {base:.2f}), circle fit {th_fit:.2f}  "
+            f"max|u| {d['max_u']:.3e}")
     ctx.close()
+    q = trace[(3 * samples) // 4 - 1]
     return {"nodes": w.mesh.n_nodes, "h": round(float(w.mesh.xy[1, 0] - w.mesh.xy[0, 0]), 6), "xi": w.phys.xi,
-            "dt": w.phys.dt, "mobility": w.phys.mobility, "steps": chunk * samples, "t_end": trace[-1][0],
-            "theta_measured": trace[-1][1], "height": round(hgt, 3), "base": round(base, 3),
-            "theta_change_last_quarter": round(trace[-1][1] - trace[(3 * samples) // 4 - 1][1], 3),
+            "dt": w.phys.dt, "mobility": w.phys.mobility, "sigma": w.phys.sigma, "box": w.name,
+            "steps": chunk * samples, "t_end": trace[-1][0],
+            "theta_measured": trace[-1][1], "theta_circle_fit": trace[-1][3], "height": round(hgt, 3),
+            "base": round(base, 3), "theta_change_last_quarter": round(trace[-1][1] - q[1], 3),
+            "theta_fit_change_last_quarter": round(trace[-1][3] - q[3], 3),
             "max_u_final": trace[-1][2], "mass_drift": abs(d["mass"] - d0["mass"]) / d0["mass"], "trace": trace}
 
 
-def contact_angle_sweep(felbm, stream, t_end, sweeps32, samples=8):
+def contact_angle_sweep(felbm, stream, t_end, sweeps32, samples=8,
+                        thetas=(30.0, 45.0, 60.0, 75.0, 90.0, 105.0, 120.0, 135.0, 150.0),
+                        contrasts=((10.0, 1.0), (100.0, 40.0)), sigma=0.01, box=6.4, resolution_study=True):
     """Equilibrium contact angle against the imposed wetting potential
     Omega_c = -cos(theta) (the 2-D analogue of the angle sweep of Sec. III.B):
     a R = 20 droplet on a wall meshed with h = xi / 8, for two density /
@@ -303,9 +324,9 @@ def contact_angle_sweep(felbm, stream, t_end, sweeps32, samples=8):
     import numpy as np
     from workloads import wetting_drop
     sweep = []
-    for m_rho, m_nu in ((10.0, 1.0), (100.0, 40.0)):
-        for theta in (30.0, 45.0, 60.0, 75.0, 90.0, 105.0, 120.0, 135.0, 150.0):
-            w = wetting_drop(theta, m_rho, m_nu, refine=2, t_end=t_end)
+    for m_rho, m_nu in contrasts:
+        for theta in thetas:
+            w = wetting_drop(theta, m_rho, m_nu, refine=2, t_end=t_end, sigma=sigma, box=box)
             log(f"contact-angle sweep: M_rho {m_rho:g} M_nu {m_nu:g} theta {theta:g} ({w.mesh.n_nodes} nodes, "
                 f"{w.steps} steps)")
             row = {"theta_imposed": theta, "omega_c": -float(np.cos(np.radians(theta))), "m_rho": m_rho,
@@ -313,7 +334,7 @@ def contact_angle_sweep(felbm, stream, t_end, sweeps32, samples=8):
             row.update(angle_run(felbm, stream, w, sweeps32, samples))
             sweep.append(row)
     resolution = []
-    for refine, xi, mobility, dt in ((1, 2.0, 0.2, None), (1, 4.0, 0.2, None), (2, 4.0, 0.2, None),
+    for refine, xi, mobility, dt in () if not resolution_study else ((1, 2.0, 0.2, None), (1, 4.0, 0.2, None), (2, 4.0, 0.2, None),
                                      (4, 4.0, 0.1, 0.0125)):
         for theta in (60.0, 120.0):
             w = wetting_drop(theta, refine=refine, xi=xi, mobility=mobility, dt=dt, t_end=t_end)
@@ -540,6 +561,11 @@ def main():
     ap.add_argument("--contact-angle-sweep", type=float, default=0.0, metavar="T",
                     help="only run the equilibrium contact angle against the imposed wetting potential "
                          "(two contrasts, 30-150 deg, and a mesh-resolution study) up to physical time T")
+    ap.add_argument("--angles", default="30,45,60,75,90,105,120,135,150", help="angles of --contact-angle-sweep")
+    ap.add_argument("--contrasts", default="10:1,100:40", help="M_rho:M_nu pairs of --contact-angle-sweep")
+    ap.add_argument("--sigma", type=float, default=0.01, help="surface tension of --contact-angle-sweep")
+    ap.add_argument("--box", type=float, default=6.4, help="box length / R of --contact-angle-sweep")
+    ap.add_argument("--no-resolution", action="store_true", help="skip the h/xi study of --contact-angle-sweep")
     ap.add_argument("--mobility-study", type=float, default=0.0, metavar="T",
                     help="only run the kinetic-energy decay of a theta = 120 deg droplet for four mobilities up "
                          "to T viscous times")
@@ -584,7 +610,11 @@ def main():
     if args.contact_angle_sweep:
         tstream = torch.cuda.Stream()
         torch.cuda.set_stream(tstream)
-        sweep, resolution = contact_angle_sweep(felbm, tstream.cuda_stream, args.contact_angle_sweep, args.sweeps32)
+        sweep, resolution = contact_angle_sweep(
+            felbm, tstream.cuda_stream, args.contact_angle_sweep, args.sweeps32,
+            thetas=tuple(float(a) for a in args.angles.split(",")),
+            contrasts=tuple(tuple(float(v) for v in c.split(":")) for c in args.contrasts.split(",")),
+            sigma=args.sigma, box=args.box, resolution_study=not args.no_resolution)
         print(json.dumps({"contact_angle_sweep": sweep, "contact_angle_resolution": resolution}))
         return
     if args.capillary:

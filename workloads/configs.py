@@ -176,25 +176,27 @@ def free_droplet(level: int, t_end: float = 8000.0) -> Workload:
 
 def wetting_drop(theta_deg: float, m_rho: float = 10.0, m_nu: float = 1.0, refine: int = 2, xi: float = 4.0,
                  radius: float = 20.0, sigma: float = 0.01, mobility: float = 0.2, dt: float | None = None,
-                 t_end: float = 8000.0) -> Workload:
+                 t_end: float = 8000.0, box: float = 6.4) -> Workload:
     """Sessile droplet for the equilibrium contact angle against the imposed
     wetting potential (the 2-D analogue of the angle sweep of Sec. III.B):
     a semicircular droplet of the given radius on the bottom wall of a
-    6.4 R x 3.2 R x-periodic box, wetting potential Omega_c = -cos(theta) on
-    the bottom wall, neutral top wall.  Jittered split mesh with spacing
-    h = 1 / refine; kinematic viscosity 1/30 in the liquid and m_nu / 30 in
-    the vapour whatever the spacing; dt = 0.1 / refine unless given.  The
-    explicit composition update needs dt below about h^4 / (32 M kappa)."""
-    L = 6.4 * radius
+    box R x box R / 2 x-periodic box (box = 6.4 by default; wider for small
+    angles, whose caps spread beyond it), wetting potential
+    Omega_c = -cos(theta) on the bottom wall, neutral top wall.  Jittered
+    split mesh with spacing h = 1 / refine; kinematic viscosity 1/30 in the
+    liquid and m_nu / 30 in the vapour whatever the spacing; dt = 0.1 / refine
+    unless given.  The explicit composition update needs dt below about
+    h^4 / (32 M kappa)."""
+    L = box * radius
     n = int(round(refine * L))
-    mesh = split_grid_mesh(L, uniform_rows(L / 2, n // 2 + 1), n, seed=[20])
+    mesh = split_grid_mesh(L, uniform_rows(3.2 * radius, int(round(refine * 3.2 * radius)) + 1), n, seed=[20])
     dt = 0.1 / refine if dt is None else dt
     nu = 0.1 / 3.0
     phys = Physics(sigma=sigma, xi=xi, mobility=mobility, rho_l=1.0, rho_v=1.0 / m_rho, nu_l=nu, nu_v=nu * m_nu,
                    dt=dt)
     drops = [(L / 2, 0.0, radius)]
     om = wetting_from_angles(mesh, theta_deg)
-    return Workload(f"wetting-drop-theta{theta_deg:g}-h{1.0 / refine:g}-xi{xi:g}", mesh, phys,
+    return Workload(f"wetting-drop-theta{theta_deg:g}-h{1.0 / refine:g}-xi{xi:g}-box{box:g}", mesh, phys,
                     droplet_field(mesh, drops, xi), om, int(round(t_end / dt)), drops,
                     extra={"theta": theta_deg, "m_rho": m_rho, "m_nu": m_nu})
 
