@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 from gpu_common import log, make_ctx, stack
+from losses import adjoint_probe_nodes, wetted_centroid_loss
 from oracle import Oracle
 from workloads import config, droplet_field, make_physics, split_grid_mesh, uniform_rows, wetting_from_angles
 
@@ -100,23 +101,6 @@ def test_checkpoint_interval_does_not_change_gradient():
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
 
 
-def wetted_centroid_loss(mesh, m, C):
-    """Loss of the adjoint workload: droplet centroid x plus the wetted length
-    squared; returns L and dL/dC."""
-    x = mesh.xy[:, 0]
-    M0, M1 = np.sum(m * C), np.sum(m * x * C)
-    xc = M1 / M0
-    we = mesh.wall_edges[mesh.wall_side == 0]
-    dx = mesh.xy[we[:, 1], 0] - mesh.xy[we[:, 0], 0]
-    dx -= mesh.period_x * np.round(dx / mesh.period_x)
-    L_w = np.sum(np.abs(dx) * 0.5 * (C[we[:, 0]] + C[we[:, 1]]))
-    dL = m * x / M0 - M1 * m / M0 ** 2
-    dLw = np.zeros_like(C)
-    np.add.at(dLw, we[:, 0], 0.5 * np.abs(dx))
-    np.add.at(dLw, we[:, 1], 0.5 * np.abs(dx))
-    return xc + L_w ** 2, dL + 2.0 * L_w * dLw
-
-
 def test_adjoint_workload_fp32_vs_fd_fp64():
     """Adjoint workload (256 x 128 mesh, seeded wettability field with theta in
     50-130 deg, 500 steps, checkpoint every 50): FP32 forward and FP32 adjoint
@@ -141,8 +125,7 @@ def test_adjoint_workload_fp32_vs_fd_fp64():
         c64.step(n)
         return wetted_centroid_loss(mesh, m, c64.read("C"))[0]
 
-    bottom = mesh.wall_nodes(0)
-    pick = np.random.default_rng([4, 5]).choice(bottom, 8, replace=False)
+    pick = adjoint_probe_nodes(mesh)
     hstep = 1e-4
     for k in pick:
         e = np.zeros(mesh.n_nodes)
@@ -154,15 +137,15 @@ def test_adjoint_workload_fp32_vs_fd_fp64():
 
 
 def test_adjoint_at_scale_vs_fd_fp64():
-    """The graded 1024 x 512 adjoint workload at full size (527,360 nodes, FP32
-    and FP64 forward and reverse, checkpoint every 10) over a short horizon of
-    40 steps, loss 1/2 sum m (C - C*)^2: the gradient with respect to Omega_c
+    """The graded 1024 x 512 adjoint workload at its stated horizon (527,360
+    nodes, 2,000 steps, checkpoint every 100; FP32 and FP64 forward and
+    reverse), loss 1/2 sum m (C - C*)^2: the gradient with respect to Omega_c
     at 4 seeded bottom-wall nodes near the two contact lines against central
     differences (h = 1e-3) of the FP64 forward.  Bars: FP64 adjoint 1e-5
     relative (difference truncation O(h^2) and rounding), FP32 adjoint 2 %."""
     w = config(5)
     mesh, phys, Ct = w.mesh, w.phys, w.extra["C_target"]
-    n, every = 40, 10
+    n, every = w.steps, w.extra["ckpt_every"]
     log(f"adjoint at scale: {mesh.n_nodes} nodes, {n} steps, ckpt {every}")
     grads = {}
     for prec, sweeps in (("fp64", 26), ("fp32", 11)):
@@ -195,6 +178,40 @@ def test_adjoint_at_scale_vs_fd_fp64():
         assert abs(grads["fp64"][k] - fd) <= 1e-5 * abs(fd) + 1e-12
         assert abs(grads["fp32"][k] - fd) <= 0.02 * abs(fd) + 1e-3 * np.abs(grads["fp32"]).max()
     c64.close()
+
+
+def test_adjoint_workload_vs_oracle_tangent():
+    """The 256 x 128 adjoint workload at its stated horizon (500 steps,
+    checkpoint every 50) against the oracle's exact forward-mode derivative
+    (complex step through the FP64 oracle, 500 steps, PCG to 1e-13; stored by
+    tests/golden/make_adjoint_cfg4_tangent.py) at the 8 seeded wall nodes.
+    Bars: FP64 adjoint (26 sweeps) 1e-6 relative, FP32 adjoint (11 sweeps)
+    2 % (+ 1e-3 of the largest component), FP64 loss 1e-10 relative."""
+    import json
+    import os
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "adjoint_cfg4_tangent.json")))
+    w = config(4)
+    mesh, phys = w.mesh, w.phys
+    n, every = w.steps, w.extra["ckpt_every"]
+    assert ref["steps"] == n and ref["nodes"] == [int(k) for k in adjoint_probe_nodes(mesh)]
+    for prec, sweeps in (("fp64", 26), ("fp32", 11)):
+        log(f"adjoint workload vs oracle tangent: {prec}, {n} steps, ckpt {every}")
+        ctx = make_ctx(mesh, phys, w.omega_c, precision=prec, sweeps=sweeps)
+        m = ctx.lumped_mass()
+        ctx.init(w.C0)
+        ctx.forward_ckpt(n, every)
+        L, dLdC = wetted_centroid_loss(mesh, m, ctx.read("C"))
+        g = ctx.backward_host(dLdC)
+        ctx.close()
+        if prec == "fp64":
+            assert abs(L - ref["loss_value"]) <= 1e-10 * abs(ref["loss_value"])
+        gmax = max(abs(v) for v in ref["dL_domega"])
+        for k, t in zip(ref["nodes"], ref["dL_domega"]):
+            log(f"  node {k}: adjoint {g[k]:.10e}  oracle tangent {t:.10e}")
+            if prec == "fp64":
+                assert abs(g[k] - t) <= 1e-6 * abs(t) + 1e-12 * gmax
+            else:
+                assert abs(g[k] - t) <= 0.02 * abs(t) + 1e-3 * gmax
 
 
 def test_torch_autograd_function():

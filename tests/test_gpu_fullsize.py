@@ -65,3 +65,38 @@ def test_full_size_mass_and_determinism(precision, sweeps):
         assert np.isfinite(runs[-1]).all()
         ctx.close()
     assert np.array_equal(runs[0], runs[1])
+
+
+def test_fp32_vs_fp64_at_the_workload_horizon():
+    """The precision form at the workload's stated 2,000 steps: FP32 (K = 11)
+    and FP64 (K = 26) from the same initial state.  Bars from the precision
+    form's targets: max|u| (the spurious-current magnitude) within 5 %, each
+    droplet's apparent contact angle (circle fit above the roughness against
+    the mean wall line) within 0.5 deg, relative mass drift below 1e-10 in
+    both; the band KE of the first droplet is reported."""
+    from paper_1708_04678_amd.analysis import cap_fit_angle
+    w = config(3)
+    res = {}
+    for prec, K in (("fp32", 11), ("fp64", 26)):
+        log(f"workload horizon: {w.steps} steps, {prec}, K = {K}")
+        ctx = make_ctx(w.mesh, w.phys, w.omega_c, precision=prec, sweeps=K)
+        xc, yc, R = w.droplets[0]
+        ctx.set_band(xc, yc, R, w.phys.xi)
+        ctx.init(w.C0)
+        m0 = ctx.diagnostics()["mass"]
+        ctx.step(w.steps)
+        d = ctx.diagnostics()
+        C = ctx.read("C")
+        ang = [cap_fit_angle(w.mesh.xy, w.mesh.tri, C, w.mesh.period_x, x_window=(x - 2 * r, x + 2 * r), y_min=10.0)[0]
+               for (x, _, r) in w.droplets]
+        drift = abs(d["mass"] - m0) / m0
+        log(f"  max|u| {d['max_u']:.6e}  band KE {d['band_ke']:.6e}  mass drift {drift:.2e}  angles "
+            + ", ".join(f"{a:.4f}" for a in ang))
+        assert drift < 1e-10
+        res[prec] = (d, ang)
+        ctx.close()
+    (d32, a32), (d64, a64) = res["fp32"], res["fp64"]
+    assert abs(d32["max_u"] - d64["max_u"]) <= 0.05 * d64["max_u"]
+    assert max(abs(a - b) for a, b in zip(a32, a64)) < 0.5
+    log(f"  max|u| rel diff {abs(d32['max_u'] - d64['max_u']) / d64['max_u']:.2e}, band KE rel diff "
+        f"{abs(d32['band_ke'] - d64['band_ke']) / d64['band_ke']:.2e}")
