@@ -28,11 +28,13 @@ def build(verbose: bool = True) -> str:
     os.makedirs(LIBDIR, exist_ok=True)
     obj_host = os.path.join(LIBDIR, "mesh_prep.o")
     obj_dev = os.path.join(LIBDIR, "felbm.o")
+    obj_dev3 = os.path.join(LIBDIR, "felbm3d.o")
     _run(["g++", *COMMON, "-c", os.path.join(CSRC, "mesh_prep.cpp"), "-o", obj_host], verbose)
-    _run([HIPCC, *COMMON, f"--offload-arch={ARCH}", *DEVICE_FLAGS, "-c", os.path.join(CSRC, "felbm.hip"), "-o", obj_dev],
-         verbose)
+    for src, obj in (("felbm.hip", obj_dev), ("felbm3d.hip", obj_dev3)):
+        _run([HIPCC, *COMMON, f"--offload-arch={ARCH}", *DEVICE_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj],
+             verbose)
     tmp = LIB + ".tmp"
-    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", obj_dev, obj_host, "-o", tmp], verbose)
+    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", obj_dev, obj_dev3, obj_host, "-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -327,7 +327,7 @@ int enqueue_fields(felbm_ctx* c, bool collide, bool record, DiagRecord* rec_targ
     TRY(launch(c, K_MOMENTS, k_moments<real, false>, gN, pop, N, Np, c->sp, c->Cn, (real*)c->pn, (real*)c->uxn,
                (real*)c->uyn, (const double*)c->mass, (const double*)c->xy, c->band, (const double*)c->rC, c->partials));
   if (record && !nc)
-    TRY(launch_bs(c, K_REDUCE, k_reduce_final, 1, RBLOCK, (const double*)c->partials, gN, N, (int64_t)c->step, rec_target,
+    TRY(launch_bs(c, K_REDUCE, k_reduce_final<>, 1, RBLOCK, (const double*)c->partials, gN, N, (int64_t)c->step, rec_target,
                c->first_bad));
   if (mode != FIELDS_FULL) {
     const FieldOps op = field_ops(c);
@@ -362,7 +362,7 @@ int enqueue_fields(felbm_ctx* c, bool collide, bool record, DiagRecord* rec_targ
                (real*)c->pn, (real*)c->uxn, (real*)c->uyn, c->lapmu_n, (const double*)c->mass, (const double*)c->xy,
                c->band, c->partials));
     if (record)
-      TRY(launch_bs(c, K_REDUCE, k_reduce_final, 1, RBLOCK, (const double*)c->partials, gN, N, (int64_t)c->step,
+      TRY(launch_bs(c, K_REDUCE, k_reduce_final<>, 1, RBLOCK, (const double*)c->partials, gN, N, (int64_t)c->step,
                     rec_target, c->first_bad));
     TRY(launch(c, K_GRAD, k_elem_grad<real>, gE, E, (const int*)c->tri, (const double*)c->geo, (const double*)c->Cn,
                (const real*)c->pn, c->gC, (real*)c->gp));
@@ -1414,7 +1414,7 @@ int felbm_diagnostics(felbm_ctx* c, felbm_diag* out) {
   else
     TRY(launch(c, K_MOMENTS, k_moments<float, false>, gN, (float*)c->pop, N, Np, c->sp, c->Cn, (float*)c->pn,
                (float*)c->uxn, (float*)c->uyn, (const double*)c->mass, (const double*)c->xy, c->band, (const double*)c->rC, c->partials));
-  TRY(launch_bs(c, K_REDUCE, k_reduce_final, 1, RBLOCK, (const double*)c->partials, gN, N, (int64_t)c->step, c->diag_now,
+  TRY(launch_bs(c, K_REDUCE, k_reduce_final<>, 1, RBLOCK, (const double*)c->partials, gN, N, (int64_t)c->step, c->diag_now,
              scratch_bad));
   DiagRecord rec;
   double res = -1.0;
@@ -1453,7 +1453,7 @@ int felbm_diagnostics_noalloc(felbm_ctx* c, felbm_diag* out) {
     hipLaunchKernelGGL((k_moments<float, false>), dim3(gN), dim3(BLOCK), 0, c->stream, (float*)c->pop, N, Np, c->sp,
                        c->Cn, (float*)c->pn, (float*)c->uxn, (float*)c->uyn, (const double*)c->mass,
                        (const double*)c->xy, c->band, (const double*)c->rC, partials);
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RBLOCK), 0, c->stream, (const double*)partials, gN, N,
+  hipLaunchKernelGGL(k_reduce_final<>, dim3(1), dim3(RBLOCK), 0, c->stream, (const double*)partials, gN, N,
                      (int64_t)c->step, rec, flag);
   HIP_OK(c, hipGetLastError());
   DiagRecord host;

@@ -1,0 +1,429 @@
+// HIP kernels (gfx950) of one FE-LBM time step in 3-D: D3Q19 populations g, h
+// on linear tetrahedra, the paper's own setting (arXiv:1708.04678, Sec. II.A:
+// D3Q19; Sec. II.C: tetrahedral elements).  The same steps as the 2-D
+// kernels with the tetrahedral forms; all gathers are global (node-centric,
+// one thread per output, no atomics), the element data in structure-of-arrays
+// order.
+//
+// Data layout (device):
+//   populations  real [38][Np]   g_0..g_18 then h_0..h_18, Np = N rounded to 64
+//   elements     tet / fnbr int32 [4][E] (fnbr: element across the face
+//                opposite local vertex l, -1 on a wall); geometry double
+//                [13][E] = (V, grad N_0, grad N_1, grad N_2, grad N_3)
+//   node->element gather list (CSR, element*4 + local vertex)
+//   wall faces containing each node (CSR of face indices; face nodes [3][W],
+//   areas [W])
+//   mass matrix  diag(m)^-1 M11 off-diagonal part, sliced ELL (slice 64);
+//                its diagonal is M11_ii / m_i = 2/5 for P1 tetrahedra
+#pragma once
+
+#include "common.hpp"
+
+namespace felbm3d {
+
+using felbm::BLOCK;
+using felbm::CS2;
+using felbm::StepParams;
+using felbm::xcd_block;
+
+constexpr int Q = 19;
+constexpr int NPOP = 38;
+
+// D3Q19: rest, the six axis directions (+x, -x, +y, -y, +z, -z), then the
+// twelve face diagonals of the (x,y), (x,z), (y,z) planes in the order
+// (+,+), (-,-), (+,-), (-,+)
+__host__ __device__ constexpr int ex(int a) {
+  return a == 1 ? 1 : a == 2 ? -1 : (a >= 7 && a <= 14) ? ((a == 7 || a == 9 || a == 11 || a == 13) ? 1 : -1) : 0;
+}
+__host__ __device__ constexpr int ey(int a) {
+  return a == 3 ? 1 : a == 4 ? -1
+       : (a >= 7 && a <= 10) ? ((a == 7 || a == 10) ? 1 : -1)
+       : (a >= 15) ? ((a == 15 || a == 17) ? 1 : -1) : 0;
+}
+__host__ __device__ constexpr int ez(int a) {
+  return a == 5 ? 1 : a == 6 ? -1
+       : (a >= 11 && a <= 14) ? ((a == 11 || a == 14) ? 1 : -1)
+       : (a >= 15) ? ((a == 15 || a == 18) ? 1 : -1) : 0;
+}
+__host__ __device__ constexpr double wq(int a) { return a == 0 ? 1.0 / 3.0 : (a < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
+__host__ __device__ constexpr int opp(int a) {
+  return a == 0 ? 0 : (a < 7 ? ((a & 1) ? a + 1 : a - 1) : (((a - 7) & 1) ? a - 1 : a + 1));
+}
+
+constexpr int NRED3 = 6;  // same record as the 2-D reductions (band entries stay 0)
+
+// a1 + a6: moments, relaxation time, equilibria and BGK collision; block partials of the reductions
+template <typename real, bool COLLIDE>
+__global__ void __launch_bounds__(BLOCK) k3_moments(real* __restrict__ pop, int N, int Np, StepParams P,
+                                                   double* __restrict__ Cn, real* __restrict__ pn,
+                                                   real* __restrict__ un, const double* __restrict__ mass,
+                                                   double* __restrict__ partials) {
+  const int blk = xcd_block();
+  const int i = blk * BLOCK + threadIdx.x;
+  double red[NRED3] = {0, 0, 0, 0, 0, 0};
+  if (i < N) {
+    double C = 0.0;
+    real p = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const real g = pop[a * Np + i];
+      C += (double)pop[(Q + a) * Np + i];
+      p += g;
+      if (ex(a)) jx += ex(a) > 0 ? g : -g;
+      if (ey(a)) jy += ey(a) > 0 ? g : -g;
+      if (ez(a)) jz += ez(a) > 0 ? g : -g;
+    }
+    const real rho = (real)(C * P.rho_l + (1.0 - C) * P.rho_v);
+    const real ux = (real)3 * jx / rho, uy = (real)3 * jy / rho, uz = (real)3 * jz / rho;
+    Cn[i] = C;
+    pn[i] = p;
+    un[i] = ux;
+    un[Np + i] = uy;
+    un[2 * Np + i] = uz;
+    const real uu = ux * ux + uy * uy + uz * uz;
+    if (COLLIDE) {
+      const real tau = (real)(1.0 / (C * P.inv_tau_l + (1.0 - C) * P.inv_tau_v));
+      const real om = (real)1 / (tau + (real)0.5);
+      const real Cr = (real)C;
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        const real eu = (real)ex(a) * ux + (real)ey(a) * uy + (real)ez(a) * uz;
+        const real poly = eu + (real)1.5 * eu * eu - (real)0.5 * uu;
+        const real geq = (real)wq(a) * (p + rho * poly);
+        const real heq = (real)wq(a) * Cr * ((real)1 + (real)3 * poly);
+        const real g = pop[a * Np + i], h = pop[(Q + a) * Np + i];
+        pop[a * Np + i] = g - om * (g - geq);
+        pop[(Q + a) * Np + i] = h - om * (h - heq);
+      }
+    }
+    const double uud = (double)uu;
+    red[0] = mass[i] * C;
+    red[1] = (C * P.rho_l + (1.0 - C) * P.rho_v) * uud;
+    red[2] = sqrt(uud);
+    red[5] = (isfinite(C) && isfinite((double)p) && isfinite(uud)) ? 0.0 : 1.0;
+    if (red[5] != 0.0) red[2] = 0.0;
+  }
+  felbm::block_reduce_store<NRED3>(red, 2, partials, gridDim.x, blk);
+}
+
+// a2: element gradients of C (FP64) and p
+template <typename real>
+__global__ void __launch_bounds__(BLOCK) k3_elem_grad(int E, const int* __restrict__ tet, const double* __restrict__ geo,
+                                                     const double* __restrict__ Cn, const real* __restrict__ pn,
+                                                     double* __restrict__ gC, real* __restrict__ gp) {
+  const int e = xcd_block() * BLOCK + threadIdx.x;
+  if (e >= E) return;
+  double c[3] = {0, 0, 0};
+  real q[3] = {0, 0, 0};
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int n = tet[v * E + e];
+    const double Cv = Cn[n];
+    const real pv = pn[n];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const double g = geo[(1 + 3 * v + r) * E + e];
+      c[r] += Cv * g;
+      q[r] += pv * (real)g;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    gC[r * E + e] = c[r];
+    gp[r * E + e] = q[r];
+  }
+}
+
+// Outward flux through a wall face from eq. bc2 (n into the fluid):
+// -int (phi_c/kappa)(C - C^2) dA with r = phi_c/kappa and C linear on the
+// triangle, exact: int lambda_i lambda_j = A (1 + delta_ij)/12 and
+// int lambda_i lambda_j lambda_k = A/10, A/30, A/60 for three, two, no equal
+// indices.
+__device__ __forceinline__ double wall_flux3(const double (&C)[3], const double (&r)[3], double area) {
+  double lin = 0.0, cub = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      lin += r[i] * C[j] * (i == j ? 2.0 : 1.0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double wgt = (i == j && j == k) ? 6.0 : ((i == j || j == k || i == k) ? 2.0 : 1.0);
+        cub += r[i] * C[j] * C[k] * wgt;
+      }
+    }
+  return -area * (lin * (1.0 / 12.0) - cub * (1.0 / 60.0));
+}
+
+// a3: flux through each face of each element as seen from the opposite vertex
+// (|f| n_out = -3 V grad N_l; averaged gradients across interior faces, the
+// wetting flux on wall faces), then the node sum over the patch plus the wall
+// faces that contain the node, over the patch volume; mu (eqn:mp_mu).
+__global__ void __launch_bounds__(BLOCK) k3_face_flux(int E, const int* __restrict__ tet, const int* __restrict__ fnbr,
+                                                     const double* __restrict__ geo, const double* __restrict__ gC,
+                                                     const double* __restrict__ Cn, const double* __restrict__ bc,
+                                                     double* __restrict__ F) {
+  const int e = xcd_block() * BLOCK + threadIdx.x;
+  if (e >= E) return;
+  const double V = geo[e];
+  const double tx = gC[e], ty = gC[E + e], tz = gC[2 * E + e];
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    const double gx = geo[(1 + 3 * l) * E + e], gy = geo[(2 + 3 * l) * E + e], gz = geo[(3 + 3 * l) * E + e];
+    const int nb = fnbr[l * E + e];
+    double fl;
+    if (nb >= 0) {
+      fl = -1.5 * V * (gx * (tx + gC[nb]) + gy * (ty + gC[E + nb]) + gz * (tz + gC[2 * E + nb]));
+    } else {
+      double Cf[3], rf[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int n = tet[((l + 1 + k) & 3) * E + e];
+        Cf[k] = Cn[n];
+        rf[k] = bc[n];
+      }
+      fl = wall_flux3(Cf, rf, 3.0 * V * sqrt(gx * gx + gy * gy + gz * gz));
+    }
+    F[l * E + e] = fl;
+  }
+}
+
+__global__ void __launch_bounds__(BLOCK) k3_lapC_mu(int N, int E, const int* __restrict__ n2e_ptr,
+                                                   const int* __restrict__ n2e, const double* __restrict__ F,
+                                                   const double* __restrict__ pvol, const double* __restrict__ Cn,
+                                                   const double* __restrict__ bc, const int* __restrict__ wf_ptr,
+                                                   const int* __restrict__ wf_list, const int* __restrict__ wface,
+                                                   const double* __restrict__ warea, int W, StepParams P,
+                                                   double* __restrict__ lapC, double* __restrict__ mu) {
+  const int k = xcd_block() * BLOCK + threadIdx.x;
+  if (k >= N) return;
+  double flux = 0.0;
+  for (int q = n2e_ptr[k]; q < n2e_ptr[k + 1]; ++q) {
+    const int packed = n2e[q];
+    flux += F[(packed & 3) * E + (packed >> 2)];
+  }
+  for (int q = wf_ptr[k]; q < wf_ptr[k + 1]; ++q) {
+    const int f = wf_list[q];
+    double Cf[3], rf[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int n = wface[c * W + f];
+      Cf[c] = Cn[n];
+      rf[c] = bc[n];
+    }
+    flux += wall_flux3(Cf, rf, warea[f]);
+  }
+  const double Ck = Cn[k], L = flux / pvol[k];
+  lapC[k] = L;
+  mu[k] = 2.0 * P.beta * Ck * (Ck - 1.0) * (2.0 * Ck - 1.0) - P.kappa * L;
+}
+
+// a4: element gradient of mu and its element Laplacian, (1/V) sum over the
+// faces of |f| n . (mean of the two adjacent gradients), zero on wall faces:
+// -3/2 sum_l grad N_l . (g_T + g_T'(l))
+__global__ void __launch_bounds__(BLOCK) k3_elem_gradmu(int E, const int* __restrict__ tet,
+                                                       const double* __restrict__ geo, const double* __restrict__ mu,
+                                                       double* __restrict__ gmu) {
+  const int e = xcd_block() * BLOCK + threadIdx.x;
+  if (e >= E) return;
+  double c[3] = {0, 0, 0};
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const double m = mu[tet[v * E + e]];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) c[r] += m * geo[(1 + 3 * v + r) * E + e];
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) gmu[r * E + e] = c[r];
+}
+
+__global__ void __launch_bounds__(BLOCK) k3_elem_lapmu(int E, const int* __restrict__ fnbr,
+                                                      const double* __restrict__ geo, const double* __restrict__ gmu,
+                                                      double* __restrict__ lapmu) {
+  const int e = xcd_block() * BLOCK + threadIdx.x;
+  if (e >= E) return;
+  const double tx = gmu[e], ty = gmu[E + e], tz = gmu[2 * E + e];
+  double acc = 0.0;
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    const int nb = fnbr[l * E + e];
+    if (nb >= 0)
+      acc += geo[(1 + 3 * l) * E + e] * (tx + gmu[nb]) + geo[(2 + 3 * l) * E + e] * (ty + gmu[E + nb]) +
+             geo[(3 + 3 * l) * E + e] * (tz + gmu[2 * E + nb]);
+  }
+  lapmu[e] = -1.5 * acc;
+}
+
+// a5 + a7: P0 forces (eq:G, eq:H at the barycentric values, eq:intF) fused
+// into the node gather of the streaming right-hand side (eq:galerkin_lbm):
+//   b_{a,i} = sum_{T ni i} V_T q_{a,T} (dt/4 + dt^2/2 e_a . grad N_i|_T),
+//   q_{a,T} = Phi_{a,T} - e_a . sum_v psi_hat_{a,v} grad N_v;  f = b / m_i.
+template <typename real>
+__global__ void __launch_bounds__(BLOCK) k3_rhs(int N, int Np, int E, const int* __restrict__ n2e_ptr,
+                                               const int* __restrict__ n2e, const int* __restrict__ tet,
+                                               const double* __restrict__ geo, const double* __restrict__ gC,
+                                               const real* __restrict__ gp, const double* __restrict__ lapmu,
+                                               const double* __restrict__ Cn, const real* __restrict__ un,
+                                               const double* __restrict__ mu, const real* __restrict__ pop,
+                                               const double* __restrict__ mass, StepParams P, real* __restrict__ f) {
+  const int i = xcd_block() * BLOCK + threadIdx.x;
+  if (i >= N) return;
+  real b[NPOP];
+#pragma unroll
+  for (int a = 0; a < NPOP; ++a) b[a] = (real)0;
+  const real dt = (real)P.dt, c1 = dt / (real)4, c2 = (real)0.5 * dt * dt;
+  const real drho_cs2 = (real)(CS2 * (P.rho_l - P.rho_v));
+  for (int q = n2e_ptr[i]; q < n2e_ptr[i + 1]; ++q) {
+    const int packed = n2e[q];
+    const int e = packed >> 2, l = packed & 3;
+    int v[4];
+    real gx[4], gy[4], gz[4];
+    double Cb = 0.0, mub = 0.0;
+    real ubx = 0, uby = 0, ubz = 0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      v[t] = tet[t * E + e];
+      gx[t] = (real)geo[(1 + 3 * t) * E + e];
+      gy[t] = (real)geo[(2 + 3 * t) * E + e];
+      gz[t] = (real)geo[(3 + 3 * t) * E + e];
+      Cb += Cn[v[t]];
+      mub += mu[v[t]];
+      ubx += un[v[t]];
+      uby += un[Np + v[t]];
+      ubz += un[2 * Np + v[t]];
+    }
+    Cb *= 0.25;
+    mub *= 0.25;
+    ubx *= (real)0.25;
+    uby *= (real)0.25;
+    ubz *= (real)0.25;
+    const real A = (real)geo[e];
+    const double rhobd = Cb * P.rho_l + (1.0 - Cb) * P.rho_v;
+    const real rhob = (real)rhobd;
+    const double gCx = gC[e], gCy = gC[E + e], gCz = gC[2 * E + e];
+    const real gpx = gp[e], gpy = gp[E + e], gpz = gp[2 * E + e];
+    const real ax = drho_cs2 * (real)gCx, ay = drho_cs2 * (real)gCy, az = drho_cs2 * (real)gCz;
+    const real bx = (real)(mub * gCx), by = (real)(mub * gCy), bz = (real)(mub * gCz);
+    const real coef = (real)Cb / (rhob * (real)CS2);
+    const real Xx = (real)gCx - coef * (gpx - bx), Xy = (real)gCy - coef * (gpy - by), Xz = (real)gCz - coef * (gpz - bz);
+    const real d = (real)(P.mobility * lapmu[e]);
+    const real uA = ubx * ax + uby * ay + ubz * az, uB = ubx * bx + uby * by + ubz * bz;
+    const real uX = ubx * Xx + uby * Xy + ubz * Xz, uu = ubx * ubx + uby * uby + ubz * ubz;
+    const real gxl = l == 0 ? gx[0] : l == 1 ? gx[1] : l == 2 ? gx[2] : gx[3];
+    const real gyl = l == 0 ? gy[0] : l == 1 ? gy[1] : l == 2 ? gy[2] : gy[3];
+    const real gzl = l == 0 ? gz[0] : l == 1 ? gz[1] : l == 2 ? gz[2] : gz[3];
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const real exa = (real)ex(a), eya = (real)ey(a), eza = (real)ez(a);
+      const real eu = exa * ubx + eya * uby + eza * ubz;
+      const real G = (real)wq(a) * ((real)1 + (real)3 * eu + (real)4.5 * eu * eu - (real)1.5 * uu);
+      const real Phig = (exa * ax + eya * ay + eza * az - uA) * (G - (real)wq(a)) + (exa * bx + eya * by + eza * bz - uB) * G;
+      const real Phih = (exa * Xx + eya * Xy + eza * Xz - uX + d) * G;
+      real sg = 0, sh = 0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const real en = exa * gx[t] + eya * gy[t] + eza * gz[t];
+        sg += pop[a * Np + v[t]] * en;
+        sh += pop[(Q + a) * Np + v[t]] * en;
+      }
+      const real enl = exa * gxl + eya * gyl + eza * gzl;
+      const real wgt = A * (c1 + c2 * enl);
+      b[a] += wgt * (Phig - sg);
+      b[Q + a] += wgt * (Phih - sh);
+    }
+  }
+  const real inv_m = (real)(1.0 / mass[i]);
+#pragma unroll
+  for (int a = 0; a < NPOP; ++a) f[a * Np + i] = b[a] * inv_m;
+}
+
+// a8: Richardson sweeps with the reciprocal Chebyshev roots on [1/5, 1] (the
+// spectrum of diag(m)^-1 M11 for P1 tetrahedra), x0 = f; (A x)_i = 2/5 x_i +
+// sum_j a_ij x_j.  MODE 0 first (x = f), 1 middle, 2 last (+ psi_hat and the
+// wall operator), 3 single, 4 none (psi_hat + f).
+template <typename real, int MODE>
+__global__ void __launch_bounds__(BLOCK) k3_sweep(int N, int Np, const int* __restrict__ sell_ptr,
+                                                 const int* __restrict__ sell_col, const real* __restrict__ sell_val,
+                                                 const real* __restrict__ f, const real* __restrict__ xin,
+                                                 real* __restrict__ xout, real* __restrict__ pop,
+                                                 const uint8_t* __restrict__ is_wall, real w) {
+  const int i = xcd_block() * BLOCK + threadIdx.x;
+  if (i >= N) return;
+  const real* __restrict__ x = (MODE == 0 || MODE == 3) ? f : xin;
+  real r[NPOP];
+  if (MODE != 4) {
+#pragma unroll
+    for (int a = 0; a < NPOP; ++a) r[a] = (real)0.4 * x[a * Np + i];
+    const int slice = i >> 6, lane = i & 63;
+    const int base = sell_ptr[slice], width = (sell_ptr[slice + 1] - base) >> 6;
+    for (int k = 0; k < width; ++k) {
+      const int idx = base + (k << 6) + lane;
+      const int j = sell_col[idx];
+      const real aij = sell_val[idx];
+#pragma unroll
+      for (int a = 0; a < NPOP; ++a) r[a] += aij * x[a * Np + j];
+    }
+#pragma unroll
+    for (int a = 0; a < NPOP; ++a) {
+      const real xi = x[a * Np + i];
+      const real fi = (MODE == 0 || MODE == 3) ? xi : f[a * Np + i];
+      r[a] = xi + w * (fi - r[a]);
+    }
+  } else {
+#pragma unroll
+    for (int a = 0; a < NPOP; ++a) r[a] = f[a * Np + i];
+  }
+  if (MODE == 0 || MODE == 1) {
+#pragma unroll
+    for (int a = 0; a < NPOP; ++a) xout[a * Np + i] = r[a];
+    return;
+  }
+  real s[NPOP];
+#pragma unroll
+  for (int a = 0; a < NPOP; ++a) s[a] = pop[a * Np + i] + r[a];
+  if (is_wall[i]) {
+#pragma unroll
+    for (int a = 1; a < Q; ++a) {
+      const int b = opp(a);
+      if (b > a) {
+        const real mg = (real)0.5 * (s[a] + s[b]), mh = (real)0.5 * (s[Q + a] + s[Q + b]);
+        s[a] = mg; s[b] = mg; s[Q + a] = mh; s[Q + b] = mh;
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < NPOP; ++a) pop[a * Np + i] = s[a];
+}
+
+// init: psi_bar^0 = psi_eq(C, u, p), then the wall operator
+template <typename real>
+__global__ void __launch_bounds__(BLOCK) k3_init(int N, int Np, StepParams P, const double* __restrict__ C,
+                                                const double* __restrict__ U, const double* __restrict__ Pr,
+                                                const uint8_t* __restrict__ is_wall, real* __restrict__ pop) {
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= N) return;
+  const double c = C[i], ux = U[3 * i], uy = U[3 * i + 1], uz = U[3 * i + 2], p = Pr[i];
+  const double rho = c * P.rho_l + (1.0 - c) * P.rho_v, uu = ux * ux + uy * uy + uz * uz;
+  double s[NPOP];
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const double eu = ex(a) * ux + ey(a) * uy + ez(a) * uz;
+    const double poly = eu + 1.5 * eu * eu - 0.5 * uu;
+    s[a] = wq(a) * (p + rho * poly);
+    s[Q + a] = wq(a) * c * (1.0 + 3.0 * poly);
+  }
+  if (is_wall[i]) {
+#pragma unroll
+    for (int a = 1; a < Q; ++a) {
+      const int b = opp(a);
+      if (b > a) {
+        const double mg = 0.5 * (s[a] + s[b]), mh = 0.5 * (s[Q + a] + s[Q + b]);
+        s[a] = mg; s[b] = mg; s[Q + a] = mh; s[Q + b] = mh;
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < NPOP; ++a) pop[a * Np + i] = (real)s[a];
+}
+
+}  // namespace felbm3d

@@ -11,7 +11,7 @@ import numpy as np
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libfelbm.so")
 
 FP64, FP32 = 0, 1
-FIELDS = {"C": 0, "RHO": 1, "P": 2, "UX": 3, "UY": 4, "MU": 5, "LAPC": 6, "LAPMU": 7}
+FIELDS = {"C": 0, "RHO": 1, "P": 2, "UX": 3, "UY": 4, "MU": 5, "LAPC": 6, "LAPMU": 7, "UZ": 8}
 ERRORS = {-1: "EINVAL", -2: "EMESH", -3: "ESTATE", -4: "ENONFINITE", -5: "ESOLVER", -6: "EDEVICE", -7: "ENOMEM"}
 
 
@@ -82,6 +82,23 @@ _SIGNATURES = {
     "felbm_lumped_mass": ([_P, _D], ct.c_int),
     "felbm_backward_full": ([_P, _D, _D, _D, _D], ct.c_int),
     "felbm_destroy": ([_P], None),
+    # 3-D (include/felbm3d.h)
+    "felbm3d_create": ([ct.POINTER(Params), ct.POINTER(_P)], ct.c_int),
+    "felbm3d_last_error": ([_P], ct.c_char_p),
+    "felbm3d_upload_mesh": ([_P, ct.c_int64, _D, ct.c_int64, _I, ct.c_int64, _I, ct.c_double, ct.c_double], ct.c_int),
+    "felbm3d_set_wetting": ([_P, _D], ct.c_int),
+    "felbm3d_init": ([_P, _D, _D, _D], ct.c_int),
+    "felbm3d_step": ([_P, ct.c_int64], ct.c_int),
+    "felbm3d_step_async": ([_P, ct.c_int64], ct.c_int),
+    "felbm3d_read": ([_P, ct.c_int32, _D], ct.c_int),
+    "felbm3d_read_populations": ([_P, _D], ct.c_int),
+    "felbm3d_diagnostics": ([_P, ct.POINTER(Diag)], ct.c_int),
+    "felbm3d_bind_stream": ([_P, ct.c_void_p], ct.c_int),
+    "felbm3d_kernel_timing": ([_P, ct.c_int32], ct.c_int),
+    "felbm3d_kernel_stats": ([_P, ct.POINTER(KStat), ct.c_int32, ct.POINTER(ct.c_int32)], ct.c_int),
+    "felbm3d_mesh_info": ([_P, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int64),
+                           ct.POINTER(ct.c_int64)], ct.c_int),
+    "felbm3d_destroy": ([_P], None),
 }
 
 
@@ -309,3 +326,96 @@ class Context:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Context3D:
+    """One 3-D FE-LBM simulation (D3Q19 on linear tetrahedra) on the current
+    HIP device (see include/felbm3d.h).  Marshalling only."""
+
+    def __init__(self, *, sigma, xi, mobility, rho_l, rho_v, nu_l, nu_v, dt, precision="fp64", solver_sweeps=28,
+                 lambda_min=0.0, lambda_max=0.0):
+        lib = load_library()
+        prec = {"fp64": FP64, "fp32": FP32}[precision] if isinstance(precision, str) else int(precision)
+        self.params = Params(sigma, xi, mobility, rho_l, rho_v, nu_l, nu_v, dt, prec, int(solver_sweeps),
+                             lambda_min, lambda_max, 0, 0)
+        h = _P()
+        rc = lib.felbm3d_create(ct.byref(self.params), ct.byref(h))
+        if rc != 0:
+            raise FelbmError(rc, lib.felbm3d_last_error(None).decode())
+        self._lib, self._h = lib, h
+        self.n_nodes = self.n_tets = 0
+
+    def _check(self, rc):
+        if rc != 0:
+            raise FelbmError(rc, self._lib.felbm3d_last_error(self._h).decode())
+
+    def upload_mesh(self, xyz, tet, wall_faces, period=(0.0, 0.0)):
+        xyz = _f64(xyz)
+        tet = np.ascontiguousarray(tet, dtype=np.int32)
+        wf = np.ascontiguousarray(wall_faces, dtype=np.int32).reshape(-1, 3)
+        self._check(self._lib.felbm3d_upload_mesh(self._h, xyz.shape[0], _dptr(xyz), tet.shape[0],
+                                                  tet.ctypes.data_as(_I), wf.shape[0], wf.ctypes.data_as(_I),
+                                                  float(period[0]), float(period[1])))
+        self.n_nodes, self.n_tets = xyz.shape[0], tet.shape[0]
+
+    def set_wetting(self, omega_c):
+        om = _f64(omega_c, (self.n_nodes,))
+        self._check(self._lib.felbm3d_set_wetting(self._h, _dptr(om)))
+
+    def init(self, C, u=None, p=None):
+        C = _f64(C, (self.n_nodes,))
+        u = None if u is None else _f64(u, (self.n_nodes, 3))
+        p = None if p is None else _f64(p, (self.n_nodes,))
+        self._check(self._lib.felbm3d_init(self._h, _dptr(C), None if u is None else _dptr(u),
+                                           None if p is None else _dptr(p)))
+
+    def step(self, n=1):
+        self._check(self._lib.felbm3d_step(self._h, int(n)))
+
+    def step_async(self, n=1):
+        self._check(self._lib.felbm3d_step_async(self._h, int(n)))
+
+    def read(self, field):
+        fid = FIELDS[field] if isinstance(field, str) else int(field)
+        out = np.empty(self.n_tets if fid == FIELDS["LAPMU"] else self.n_nodes)
+        self._check(self._lib.felbm3d_read(self._h, fid, _dptr(out)))
+        return out
+
+    def read_populations(self):
+        out = np.empty((38, self.n_nodes))
+        self._check(self._lib.felbm3d_read_populations(self._h, _dptr(out)))
+        return out
+
+    def diagnostics(self):
+        d = Diag()
+        self._check(self._lib.felbm3d_diagnostics(self._h, ct.byref(d)))
+        return d.as_dict()
+
+    def bind_stream(self, stream_handle):
+        self._check(self._lib.felbm3d_bind_stream(self._h, None if stream_handle is None else ct.c_void_p(stream_handle)))
+
+    def kernel_timing(self, enable=True):
+        self._check(self._lib.felbm3d_kernel_timing(self._h, 1 if enable else 0))
+
+    def kernel_stats(self):
+        buf = (KStat * 32)()
+        n = ct.c_int32()
+        self._check(self._lib.felbm3d_kernel_stats(self._h, buf, 32, ct.byref(n)))
+        return [{"name": buf[k].name.decode(), "launches": buf[k].launches, "total_ms": buf[k].total_ms,
+                 "bytes_per_launch": buf[k].bytes_per_launch} for k in range(n.value)]
+
+    def mesh_info(self):
+        v = [ct.c_int64() for _ in range(4)]
+        self._check(self._lib.felbm3d_mesh_info(self._h, *[ct.byref(x) for x in v]))
+        return dict(zip(["n_nodes", "n_tets", "n_wall_faces", "mass_offdiag_nnz"], [x.value for x in v]))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.felbm3d_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
