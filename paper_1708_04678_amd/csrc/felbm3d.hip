@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -33,6 +34,10 @@ inline int grid_for(int64_t n) {
   return (int)std::max<int64_t>(b, 8);
 }
 
+// one thread per node and population set: a block of four 64-node slices per
+// set, the g blocks in the first half of the grid and the h blocks in the second
+inline int grid_sets_for(int64_t n) { return 2 * grid_for(n); }
+
 // Host-side mesh preparation (caller order kept).
 struct Prep3 {
   int64_t N = 0, Np = 0, E = 0, W = 0, nnz = 0;
@@ -46,6 +51,11 @@ struct Prep3 {
   std::vector<double> mass, pvol;
   std::vector<int32_t> sell_ptr, sell_col;
   std::vector<double> sell_val;
+  // right-hand side: incident elements (alpha0 = V/m_i, beta0 = V grad N_i / m_i) and patch
+  // moments (G0_ij = sum V grad N_j / m_i; S0_ij = sum V grad N_i grad N_j^T / m_i as xx, yy, zz
+  // and the doubled symmetric xy, xz, yz), both in sliced ELL; dt factors applied at upload
+  std::vector<int32_t> inc_ptr, inc_e, pair_ptr, pair_col;
+  std::vector<double> inc_w, pair_v;  // [4][inc slots], [9][pair slots]
 };
 
 struct FaceRec {
@@ -278,6 +288,98 @@ int prepare3(int64_t N, const double* xyz, int64_t E, const int32_t* tet, int64_
       }
     m.sell_ptr[s + 1] = (int32_t)m.sell_col.size();
   }
+  // incident-element weights in sliced ELL (padding: element -1)
+  m.inc_ptr.assign(nslices + 1, 0);
+  {
+    std::vector<int32_t> ie;
+    std::vector<double> iw[4];
+    for (int64_t s = 0; s < nslices; ++s) {
+      int64_t width = 0;
+      for (int64_t i = s * 64; i < std::min<int64_t>(N, (s + 1) * 64); ++i)
+        width = std::max<int64_t>(width, m.n2e_ptr[i + 1] - m.n2e_ptr[i]);
+      const size_t base = ie.size();
+      ie.resize(base + width * 64, -1);
+      for (auto& v : iw) v.resize(base + width * 64, 0.0);
+      for (int64_t i = s * 64; i < std::min<int64_t>(N, (s + 1) * 64); ++i)
+        for (int32_t q = m.n2e_ptr[i]; q < m.n2e_ptr[i + 1]; ++q) {
+          const int64_t e = m.n2e[q] >> 2, l = m.n2e[q] & 3;
+          const size_t idx = base + (size_t)(q - m.n2e_ptr[i]) * 64 + (size_t)(i - s * 64);
+          ie[idx] = (int32_t)e;
+          iw[0][idx] = m.geo[e] / m.mass[i];
+          for (int r = 0; r < 3; ++r) iw[1 + r][idx] = m.geo[e] * m.geo[(1 + 3 * l + r) * E + e] / m.mass[i];
+        }
+      m.inc_ptr[s + 1] = (int32_t)ie.size();
+    }
+    m.inc_e = std::move(ie);
+    m.inc_w.resize(4 * m.inc_e.size());
+    for (int c = 0; c < 4; ++c) std::copy(iw[c].begin(), iw[c].end(), m.inc_w.begin() + c * m.inc_e.size());
+  }
+  // patch moments: the row of node i holds i and every node sharing an element with it
+  {
+    std::vector<int32_t> pos(N, -1), cols;
+    std::vector<std::array<double, 9>> vals;
+    std::vector<int32_t> pptr(N + 1, 0), pcol;
+    std::vector<std::array<double, 9>> pval;
+    for (int64_t i = 0; i < N; ++i) {
+      cols.clear();
+      vals.clear();
+      for (int32_t q = m.n2e_ptr[i]; q < m.n2e_ptr[i + 1]; ++q) {
+        const int64_t e = m.n2e[q] >> 2, l = m.n2e[q] & 3;
+        const double V = m.geo[e];
+        const double gi[3] = {m.geo[(1 + 3 * l) * E + e], m.geo[(2 + 3 * l) * E + e], m.geo[(3 + 3 * l) * E + e]};
+        for (int v = 0; v < 4; ++v) {
+          const int32_t j = tet[4 * e + v];
+          if (pos[j] < 0) {
+            pos[j] = (int32_t)cols.size();
+            cols.push_back(j);
+            vals.push_back(std::array<double, 9>{});
+          }
+          std::array<double, 9>& a = vals[pos[j]];
+          const double gj[3] = {m.geo[(1 + 3 * v) * E + e], m.geo[(2 + 3 * v) * E + e], m.geo[(3 + 3 * v) * E + e]};
+          for (int r = 0; r < 3; ++r) {
+            a[r] += V * gj[r];
+            a[3 + r] += V * gi[r] * gj[r];
+          }
+          a[6] += V * (gi[0] * gj[1] + gi[1] * gj[0]);
+          a[7] += V * (gi[0] * gj[2] + gi[2] * gj[0]);
+          a[8] += V * (gi[1] * gj[2] + gi[2] * gj[1]);
+        }
+      }
+      std::vector<int32_t> order(cols.size());
+      for (size_t k = 0; k < order.size(); ++k) order[k] = (int32_t)k;
+      std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cols[x] < cols[y]; });
+      for (int32_t k : order) {
+        pcol.push_back(cols[k]);
+        std::array<double, 9> a = vals[k];
+        for (double& v : a) v /= m.mass[i];
+        pval.push_back(a);
+        pos[cols[k]] = -1;
+      }
+      pptr[i + 1] = (int32_t)pcol.size();
+    }
+    m.pair_ptr.assign(nslices + 1, 0);
+    std::vector<double> pv[9];
+    for (int64_t s = 0; s < nslices; ++s) {
+      int64_t width = 0;
+      for (int64_t i = s * 64; i < std::min<int64_t>(N, (s + 1) * 64); ++i)
+        width = std::max<int64_t>(width, pptr[i + 1] - pptr[i]);
+      const size_t base = m.pair_col.size();
+      m.pair_col.resize(base + width * 64);
+      for (auto& v : pv) v.resize(base + width * 64, 0.0);
+      for (int64_t k = 0; k < width; ++k)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int64_t i = s * 64 + lane;
+          const size_t idx = base + k * 64 + lane;
+          const bool real_entry = i < N && k < pptr[i + 1] - pptr[i];
+          m.pair_col[idx] = real_entry ? pcol[pptr[i] + k] : (int32_t)std::min<int64_t>(i, N - 1);
+          if (real_entry)
+            for (int c = 0; c < 9; ++c) pv[c][idx] = pval[pptr[i] + k][c];
+        }
+      m.pair_ptr[s + 1] = (int32_t)m.pair_col.size();
+    }
+    m.pair_v.resize(9 * m.pair_col.size());
+    for (int c = 0; c < 9; ++c) std::copy(pv[c].begin(), pv[c].end(), m.pair_v.begin() + c * m.pair_col.size());
+  }
   return FELBM_OK;
 }
 
@@ -300,6 +402,9 @@ struct felbm3d_ctx {
   std::vector<double> cheb_w;
   int32_t *tet = nullptr, *fnbr = nullptr, *n2e_ptr = nullptr, *n2e = nullptr, *wf_ptr = nullptr, *wf_list = nullptr;
   int32_t *wface = nullptr, *sell_ptr = nullptr, *sell_col = nullptr, *first_bad = nullptr;
+  int32_t *inc_ptr = nullptr, *inc_e = nullptr, *pair_ptr = nullptr, *pair_col = nullptr;
+  int64_t inc_slots = 0, pair_slots = 0;
+  void *inc_w = nullptr, *pair_v = nullptr, *fpar = nullptr;
   double *geo = nullptr, *warea = nullptr, *bc = nullptr, *mass = nullptr, *pvol = nullptr, *eflux = nullptr;
   uint8_t* is_wall = nullptr;
   void *sell_val = nullptr, *pop = nullptr, *f = nullptr, *xa = nullptr, *xb = nullptr, *pn = nullptr, *un = nullptr,
@@ -438,13 +543,14 @@ int enqueue_fields(felbm3d_ctx* c, bool collide, DiagRecord* rec) {
                c->lapC, c->mu));
   TRY3(launch3(c, K3_GRADMU, k3_elem_gradmu, gE, BLOCK, E, (const int*)c->tet, (const double*)c->geo,
                (const double*)c->mu, c->gmu));
-  return launch3(c, K3_LAPMU, k3_elem_lapmu, gE, BLOCK, E, (const int*)c->fnbr, (const double*)c->geo,
-                 (const double*)c->gmu, c->lapmu);
+  return launch3(c, K3_LAPMU, k3_elem_lapmu_force<real>, gE, BLOCK, E, Np, (const int*)c->tet, (const int*)c->fnbr,
+                 (const double*)c->geo, (const double*)c->gmu, (const double*)c->gC, (const real*)c->gp,
+                 (const double*)c->Cn, (const double*)c->mu, (const real*)c->un, c->sp, c->lapmu, (real*)c->fpar);
 }
 
 template <typename real, int MODE>
 int sweep3(felbm3d_ctx* c, int kid, const real* xin, real* xout, real w) {
-  return launch3(c, kid, k3_sweep<real, MODE>, grid_for(c->N), BLOCK, (int)c->N, (int)c->Np, (const int*)c->sell_ptr,
+  return launch3(c, kid, k3_sweep<real, MODE>, grid_sets_for(c->N), BLOCK, (int)c->N, (int)c->Np, (const int*)c->sell_ptr,
                  (const int*)c->sell_col, (const real*)c->sell_val, (const real*)c->f, xin, xout, (real*)c->pop,
                  (const uint8_t*)c->is_wall, w);
 }
@@ -452,11 +558,10 @@ int sweep3(felbm3d_ctx* c, int kid, const real* xin, real* xout, real w) {
 template <typename real>
 int enqueue_step(felbm3d_ctx* c) {
   TRY3(enqueue_fields<real>(c, true, c->hist + (c->step & 1)));
-  const int gN = grid_for(c->N);
-  TRY3(launch3(c, K3_RHS, k3_rhs<real>, gN, BLOCK, (int)c->N, (int)c->Np, (int)c->E, (const int*)c->n2e_ptr,
-               (const int*)c->n2e, (const int*)c->tet, (const double*)c->geo, (const double*)c->gC, (const real*)c->gp,
-               (const double*)c->lapmu, (const double*)c->Cn, (const real*)c->un, (const double*)c->mu,
-               (const real*)c->pop, (const double*)c->mass, c->sp, (real*)c->f));
+  TRY3(launch3(c, K3_RHS, k3_rhs<real>, grid_sets_for(c->N), BLOCK, (int)c->N, (int)c->Np, (int)c->E,
+               (const int*)c->inc_ptr, (const int*)c->inc_e, (const real*)c->inc_w, (int)c->inc_slots,
+               (const real*)c->fpar, (const int*)c->pair_ptr, (const int*)c->pair_col, (const real*)c->pair_v,
+               (int)c->pair_slots, (const real*)c->pop, (real*)c->f));
   const int K = c->prm.solver_sweeps;
   real *xa = (real*)c->xa, *xb = (real*)c->xb;
   if (K == 0) {
@@ -591,6 +696,15 @@ int felbm3d_upload_mesh(felbm3d_ctx* c, int64_t n_nodes, const double* xyz, int6
   TRY3(dalloc(c, &c->sell_ptr, m.sell_ptr.size()));
   TRY3(dalloc(c, &c->sell_col, m.sell_col.size()));
   TRY3(dalloc_bytes(c, &c->sell_val, m.sell_val.size() * rs));
+  c->inc_slots = (int64_t)m.inc_e.size();
+  c->pair_slots = (int64_t)m.pair_col.size();
+  TRY3(dalloc(c, &c->inc_ptr, m.inc_ptr.size()));
+  TRY3(dalloc(c, &c->inc_e, m.inc_e.size()));
+  TRY3(dalloc(c, &c->pair_ptr, m.pair_ptr.size()));
+  TRY3(dalloc(c, &c->pair_col, m.pair_col.size()));
+  TRY3(dalloc_bytes(c, &c->inc_w, m.inc_w.size() * rs));
+  TRY3(dalloc_bytes(c, &c->pair_v, m.pair_v.size() * rs));
+  TRY3(dalloc_bytes(c, &c->fpar, 13 * E * rs));
   TRY3(dalloc_bytes(c, &c->pop, 38 * Np * rs));
   TRY3(dalloc_bytes(c, &c->f, 38 * Np * rs));
   TRY3(dalloc_bytes(c, &c->xa, 38 * Np * rs));
@@ -622,11 +736,25 @@ int felbm3d_upload_mesh(felbm3d_ctx* c, int64_t n_nodes, const double* xyz, int6
   TRY3(upload(c, c->pvol, m.pvol));
   TRY3(upload(c, c->sell_ptr, m.sell_ptr));
   TRY3(upload(c, c->sell_col, m.sell_col));
+  TRY3(upload(c, c->inc_ptr, m.inc_ptr));
+  TRY3(upload(c, c->inc_e, m.inc_e));
+  TRY3(upload(c, c->pair_ptr, m.pair_ptr));
+  TRY3(upload(c, c->pair_col, m.pair_col));
+  // dt factors of the right-hand side: dt/4 on alpha and G, dt^2/2 on beta and S
+  const double c1 = c->prm.dt / 4.0, c2 = 0.5 * c->prm.dt * c->prm.dt;
+  for (size_t q = 0; q < m.inc_w.size(); ++q) m.inc_w[q] *= (q < m.inc_e.size()) ? c1 : c2;
+  for (size_t q = 0; q < m.pair_v.size(); ++q) m.pair_v[q] *= (q < 3 * m.pair_col.size()) ? c1 : c2;
   if (c->prm.precision == FELBM_FP64) {
     TRY3(upload(c, (double*)c->sell_val, m.sell_val));
+    TRY3(upload(c, (double*)c->inc_w, m.inc_w));
+    TRY3(upload(c, (double*)c->pair_v, m.pair_v));
+    HIP_OK3(c, hipStreamSynchronize(c->stream));
   } else {
-    std::vector<float> v32(m.sell_val.begin(), m.sell_val.end());
+    std::vector<float> v32(m.sell_val.begin(), m.sell_val.end()), w32(m.inc_w.begin(), m.inc_w.end()),
+        p32(m.pair_v.begin(), m.pair_v.end());
     TRY3(upload(c, (float*)c->sell_val, v32));
+    TRY3(upload(c, (float*)c->inc_w, w32));
+    TRY3(upload(c, (float*)c->pair_v, p32));
     HIP_OK3(c, hipStreamSynchronize(c->stream));
   }
   std::vector<double> zeros(N, 0.0);
@@ -645,8 +773,9 @@ int felbm3d_upload_mesh(felbm3d_ctx* c, int64_t n_nodes, const double* xyz, int6
   c->bytes[K3_FFLUX] = Ed * (16 + 104 + 24 + 32);
   c->bytes[K3_LAPC] = Nd * (4 + 8 + 8 + 8 + 8 + 8 + 4) + 4 * Ed * (4 + 8);
   c->bytes[K3_GRADMU] = Ed * (16 + 96 + 24) + Nd * 8;
-  c->bytes[K3_LAPMU] = Ed * (16 + 96 + 24 + 8);
-  c->bytes[K3_RHS] = 2 * pops + Nd * (4 + 8 + 8 + 3 * s + 8) + 4 * Ed * 4 + Ed * (16 + 104 + 24 + 3 * s + 8);
+  c->bytes[K3_LAPMU] = Ed * (16 + 16 + 96 + 24 + 8 + 24 + 3 * s + 13 * s) + Nd * (8 + 8 + 3 * s);
+  c->bytes[K3_RHS] = 2 * pops + (double)m.inc_e.size() * (4 + 4 * s) + (double)m.pair_col.size() * (4 + 9 * s) +
+                     Ed * 13 * s;
   c->bytes[K3_SWEEP_FIRST] = 2 * pops + mat;
   c->bytes[K3_SWEEP_MID] = 3 * pops + mat;
   c->bytes[K3_SWEEP_LAST] = 4 * pops + mat + Nd;

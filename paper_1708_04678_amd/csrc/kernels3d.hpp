@@ -15,6 +15,8 @@
 //   areas [W])
 //   mass matrix  diag(m)^-1 M11 off-diagonal part, sliced ELL (slice 64);
 //                its diagonal is M11_ii / m_i = 2/5 for P1 tetrahedra
+//   right-hand side: incident-element weights [4][slots] and patch moments
+//                [9][slots] in sliced ELL; element force parameters [13][E]
 #pragma once
 
 #include "common.hpp"
@@ -237,9 +239,20 @@ __global__ void __launch_bounds__(BLOCK) k3_elem_gradmu(int E, const int* __rest
   for (int r = 0; r < 3; ++r) gmu[r * E + e] = c[r];
 }
 
-__global__ void __launch_bounds__(BLOCK) k3_elem_lapmu(int E, const int* __restrict__ fnbr,
-                                                      const double* __restrict__ geo, const double* __restrict__ gmu,
-                                                      double* __restrict__ lapmu) {
+// a4 + a5: element Laplacian of mu (FP64), fused with the element's force
+// parameters at the barycentric values (eq:G, eq:H): for the g set
+// A = (rho_l - rho_v) c_s^2 grad C_T and B = mu_bar grad C_T, for the h set
+// X = grad C_T - C_bar / (rho_bar c_s^2) (grad p_T - mu_bar grad C_T) and
+// d = M lap mu_T; both with u_bar.  Stored [13][E] as (u_bar, A, B, X, d).
+template <typename real>
+__global__ void __launch_bounds__(BLOCK) k3_elem_lapmu_force(int E, int Np, const int* __restrict__ tet,
+                                                            const int* __restrict__ fnbr,
+                                                            const double* __restrict__ geo,
+                                                            const double* __restrict__ gmu,
+                                                            const double* __restrict__ gC, const real* __restrict__ gp,
+                                                            const double* __restrict__ Cn, const double* __restrict__ mu,
+                                                            const real* __restrict__ un, StepParams P,
+                                                            double* __restrict__ lapmu, real* __restrict__ fpar) {
   const int e = xcd_block() * BLOCK + threadIdx.x;
   if (e >= E) return;
   const double tx = gmu[e], ty = gmu[E + e], tz = gmu[2 * E + e];
@@ -251,148 +264,198 @@ __global__ void __launch_bounds__(BLOCK) k3_elem_lapmu(int E, const int* __restr
       acc += geo[(1 + 3 * l) * E + e] * (tx + gmu[nb]) + geo[(2 + 3 * l) * E + e] * (ty + gmu[E + nb]) +
              geo[(3 + 3 * l) * E + e] * (tz + gmu[2 * E + nb]);
   }
-  lapmu[e] = -1.5 * acc;
+  const double lm = -1.5 * acc;
+  lapmu[e] = lm;
+  double Cb = 0.0, mub = 0.0;
+  real ubx = 0, uby = 0, ubz = 0;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int v = tet[t * E + e];
+    Cb += Cn[v];
+    mub += mu[v];
+    ubx += un[v];
+    uby += un[Np + v];
+    ubz += un[2 * Np + v];
+  }
+  Cb *= 0.25;
+  mub *= 0.25;
+  const double gCx = gC[e], gCy = gC[E + e], gCz = gC[2 * E + e];
+  const real drho_cs2 = (real)(CS2 * (P.rho_l - P.rho_v));
+  const real rhob = (real)(Cb * P.rho_l + (1.0 - Cb) * P.rho_v);
+  const real bx = (real)(mub * gCx), by = (real)(mub * gCy), bz = (real)(mub * gCz);
+  const real coef = (real)Cb / (rhob * (real)CS2);
+  real* __restrict__ o = fpar + e;
+  o[0] = ubx * (real)0.25;
+  o[E] = uby * (real)0.25;
+  o[2 * E] = ubz * (real)0.25;
+  o[3 * E] = drho_cs2 * (real)gCx;
+  o[4 * E] = drho_cs2 * (real)gCy;
+  o[5 * E] = drho_cs2 * (real)gCz;
+  o[6 * E] = bx;
+  o[7 * E] = by;
+  o[8 * E] = bz;
+  o[9 * E] = (real)gCx - coef * (gp[e] - bx);
+  o[10 * E] = (real)gCy - coef * (gp[E + e] - by);
+  o[11 * E] = (real)gCz - coef * (gp[2 * E + e] - bz);
+  o[12 * E] = (real)(P.mobility * lm);
 }
 
-// a5 + a7: P0 forces (eq:G, eq:H at the barycentric values, eq:intF) fused
-// into the node gather of the streaming right-hand side (eq:galerkin_lbm):
-//   b_{a,i} = sum_{T ni i} V_T q_{a,T} (dt/4 + dt^2/2 e_a . grad N_i|_T),
-//   q_{a,T} = Phi_{a,T} - e_a . sum_v psi_hat_{a,v} grad N_v;  f = b / m_i.
+// a5 + a7: the Galerkin right-hand side (eq:galerkin_lbm) divided by m_i,
+// one thread per (node, population set).  With weights alpha = (dt/4) V_T / m_i
+// and beta = (dt^2/2) V_T grad N_i|_T / m_i of each incident element and the
+// patch moments G_ij = (dt/4) sum_T V_T grad N_j / m_i and
+// S_ij = (dt^2/2) sum_T V_T (grad N_i grad N_j^T) / m_i (held as xx, yy, zz and
+// the doubled symmetric xy, xz, yz), both precomputed from the geometry:
+//   f_{a,i} = sum_T (alpha + e_a . beta) Phi_{a,T}
+//           - sum_j psi_hat_{a,j} (e_a . G_ij + e_a . S_ij e_a),
+// which is b_{a,i}/m_i with q_{a,T} = Phi_{a,T} - e_a . sum_v psi_hat_{a,v} grad N_v
+// regrouped by node (each psi_hat value is gathered once per patch node instead
+// of once per incident element).  The first half of the grid computes the g
+// set, the second half the h set, four 64-node slices per block.  Element weights and patch moments are in
+// sliced-ELL order (slice of 64 nodes, entry k of lane l at base + 64 k + l).
 template <typename real>
-__global__ void __launch_bounds__(BLOCK) k3_rhs(int N, int Np, int E, const int* __restrict__ n2e_ptr,
-                                               const int* __restrict__ n2e, const int* __restrict__ tet,
-                                               const double* __restrict__ geo, const double* __restrict__ gC,
-                                               const real* __restrict__ gp, const double* __restrict__ lapmu,
-                                               const double* __restrict__ Cn, const real* __restrict__ un,
-                                               const double* __restrict__ mu, const real* __restrict__ pop,
-                                               const double* __restrict__ mass, StepParams P, real* __restrict__ f) {
-  const int i = xcd_block() * BLOCK + threadIdx.x;
+__global__ void __launch_bounds__(BLOCK) k3_rhs(int N, int Np, int E, const int* __restrict__ inc_ptr,
+                                               const int* __restrict__ inc_e, const real* __restrict__ inc_w,
+                                               int inc_slots, const real* __restrict__ fpar,
+                                               const int* __restrict__ pair_ptr, const int* __restrict__ pair_col,
+                                               const real* __restrict__ pair_v, int pair_slots,
+                                               const real* __restrict__ pop, real* __restrict__ f) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int blk = xcd_block(), half = gridDim.x >> 1;
+  const bool hset = blk >= half;
+  const int slice = (blk - (hset ? half : 0)) * 4 + wave;
+  const int i = (slice << 6) + lane;
   if (i >= N) return;
-  real b[NPOP];
+  real b[Q];
 #pragma unroll
-  for (int a = 0; a < NPOP; ++a) b[a] = (real)0;
-  const real dt = (real)P.dt, c1 = dt / (real)4, c2 = (real)0.5 * dt * dt;
-  const real drho_cs2 = (real)(CS2 * (P.rho_l - P.rho_v));
-  for (int q = n2e_ptr[i]; q < n2e_ptr[i + 1]; ++q) {
-    const int packed = n2e[q];
-    const int e = packed >> 2, l = packed & 3;
-    int v[4];
-    real gx[4], gy[4], gz[4];
-    double Cb = 0.0, mub = 0.0;
-    real ubx = 0, uby = 0, ubz = 0;
+  for (int a = 0; a < Q; ++a) b[a] = (real)0;
+  {
+    const int base = inc_ptr[slice], width = (inc_ptr[slice + 1] - base) >> 6;
+    for (int k = 0; k < width; ++k) {
+      const int idx = base + (k << 6) + lane;
+      const int e = inc_e[idx];
+      if (e < 0) continue;
+      const real al = inc_w[idx], btx = inc_w[inc_slots + idx], bty = inc_w[2 * inc_slots + idx],
+                 btz = inc_w[3 * inc_slots + idx];
+      const real ux = fpar[e], uy = fpar[E + e], uz = fpar[2 * E + e];
+      const real uu = ux * ux + uy * uy + uz * uz;
+      if (!hset) {
+        const real Ax = fpar[3 * E + e], Ay = fpar[4 * E + e], Az = fpar[5 * E + e];
+        const real Bx = fpar[6 * E + e], By = fpar[7 * E + e], Bz = fpar[8 * E + e];
+        const real uA = ux * Ax + uy * Ay + uz * Az, uB = ux * Bx + uy * By + uz * Bz;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      v[t] = tet[t * E + e];
-      gx[t] = (real)geo[(1 + 3 * t) * E + e];
-      gy[t] = (real)geo[(2 + 3 * t) * E + e];
-      gz[t] = (real)geo[(3 + 3 * t) * E + e];
-      Cb += Cn[v[t]];
-      mub += mu[v[t]];
-      ubx += un[v[t]];
-      uby += un[Np + v[t]];
-      ubz += un[2 * Np + v[t]];
-    }
-    Cb *= 0.25;
-    mub *= 0.25;
-    ubx *= (real)0.25;
-    uby *= (real)0.25;
-    ubz *= (real)0.25;
-    const real A = (real)geo[e];
-    const double rhobd = Cb * P.rho_l + (1.0 - Cb) * P.rho_v;
-    const real rhob = (real)rhobd;
-    const double gCx = gC[e], gCy = gC[E + e], gCz = gC[2 * E + e];
-    const real gpx = gp[e], gpy = gp[E + e], gpz = gp[2 * E + e];
-    const real ax = drho_cs2 * (real)gCx, ay = drho_cs2 * (real)gCy, az = drho_cs2 * (real)gCz;
-    const real bx = (real)(mub * gCx), by = (real)(mub * gCy), bz = (real)(mub * gCz);
-    const real coef = (real)Cb / (rhob * (real)CS2);
-    const real Xx = (real)gCx - coef * (gpx - bx), Xy = (real)gCy - coef * (gpy - by), Xz = (real)gCz - coef * (gpz - bz);
-    const real d = (real)(P.mobility * lapmu[e]);
-    const real uA = ubx * ax + uby * ay + ubz * az, uB = ubx * bx + uby * by + ubz * bz;
-    const real uX = ubx * Xx + uby * Xy + ubz * Xz, uu = ubx * ubx + uby * uby + ubz * ubz;
-    const real gxl = l == 0 ? gx[0] : l == 1 ? gx[1] : l == 2 ? gx[2] : gx[3];
-    const real gyl = l == 0 ? gy[0] : l == 1 ? gy[1] : l == 2 ? gy[2] : gy[3];
-    const real gzl = l == 0 ? gz[0] : l == 1 ? gz[1] : l == 2 ? gz[2] : gz[3];
+        for (int a = 0; a < Q; ++a) {
+          const real exa = (real)ex(a), eya = (real)ey(a), eza = (real)ez(a);
+          const real eu = exa * ux + eya * uy + eza * uz;
+          const real G = (real)wq(a) * ((real)1 + (real)3 * eu + (real)4.5 * eu * eu - (real)1.5 * uu);
+          const real Phi = (exa * Ax + eya * Ay + eza * Az - uA) * (G - (real)wq(a)) +
+                           (exa * Bx + eya * By + eza * Bz - uB) * G;
+          b[a] += (al + exa * btx + eya * bty + eza * btz) * Phi;
+        }
+      } else {
+        const real Xx = fpar[9 * E + e], Xy = fpar[10 * E + e], Xz = fpar[11 * E + e], d = fpar[12 * E + e];
+        const real uX = ux * Xx + uy * Xy + uz * Xz;
 #pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      const real exa = (real)ex(a), eya = (real)ey(a), eza = (real)ez(a);
-      const real eu = exa * ubx + eya * uby + eza * ubz;
-      const real G = (real)wq(a) * ((real)1 + (real)3 * eu + (real)4.5 * eu * eu - (real)1.5 * uu);
-      const real Phig = (exa * ax + eya * ay + eza * az - uA) * (G - (real)wq(a)) + (exa * bx + eya * by + eza * bz - uB) * G;
-      const real Phih = (exa * Xx + eya * Xy + eza * Xz - uX + d) * G;
-      real sg = 0, sh = 0;
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const real en = exa * gx[t] + eya * gy[t] + eza * gz[t];
-        sg += pop[a * Np + v[t]] * en;
-        sh += pop[(Q + a) * Np + v[t]] * en;
+        for (int a = 0; a < Q; ++a) {
+          const real exa = (real)ex(a), eya = (real)ey(a), eza = (real)ez(a);
+          const real eu = exa * ux + eya * uy + eza * uz;
+          const real G = (real)wq(a) * ((real)1 + (real)3 * eu + (real)4.5 * eu * eu - (real)1.5 * uu);
+          b[a] += (al + exa * btx + eya * bty + eza * btz) * ((exa * Xx + eya * Xy + eza * Xz - uX + d) * G);
+        }
       }
-      const real enl = exa * gxl + eya * gyl + eza * gzl;
-      const real wgt = A * (c1 + c2 * enl);
-      b[a] += wgt * (Phig - sg);
-      b[Q + a] += wgt * (Phih - sh);
     }
   }
-  const real inv_m = (real)(1.0 / mass[i]);
+  const real* __restrict__ ps = pop + (hset ? (size_t)Q * Np : 0);
+  {
+    const int base = pair_ptr[slice], width = (pair_ptr[slice + 1] - base) >> 6;
+    for (int k = 0; k < width; ++k) {
+      const int idx = base + (k << 6) + lane;
+      const int j = pair_col[idx];
+      const real Gx = pair_v[idx], Gy = pair_v[pair_slots + idx], Gz = pair_v[2 * pair_slots + idx];
+      const real Sxx = pair_v[3 * pair_slots + idx], Syy = pair_v[4 * pair_slots + idx],
+                 Szz = pair_v[5 * pair_slots + idx], Sxy = pair_v[6 * pair_slots + idx],
+                 Sxz = pair_v[7 * pair_slots + idx], Syz = pair_v[8 * pair_slots + idx];
 #pragma unroll
-  for (int a = 0; a < NPOP; ++a) f[a * Np + i] = b[a] * inv_m;
+      for (int a = 0; a < Q; ++a) {
+        const real exa = (real)ex(a), eya = (real)ey(a), eza = (real)ez(a);
+        const real c = exa * Gx + eya * Gy + eza * Gz + exa * exa * Sxx + eya * eya * Syy + eza * eza * Szz +
+                       exa * eya * Sxy + exa * eza * Sxz + eya * eza * Syz;
+        b[a] -= c * ps[a * Np + j];
+      }
+    }
+  }
+  real* __restrict__ fo = f + (hset ? (size_t)Q * Np : 0);
+#pragma unroll
+  for (int a = 0; a < Q; ++a) fo[a * Np + i] = b[a];
 }
 
 // a8: Richardson sweeps with the reciprocal Chebyshev roots on [1/5, 1] (the
 // spectrum of diag(m)^-1 M11 for P1 tetrahedra), x0 = f; (A x)_i = 2/5 x_i +
 // sum_j a_ij x_j.  MODE 0 first (x = f), 1 middle, 2 last (+ psi_hat and the
-// wall operator), 3 single, 4 none (psi_hat + f).
+// wall operator), 3 single, 4 none (psi_hat + f).  One thread per (node,
+// population set): the first half of the grid sweeps the 19 g populations, the
+// second half the 19 h populations (opposite pairs stay within one thread for
+// the wall operator), each block four 64-node matrix slices.  Keeping a block
+// on one set measured 2.3x faster than splitting a block's waves between the
+// sets.
 template <typename real, int MODE>
 __global__ void __launch_bounds__(BLOCK) k3_sweep(int N, int Np, const int* __restrict__ sell_ptr,
                                                  const int* __restrict__ sell_col, const real* __restrict__ sell_val,
                                                  const real* __restrict__ f, const real* __restrict__ xin,
                                                  real* __restrict__ xout, real* __restrict__ pop,
                                                  const uint8_t* __restrict__ is_wall, real w) {
-  const int i = xcd_block() * BLOCK + threadIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int b = xcd_block(), half = gridDim.x >> 1;
+  const bool hset = b >= half;
+  const int slice = (b - (hset ? half : 0)) * 4 + wave;
+  const int i = (slice << 6) + lane;
   if (i >= N) return;
-  const real* __restrict__ x = (MODE == 0 || MODE == 3) ? f : xin;
-  real r[NPOP];
+  const size_t off = hset ? (size_t)Q * Np : 0;
+  const real* __restrict__ fs = f + off;
+  const real* __restrict__ x = (MODE == 0 || MODE == 3) ? fs : xin + off;
+  real r[Q];
   if (MODE != 4) {
 #pragma unroll
-    for (int a = 0; a < NPOP; ++a) r[a] = (real)0.4 * x[a * Np + i];
-    const int slice = i >> 6, lane = i & 63;
+    for (int a = 0; a < Q; ++a) r[a] = (real)0.4 * x[a * Np + i];
     const int base = sell_ptr[slice], width = (sell_ptr[slice + 1] - base) >> 6;
     for (int k = 0; k < width; ++k) {
       const int idx = base + (k << 6) + lane;
       const int j = sell_col[idx];
       const real aij = sell_val[idx];
 #pragma unroll
-      for (int a = 0; a < NPOP; ++a) r[a] += aij * x[a * Np + j];
+      for (int a = 0; a < Q; ++a) r[a] += aij * x[a * Np + j];
     }
 #pragma unroll
-    for (int a = 0; a < NPOP; ++a) {
+    for (int a = 0; a < Q; ++a) {
       const real xi = x[a * Np + i];
-      const real fi = (MODE == 0 || MODE == 3) ? xi : f[a * Np + i];
+      const real fi = (MODE == 0 || MODE == 3) ? xi : fs[a * Np + i];
       r[a] = xi + w * (fi - r[a]);
     }
   } else {
 #pragma unroll
-    for (int a = 0; a < NPOP; ++a) r[a] = f[a * Np + i];
+    for (int a = 0; a < Q; ++a) r[a] = fs[a * Np + i];
   }
   if (MODE == 0 || MODE == 1) {
 #pragma unroll
-    for (int a = 0; a < NPOP; ++a) xout[a * Np + i] = r[a];
+    for (int a = 0; a < Q; ++a) xout[off + a * Np + i] = r[a];
     return;
   }
-  real s[NPOP];
+  real* __restrict__ ps = pop + off;
 #pragma unroll
-  for (int a = 0; a < NPOP; ++a) s[a] = pop[a * Np + i] + r[a];
+  for (int a = 0; a < Q; ++a) r[a] += ps[a * Np + i];
   if (is_wall[i]) {
 #pragma unroll
     for (int a = 1; a < Q; ++a) {
       const int b = opp(a);
       if (b > a) {
-        const real mg = (real)0.5 * (s[a] + s[b]), mh = (real)0.5 * (s[Q + a] + s[Q + b]);
-        s[a] = mg; s[b] = mg; s[Q + a] = mh; s[Q + b] = mh;
+        const real m = (real)0.5 * (r[a] + r[b]);
+        r[a] = m;
+        r[b] = m;
       }
     }
   }
 #pragma unroll
-  for (int a = 0; a < NPOP; ++a) pop[a * Np + i] = s[a];
+  for (int a = 0; a < Q; ++a) ps[a * Np + i] = r[a];
 }
 
 // init: psi_bar^0 = psi_eq(C, u, p), then the wall operator

@@ -100,3 +100,59 @@ def test_fp32_vs_fp64_at_the_workload_horizon():
     assert max(abs(a - b) for a, b in zip(a32, a64)) < 0.5
     log(f"  max|u| rel diff {abs(d32['max_u'] - d64['max_u']) / d64['max_u']:.2e}, band KE rel diff "
         f"{abs(d32['band_ke'] - d64['band_ke']) / d64['band_ke']:.2e}")
+
+
+@pytest.fixture(scope="module")
+def sessile3d():
+    from workloads.mesh3d import sessile_drop_3d
+    return sessile_drop_3d()
+
+
+def test_3d_full_size_fields_match_oracle(sessile3d):
+    """The 3-D droplet at the paper's mesh size (1,490,944 nodes, 8,847,360
+    tetrahedra, layers refined toward the wall), FP64: every field of the
+    initial state (moments, the patch Laplacian of C with the wetting flux,
+    mu, the element Laplacian of mu) against the oracle's field chain on the
+    whole mesh (geometry only; its assembled matrices at this size need
+    30 GB), to 1e-13 of each field's largest value."""
+    from oracle import felbm3d_oracle as fo3
+    from test_gpu_3d import FIELD_NAMES, make_ctx3, oracle_fields
+    name, mesh, phys, C0, om, _ = sessile3d
+    log(f"3-D full size {name}: {mesh.n_nodes} nodes, {mesh.n_tets} tets; oracle fields")
+    o = fo3.Oracle3D(mesh, phys, om, with_matrices=False)
+    g, h = o.init_state(C0)
+    ref = oracle_fields(o, g, h)
+    ctx = make_ctx3(mesh, phys, om, sweeps=30)
+    ctx.init(C0)
+    for fname in FIELD_NAMES:
+        err = rel(ctx.read(fname), ref[fname])
+        log(f"  {fname}: max rel diff {err:.3e}")
+        assert err < 1e-13, fname
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision,sweeps,bar", [("fp64", 30, 1e-12), ("fp32", 13, 1e-5)])
+def test_3d_full_size_mass_and_determinism(sessile3d, precision, sweeps, bar):
+    """100 steps of the 3-D droplet at full size in the benchmark's launch
+    configuration: the lumped mass of C stays to rounding (FP32 stores the
+    populations in single precision, no compensated composition), the state
+    stays finite with no velocity at wall nodes, and two runs agree bitwise."""
+    from test_gpu_3d import make_ctx3
+    name, mesh, phys, C0, om, _ = sessile3d
+    log(f"3-D full size, 100 steps, {precision} K = {sweeps}: mass and bitwise repeat")
+    runs = []
+    walls = mesh.wall_nodes()
+    for _ in range(2):
+        ctx = make_ctx3(mesh, phys, om, precision=precision, sweeps=sweeps)
+        ctx.init(C0)
+        m0 = ctx.diagnostics()["mass"]
+        ctx.step(100)
+        d = ctx.diagnostics()
+        drift = abs(d["mass"] - m0) / m0
+        log(f"  mass drift {drift:.3e}  max|u| {d['max_u']:.6e}")
+        assert drift < bar and d["nonfinite"] == 0
+        for comp in ("UX", "UY", "UZ"):
+            assert np.abs(ctx.read(comp)[walls]).max() < 1e-6 * max(d["max_u"], 1e-30)
+        runs.append(ctx.read_populations())
+        ctx.close()
+    assert np.array_equal(runs[0], runs[1])

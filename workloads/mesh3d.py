@@ -103,8 +103,13 @@ def tet_box_mesh(lx: float, ly: float, lz: float, nx: int, ny: int, nz: int, see
         raise RuntimeError("tet_box_mesh produced a degenerate tetrahedron")
     # boundary faces: faces of exactly one tetrahedron
     faces = np.concatenate([tet[:, [1, 2, 3]], tet[:, [0, 3, 2]], tet[:, [0, 1, 3]], tet[:, [0, 2, 1]]])
-    key = np.sort(faces, axis=1)
-    _, inv, cnt = np.unique(key, axis=0, return_inverse=True, return_counts=True)
+    key = np.sort(faces, axis=1).astype(np.int64)
+    n = np.int64(xyz.shape[0])
+    if float(n) ** 3 < 2.0 ** 62:  # one int64 per sorted triple
+        _, inv, cnt = np.unique((key[:, 0] * n + key[:, 1]) * n + key[:, 2], return_inverse=True,
+                                return_counts=True)
+    else:
+        _, inv, cnt = np.unique(key, axis=0, return_inverse=True, return_counts=True)
     bnd = faces[cnt[inv.ravel()] == 1]
     zf = xyz[bnd, 2]
     side = np.full(len(bnd), -1, np.int8)
@@ -138,3 +143,36 @@ def wetting_from_angles_3d(mesh: TetMesh, theta_bottom_deg, theta_top_deg=90.0) 
         nodes = mesh.wall_nodes(side)
         om[nodes] = -np.cos(np.deg2rad(float(th)))
     return om
+
+
+def graded_z_rows(fine: float, fine_top: float, growth: float, coarse: float, nz: int) -> np.ndarray:
+    """nz + 1 layer heights from z = 0: spacing `fine` up to z = fine_top, then
+    growing by `growth` per layer up to `coarse`, then constant."""
+    z = [0.0]
+    h = fine
+    while len(z) < nz + 1:
+        if z[-1] + 1e-12 >= fine_top:
+            h = min(h * growth, coarse)
+        z.append(z[-1] + h)
+    return np.asarray(z)
+
+
+def sessile_drop_3d(nx: int = 128, ny: int = 128, nz: int = 90, R: float = 32.0, theta: float = 150.0,
+                    m_rho: float = 10.0, m_nu: float = 1.0, sigma: float = 0.0025, seed: int = 7):
+    """The 3-D droplet of the paper's equilibrium-shape study (Sec. III): a
+    hemisphere of radius R resting on the bottom wall of a box whose layers
+    are refined toward that wall, wetting potential of theta_eq on the bottom,
+    90 deg on the top.  Defaults: 128 x 128 unit columns, 90 layers of 0.5 up
+    to z = 16 growing by 6 % to 1.25 (top at z ~ 82); 1,490,944 nodes
+    (the paper's mesh holds 1.5e6), 8,847,360 tetrahedra; xi = 4, sigma = 0.0025,
+    mobility 0.02, dt = 0.05, tau_l = 1, densities and viscosities by
+    M_rho, M_nu.  Returns (name, mesh, physics, C0, Omega_c, droplets)."""
+    from .configs import make_physics
+    z_rows = graded_z_rows(0.5, 16.0, 1.06, 1.25, nz)
+    mesh = tet_box_mesh(float(nx), float(ny), float(z_rows[-1]), nx, ny, nz, seed=[seed], z_rows=z_rows)
+    phys = make_physics(sigma=sigma, m_rho=m_rho, m_nu=m_nu, dt=0.05)
+    drops = [(0.5 * nx, 0.5 * ny, 0.0, R)]
+    C0 = droplet_field_3d(mesh, drops, phys.xi)
+    om = wetting_from_angles_3d(mesh, theta, 90.0)
+    name = f"sessile3d-{nx}x{ny}x{nz}-R{R:g}-theta{theta:g}"
+    return name, mesh, phys, C0, om, drops
