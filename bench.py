@@ -456,7 +456,7 @@ def washburn_length(t, K, eta_l, eta_v, length, l0):
     return (-b + np.sqrt(b * b + 4.0 * a * c)) / (2.0 * a)
 
 
-def capillary_study(felbm, stream, sweeps32, samples=40, fill=0.75):
+def capillary_study(felbm, stream, sweeps32, samples=40, fill=0.75, length_widths=10.0):
     """Capillary intrusion into a 2-D channel (Sec. III.C in its 2-D form):
     for theta = 56, 72, 83 deg the liquid length l(t) = (liquid volume in the
     channel) / H against the Washburn law of `washburn_length`, run until the
@@ -465,12 +465,13 @@ def capillary_study(felbm, stream, sweeps32, samples=40, fill=0.75):
     eta_v L l]; and the law with a constant extra resistance eta_l l_e (the
     entrance, the reservoir and the moving contact lines), fitted jointly as
     (eta_l - eta_v) l^2 / 2 + eta_v L l + eta_l l_e l = K_fit t + c.  The
-    effective cos(theta) is 6 K_fit / (H sigma)."""
+    effective cos(theta) is 6 K_fit / (H sigma).  The channel is
+    `length_widths` widths long."""
     import numpy as np
     from workloads import capillary_channel
     rows = []
     for theta in (56.0, 72.0, 83.0):
-        w = capillary_channel(theta)
+        w = capillary_channel(theta, length=10.0 * length_widths)
         e, p = w.extra, w.phys
         H, L, l0 = e["width"], e["length"], e["l0"]
         eta_l, eta_v = p.rho_l * p.nu_l, p.rho_v * p.nu_v
@@ -489,6 +490,8 @@ def capillary_study(felbm, stream, sweeps32, samples=40, fill=0.75):
                 ctx.step(chunk)
             t = s * chunk * p.dt
             l_meas = float((m[inside] * ctx.read("C")[inside]).sum() / H)
+            if s % 5 == 0:
+                log(f"  sample {s}/{samples}: t {t:.0f}, l {l_meas:.2f}")
             trace.append((round(t, 3), round(l_meas, 4), round(float(washburn_length(t, K, eta_l, eta_v, L, l0)), 4)))
         d = ctx.diagnostics()
         ctx.close()
@@ -634,6 +637,8 @@ def main():
                          "to T viscous times")
     ap.add_argument("--capillary", action="store_true",
                     help="only run capillary intrusion into a channel (theta = 56, 72, 83 deg) against Washburn")
+    ap.add_argument("--capillary-length", type=float, default=10.0,
+                    help="channel length of --capillary in channel widths")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB ten times (HBM counter calibration)")
     args = ap.parse_args()
@@ -683,7 +688,8 @@ def main():
     if args.capillary:
         tstream = torch.cuda.Stream()
         torch.cuda.set_stream(tstream)
-        print(json.dumps({"capillary_intrusion": capillary_study(felbm, tstream.cuda_stream, args.sweeps32)}))
+        print(json.dumps({"capillary_intrusion": capillary_study(felbm, tstream.cuda_stream, args.sweeps32,
+                                                                 length_widths=args.capillary_length)}))
         return
     if args.mobility_study:
         tstream = torch.cuda.Stream()
