@@ -337,7 +337,7 @@ int enqueue_fields(felbm_ctx* c, bool collide, bool record, DiagRecord* rec_targ
     else
       TRY(launch(c, K_LAPC_OP, k_lapC_mu_op<real, false>, gN, N, op, (const double*)c->Cn, (const double*)c->bc, c->sp,
                  c->lapC, c->mu));
-    return launch(c, K_LAPMU_OP, k_lapmu_op<real>, gE, E, (const int*)c->tri, op, (const double*)c->mu, c->lapmu);
+    return launch(c, K_LAPMU_OP, k_lapmu_op, gE, E, (const int*)c->tri, op, (const double*)c->mu, c->lapmu);
   }
   TRY(launch(c, K_GRAD, k_elem_grad<real>, gE, E, (const int*)c->tri, (const double*)c->geo, (const double*)c->Cn,
              (const real*)c->pn, c->gC, (real*)c->gp));
@@ -778,7 +778,7 @@ int build_field_operators(felbm_ctx* c, const MeshPrep& m, const std::vector<dou
   }
   // element rows: weights of mu_1 - mu_0, mu_2 - mu_0 and of the three vertices across the edges
   std::vector<int32_t> eopp(3 * E);
-  std::vector<wreal> ew(5 * E);
+  std::vector<double> ew(5 * E);
   for (int64_t e = 0; e < E; ++e) {
     double wv[3] = {0, 0, 0}, wo[3] = {0, 0, 0};
     int32_t opp[3] = {m.tri[e], m.tri[e], m.tri[e]};
@@ -799,11 +799,11 @@ int build_field_operators(felbm_ctx* c, const MeshPrep& m, const std::vector<dou
         }
       }
     }
-    ew[e] = (wreal)wv[1];
-    ew[E + e] = (wreal)wv[2];
+    ew[e] = wv[1];
+    ew[E + e] = wv[2];
     for (int l = 0; l < 3; ++l) {
       eopp[l * E + e] = opp[l];
-      ew[(2 + l) * E + e] = (wreal)wo[l];
+      ew[(2 + l) * E + e] = wo[l];
     }
   }
   TRY(dalloc(c, &c->lop_ptr, sptr.size()));
@@ -813,7 +813,7 @@ int build_field_operators(felbm_ctx* c, const MeshPrep& m, const std::vector<dou
   TRY(dalloc(c, &c->wab, std::max<size_t>(wab.size(), 1)));
   TRY(dalloc(c, &c->wlen, std::max<size_t>(wlen.size(), 1)));
   TRY(dalloc(c, &c->eopp, eopp.size()));
-  TRY(dalloc_bytes(c, &c->ew, ew.size() * sizeof(wreal)));
+  TRY(dalloc_bytes(c, &c->ew, ew.size() * sizeof(double)));
   TRY(upload(c, c->lop_ptr, sptr));
   TRY(upload(c, c->lop_col, scol));
   HIP_OK(c, hipMemcpyAsync(c->lop_w, sval.data(), sval.size() * sizeof(wreal), hipMemcpyHostToDevice, c->stream));
@@ -823,13 +823,13 @@ int build_field_operators(felbm_ctx* c, const MeshPrep& m, const std::vector<dou
     TRY(upload(c, c->wlen, wlen));
   }
   TRY(upload(c, c->eopp, eopp));
-  HIP_OK(c, hipMemcpyAsync(c->ew, ew.data(), ew.size() * sizeof(wreal), hipMemcpyHostToDevice, c->stream));
+  HIP_OK(c, hipMemcpyAsync(c->ew, ew.data(), ew.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
   HIP_OK(c, hipStreamSynchronize(c->stream));  // host vectors are about to go out of scope
   // algorithmic bytes: true entries (column + weight), C_k, the wall pointer, mu written;
   // per element three vertex ids, three opposite ids, five weights, lap mu written
   const double ws = (double)sizeof(wreal);
   c->kstat[K_LAPC_OP].bytes = (double)true_nnz * (4 + ws) + (double)N * (8 + 4 + 8) + (double)wab.size() * (8 + 8);
-  c->kstat[K_LAPMU_OP].bytes = (double)E * (12 + 12 + 5 * ws + 8) + (double)N * 8;
+  c->kstat[K_LAPMU_OP].bytes = (double)E * (12 + 12 + 5 * 8 + 8) + (double)N * 8;
   return FELBM_OK;
 }
 

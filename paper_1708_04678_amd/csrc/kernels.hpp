@@ -280,8 +280,10 @@ __global__ void __launch_bounds__(BLOCK) k_lapC_mu(int N, int E, const int* __re
 // in mu at the element's vertices and at the three vertices across its edges:
 //   lap mu_T = w1 (mu_1 - mu_0) + w2 (mu_2 - mu_0) + sum_l w_opp,l (mu_opp,l - mu_0),
 // where an edge on a wall contributes nothing (eqn:bc1; its opposite slot
-// points at vertex 0 with weight 0).  Weights in the working precision
-// (wreal), arithmetic and values in FP64.
+// points at vertex 0 with weight 0).  Values and arithmetic in FP64; the
+// patch weights in the working precision (wreal), the element weights in
+// FP64 (the FP32 composition transport relies on sum_T A_T lap mu_T = 0 to
+// rounding, which FP32 weights would break by their rounding).
 // ----------------------------------------------------------------------------
 struct FieldOps {
   const int* lop_ptr;   // [Np/64 + 1] slice offsets
@@ -291,7 +293,8 @@ struct FieldOps {
   const int2* wab;      // [wall entries] edge end nodes
   const double* wlen;   // [wall entries] edge length / patch volume
   const int* eopp;      // [3][E] vertex across the edge opposite local vertex l (vertex 0 on a wall edge)
-  const void* ew;       // [5][E] wreal
+  const void* ew;       // [5][E] double in both precisions: A_T times these weights must cancel
+                        // across each interior edge to rounding, which conserves mass
 };
 
 template <typename wreal, bool WRITE_LAPC>
@@ -318,17 +321,15 @@ __global__ void __launch_bounds__(BLOCK) k_lapC_mu_op(int N, FieldOps op, const 
   mu[k] = 2.0 * P.beta * Ck * (Ck - 1.0) * (2.0 * Ck - 1.0) - P.kappa * acc;
 }
 
-template <typename wreal>
 __global__ void __launch_bounds__(BLOCK) k_lapmu_op(int E, const int* __restrict__ tri, FieldOps op,
                                                    const double* __restrict__ mu, double* __restrict__ lapmu) {
   const int e = xcd_block() * BLOCK + threadIdx.x;
   if (e >= E) return;
-  const wreal* __restrict__ w = static_cast<const wreal*>(op.ew);
+  const double* __restrict__ w = static_cast<const double*>(op.ew);
   const double m0 = mu[tri[e]];
   const double d1 = mu[tri[E + e]] - m0, d2 = mu[tri[2 * E + e]] - m0;
   const double o0 = mu[op.eopp[e]] - m0, o1 = mu[op.eopp[E + e]] - m0, o2 = mu[op.eopp[2 * E + e]] - m0;
-  lapmu[e] = (double)w[e] * d1 + (double)w[E + e] * d2 + (double)w[2 * E + e] * o0 + (double)w[3 * E + e] * o1 +
-             (double)w[4 * E + e] * o2;
+  lapmu[e] = w[e] * d1 + w[E + e] * d2 + w[2 * E + e] * o0 + w[3 * E + e] * o1 + w[4 * E + e] * o2;
 }
 
 // a4: element gradient of mu (P1) ...
