@@ -22,11 +22,10 @@ using namespace felbm3d;
 
 namespace {
 
-enum Kernel3 { K3_MOMENTS = 0, K3_REDUCE, K3_GRAD, K3_FFLUX, K3_LAPC, K3_GRADMU, K3_LAPMU, K3_RHS, K3_SWEEP_FIRST,
-               K3_SWEEP_MID, K3_SWEEP_LAST, K3_COUNT };
-const char* const kNames3[K3_COUNT] = {"moments_collide", "reduce_final", "elem_grad", "face_flux", "lapC_mu",
-                                       "elem_gradmu", "elem_lapmu", "rhs_gather", "sweep_first", "sweep_mid",
-                                       "sweep_last"};
+enum Kernel3 { K3_MOMENTS = 0, K3_REDUCE, K3_LAPC, K3_LAPMU, K3_RHS, K3_SWEEP_FIRST, K3_SWEEP_MID, K3_SWEEP_LAST,
+               K3_COUNT };
+const char* const kNames3[K3_COUNT] = {"moments_collide", "reduce_final", "lapC_mu_op", "lapmu_force_op",
+                                       "rhs_gather", "sweep_first", "sweep_mid", "sweep_last"};
 
 inline int grid_for(int64_t n) {
   int64_t b = (n + BLOCK - 1) / BLOCK;
@@ -56,6 +55,11 @@ struct Prep3 {
   // and the doubled symmetric xy, xz, yz), both in sliced ELL; dt factors applied at upload
   std::vector<int32_t> inc_ptr, inc_e, pair_ptr, pair_col;
   std::vector<double> inc_w, pair_v;  // [4][inc slots], [9][pair slots]
+  // field operators: patch Laplacian of C (sliced ELL over the 2-ring, weights / V_k,
+  // difference form) with the wall faces of each patch (CSR: [3][L] nodes, area / V_k),
+  // and the element Laplacian of mu ([4][E] vertices across the faces, [7][E] weights)
+  std::vector<int32_t> lop_ptr, lop_col, wl_ptr, wl_face, eopp;
+  std::vector<double> lop_w, wl_scale, ew;
 };
 
 struct FaceRec {
@@ -241,6 +245,120 @@ int prepare3(int64_t N, const double* xyz, int64_t E, const int32_t* tet, int64_
     for (int64_t w = 0; w < W; ++w)
       for (int v = 0; v < 3; ++v) m.wf_list[fill[wface[3 * w + v]]++] = (int32_t)w;
   }
+  // patch Laplacian of C as an operator (eqn:lapl_int_mp with averaged face gradients)
+  {
+    auto grad = [&](int64_t e, int v, int r) { return m.geo[(1 + 3 * v + r) * E + e]; };
+    std::vector<int32_t> pos(N, -1), cols;
+    std::vector<double> vals;
+    std::vector<int32_t> rptr_op(N + 1, 0), rcol_op;
+    std::vector<double> rval_op;
+    std::vector<std::array<int32_t, 3>> wl;
+    m.wl_ptr.assign(N + 1, 0);
+    for (int64_t k = 0; k < N; ++k) {
+      cols.clear();
+      vals.clear();
+      auto add = [&](int32_t j, double w) {
+        if (pos[j] < 0) {
+          pos[j] = (int32_t)cols.size();
+          cols.push_back(j);
+          vals.push_back(0.0);
+        }
+        vals[pos[j]] += w;
+      };
+      const double inv_vol = 1.0 / m.pvol[k];
+      for (int32_t q = m.n2e_ptr[k]; q < m.n2e_ptr[k + 1]; ++q) {
+        const int64_t e = m.n2e[q] >> 2;
+        const int l = m.n2e[q] & 3;
+        const double V = m.geo[e];
+        const int64_t nb = m.fnbr[l * E + e];
+        if (nb >= 0) {
+          for (int v = 0; v < 4; ++v)
+            add(m.tet[v * E + e],
+                -1.5 * V * (grad(e, l, 0) * grad(e, v, 0) + grad(e, l, 1) * grad(e, v, 1) + grad(e, l, 2) * grad(e, v, 2)));
+          for (int w = 0; w < 4; ++w)
+            add(m.tet[w * E + nb], -1.5 * V *
+                                        (grad(e, l, 0) * grad(nb, w, 0) + grad(e, l, 1) * grad(nb, w, 1) +
+                                         grad(e, l, 2) * grad(nb, w, 2)));
+        } else {  // wall face opposite k: area 3V |grad N_l|
+          const double gn = std::sqrt(grad(e, l, 0) * grad(e, l, 0) + grad(e, l, 1) * grad(e, l, 1) +
+                                      grad(e, l, 2) * grad(e, l, 2));
+          wl.push_back({m.tet[((l + 1) & 3) * E + e], m.tet[((l + 2) & 3) * E + e], m.tet[((l + 3) & 3) * E + e]});
+          m.wl_scale.push_back(3.0 * V * gn * inv_vol);
+        }
+      }
+      for (int32_t q = m.wf_ptr[k]; q < m.wf_ptr[k + 1]; ++q) {  // wall faces containing k
+        const int32_t f = m.wf_list[q];
+        wl.push_back({m.wface[f], m.wface[W + f], m.wface[2 * W + f]});
+        m.wl_scale.push_back(m.warea[f] * inv_vol);
+      }
+      m.wl_ptr[k + 1] = (int32_t)wl.size();
+      std::vector<int32_t> order(cols.size());
+      for (size_t q = 0; q < order.size(); ++q) order[q] = (int32_t)q;
+      std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cols[a] < cols[b]; });
+      for (int32_t q : order) {
+        if (cols[q] != (int32_t)k) {  // difference form: the node's own weight drops out
+          rcol_op.push_back(cols[q]);
+          rval_op.push_back(vals[q] * inv_vol);
+        }
+        pos[cols[q]] = -1;
+      }
+      rptr_op[k + 1] = (int32_t)rcol_op.size();
+    }
+    const int64_t L = (int64_t)wl.size();
+    m.wl_face.assign(3 * L, 0);
+    for (int64_t q = 0; q < L; ++q)
+      for (int c = 0; c < 3; ++c) m.wl_face[c * L + q] = wl[q][c];
+    const int64_t ns = ((N + 63) / 64 * 64) / 64;
+    m.lop_ptr.assign(ns + 1, 0);
+    for (int64_t sl = 0; sl < ns; ++sl) {
+      int64_t width = 0;
+      for (int64_t i = sl * 64; i < std::min<int64_t>(N, (sl + 1) * 64); ++i)
+        width = std::max<int64_t>(width, rptr_op[i + 1] - rptr_op[i]);
+      const size_t base = m.lop_col.size();
+      m.lop_col.resize(base + width * 64);
+      m.lop_w.resize(base + width * 64);
+      for (int64_t q = 0; q < width; ++q)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int64_t i = sl * 64 + lane;
+          const size_t idx = base + q * 64 + lane;
+          const bool real_entry = i < N && q < rptr_op[i + 1] - rptr_op[i];
+          m.lop_col[idx] = real_entry ? rcol_op[rptr_op[i] + q] : (int32_t)std::min<int64_t>(i, N - 1);
+          m.lop_w[idx] = real_entry ? rval_op[rptr_op[i] + q] : 0.0;
+        }
+      m.lop_ptr[sl + 1] = (int32_t)m.lop_col.size();
+    }
+    // element Laplacian of mu: weights of mu_1..3 - mu_0 and of the vertices across the faces
+    m.eopp.assign(4 * E, 0);
+    m.ew.assign(7 * E, 0.0);
+    for (int64_t e = 0; e < E; ++e) {
+      double a[4] = {0, 0, 0, 0}, b[4] = {0, 0, 0, 0};
+      int32_t opp[4] = {m.tet[e], m.tet[e], m.tet[e], m.tet[e]};
+      for (int l = 0; l < 4; ++l) {
+        const int64_t nb = m.fnbr[l * E + e];
+        if (nb < 0) continue;  // zero normal flux of grad mu through a wall (eqn:bc1)
+        for (int v = 0; v < 4; ++v)
+          a[v] -= 1.5 * (grad(e, l, 0) * grad(e, v, 0) + grad(e, l, 1) * grad(e, v, 1) + grad(e, l, 2) * grad(e, v, 2));
+        for (int w = 0; w < 4; ++w) {
+          const int32_t node = m.tet[w * E + nb];
+          const double wt =
+              -1.5 * (grad(e, l, 0) * grad(nb, w, 0) + grad(e, l, 1) * grad(nb, w, 1) + grad(e, l, 2) * grad(nb, w, 2));
+          int v = 0;
+          while (v < 4 && m.tet[v * E + e] != node) ++v;
+          if (v < 4) {
+            a[v] += wt;
+          } else {
+            opp[l] = node;
+            b[l] += wt;
+          }
+        }
+      }
+      for (int v = 1; v < 4; ++v) m.ew[(v - 1) * E + e] = a[v];
+      for (int l = 0; l < 4; ++l) {
+        m.eopp[l * E + e] = opp[l];
+        m.ew[(3 + l) * E + e] = b[l];
+      }
+    }
+  }
   // row-scaled consistent mass matrix a_ij = M11_ij / m_i (i != j), M11_ij = sum V/20
   std::vector<std::pair<int32_t, double>> row;
   std::vector<int32_t> rptr(N + 1, 0), rcol;
@@ -400,17 +518,20 @@ struct felbm3d_ctx {
   int64_t N = 0, Np = 0, E = 0, W = 0, nnz = 0, step = 0;
   size_t rs = 8;
   std::vector<double> cheb_w;
-  int32_t *tet = nullptr, *fnbr = nullptr, *n2e_ptr = nullptr, *n2e = nullptr, *wf_ptr = nullptr, *wf_list = nullptr;
-  int32_t *wface = nullptr, *sell_ptr = nullptr, *sell_col = nullptr, *first_bad = nullptr;
+  int32_t* tet = nullptr;
+  int32_t *sell_ptr = nullptr, *sell_col = nullptr, *first_bad = nullptr;
   int32_t *inc_ptr = nullptr, *inc_e = nullptr, *pair_ptr = nullptr, *pair_col = nullptr;
   int64_t inc_slots = 0, pair_slots = 0;
   void *inc_w = nullptr, *pair_v = nullptr, *fpar = nullptr;
-  double *geo = nullptr, *warea = nullptr, *bc = nullptr, *mass = nullptr, *pvol = nullptr, *eflux = nullptr;
+  double *bc = nullptr, *mass = nullptr;
+  void* grad = nullptr;  // [12][E] shape-function gradients, working precision
   uint8_t* is_wall = nullptr;
-  void *sell_val = nullptr, *pop = nullptr, *f = nullptr, *xa = nullptr, *xb = nullptr, *pn = nullptr, *un = nullptr,
-       *gp = nullptr;
-  double *Cn = nullptr, *mu = nullptr, *lapC = nullptr, *gC = nullptr, *gmu = nullptr, *lapmu = nullptr,
-         *partials = nullptr;
+  void *sell_val = nullptr, *pop = nullptr, *f = nullptr, *xa = nullptr, *xb = nullptr, *pn = nullptr, *un = nullptr;
+  int32_t *lop_ptr = nullptr, *lop_col = nullptr, *wl_ptr = nullptr, *wl_face = nullptr, *eopp = nullptr;
+  double* wl_scale = nullptr;
+  void *lop_w = nullptr, *ew = nullptr;
+  int64_t n_wall_entries = 0;
+  double *Cn = nullptr, *mu = nullptr, *lapC = nullptr, *lapmu = nullptr, *partials = nullptr;
   DiagRecord *hist = nullptr, *diag_now = nullptr;
   bool timing = false;
   int64_t launches[K3_COUNT] = {};
@@ -533,19 +654,12 @@ int enqueue_fields(felbm3d_ctx* c, bool collide, DiagRecord* rec) {
   if (rec)
     TRY3(launch3(c, K3_REDUCE, felbm::k_reduce_final<>, 1, RBLOCK, (const double*)c->partials, gN, N, (int64_t)c->step,
                  rec, c->first_bad));
-  TRY3(launch3(c, K3_GRAD, k3_elem_grad<real>, gE, BLOCK, E, (const int*)c->tet, (const double*)c->geo,
-               (const double*)c->Cn, (const real*)c->pn, c->gC, (real*)c->gp));
-  TRY3(launch3(c, K3_FFLUX, k3_face_flux, gE, BLOCK, E, (const int*)c->tet, (const int*)c->fnbr, (const double*)c->geo,
-               (const double*)c->gC, (const double*)c->Cn, (const double*)c->bc, c->eflux));
-  TRY3(launch3(c, K3_LAPC, k3_lapC_mu, gN, BLOCK, N, E, (const int*)c->n2e_ptr, (const int*)c->n2e,
-               (const double*)c->eflux, (const double*)c->pvol, (const double*)c->Cn, (const double*)c->bc,
-               (const int*)c->wf_ptr, (const int*)c->wf_list, (const int*)c->wface, (const double*)c->warea, W, c->sp,
-               c->lapC, c->mu));
-  TRY3(launch3(c, K3_GRADMU, k3_elem_gradmu, gE, BLOCK, E, (const int*)c->tet, (const double*)c->geo,
-               (const double*)c->mu, c->gmu));
-  return launch3(c, K3_LAPMU, k3_elem_lapmu_force<real>, gE, BLOCK, E, Np, (const int*)c->tet, (const int*)c->fnbr,
-                 (const double*)c->geo, (const double*)c->gmu, (const double*)c->gC, (const real*)c->gp,
-                 (const double*)c->Cn, (const double*)c->mu, (const real*)c->un, c->sp, c->lapmu, (real*)c->fpar);
+  TRY3(launch3(c, K3_LAPC, k3_lapC_mu_op<real>, gN, BLOCK, N, (const int*)c->lop_ptr, (const int*)c->lop_col,
+               (const real*)c->lop_w, (const int*)c->wl_ptr, (const int*)c->wl_face, (const double*)c->wl_scale,
+               (int)c->n_wall_entries, (const double*)c->Cn, (const double*)c->bc, c->sp, c->lapC, c->mu));
+  return launch3(c, K3_LAPMU, k3_lapmu_force_op<real, real>, gE, BLOCK, E, Np, (const int*)c->tet,
+                 (const int*)c->eopp, (const real*)c->ew, (const real*)c->grad, (const double*)c->Cn,
+                 (const double*)c->mu, (const real*)c->pn, (const real*)c->un, c->sp, c->lapmu, (real*)c->fpar);
 }
 
 template <typename real, int MODE>
@@ -680,19 +794,9 @@ int felbm3d_upload_mesh(felbm3d_ctx* c, int64_t n_nodes, const double* xyz, int6
   const int64_t N = m.N, Np = m.Np, E = m.E;
   const size_t rs = c->rs;
   TRY3(dalloc(c, &c->tet, 4 * E));
-  TRY3(dalloc(c, &c->fnbr, 4 * E));
-  TRY3(dalloc(c, &c->geo, 13 * E));
-  TRY3(dalloc(c, &c->n2e_ptr, N + 1));
-  TRY3(dalloc(c, &c->n2e, 4 * E));
-  TRY3(dalloc(c, &c->wf_ptr, N + 1));
-  TRY3(dalloc(c, &c->wf_list, m.wf_list.size()));
-  TRY3(dalloc(c, &c->wface, m.wface.size()));
-  TRY3(dalloc(c, &c->warea, m.warea.size()));
   TRY3(dalloc(c, &c->is_wall, N));
   TRY3(dalloc(c, &c->bc, N));
   TRY3(dalloc(c, &c->mass, N));
-  TRY3(dalloc(c, &c->pvol, N));
-  TRY3(dalloc(c, &c->eflux, 4 * E));
   TRY3(dalloc(c, &c->sell_ptr, m.sell_ptr.size()));
   TRY3(dalloc(c, &c->sell_col, m.sell_col.size()));
   TRY3(dalloc_bytes(c, &c->sell_val, m.sell_val.size() * rs));
@@ -705,37 +809,41 @@ int felbm3d_upload_mesh(felbm3d_ctx* c, int64_t n_nodes, const double* xyz, int6
   TRY3(dalloc_bytes(c, &c->inc_w, m.inc_w.size() * rs));
   TRY3(dalloc_bytes(c, &c->pair_v, m.pair_v.size() * rs));
   TRY3(dalloc_bytes(c, &c->fpar, 13 * E * rs));
+  c->n_wall_entries = (int64_t)m.wl_scale.size();
+  TRY3(dalloc(c, &c->lop_ptr, m.lop_ptr.size()));
+  TRY3(dalloc(c, &c->lop_col, m.lop_col.size()));
+  TRY3(dalloc_bytes(c, &c->lop_w, m.lop_w.size() * rs));
+  TRY3(dalloc(c, &c->wl_ptr, m.wl_ptr.size()));
+  TRY3(dalloc(c, &c->wl_face, m.wl_face.size()));
+  TRY3(dalloc(c, &c->wl_scale, m.wl_scale.size()));
+  TRY3(dalloc(c, &c->eopp, m.eopp.size()));
+  TRY3(dalloc_bytes(c, &c->ew, m.ew.size() * rs));
+  TRY3(dalloc_bytes(c, &c->grad, 12 * E * rs));
   TRY3(dalloc_bytes(c, &c->pop, 38 * Np * rs));
   TRY3(dalloc_bytes(c, &c->f, 38 * Np * rs));
   TRY3(dalloc_bytes(c, &c->xa, 38 * Np * rs));
   TRY3(dalloc_bytes(c, &c->xb, 38 * Np * rs));
   TRY3(dalloc_bytes(c, &c->pn, Np * rs));
   TRY3(dalloc_bytes(c, &c->un, 3 * Np * rs));
-  TRY3(dalloc_bytes(c, &c->gp, 3 * E * rs));
   TRY3(dalloc(c, &c->Cn, N));
   TRY3(dalloc(c, &c->mu, N));
   TRY3(dalloc(c, &c->lapC, N));
-  TRY3(dalloc(c, &c->gC, 3 * E));
-  TRY3(dalloc(c, &c->gmu, 3 * E));
   TRY3(dalloc(c, &c->lapmu, E));
   TRY3(dalloc(c, &c->partials, (size_t)NRED * grid_for(N)));
   TRY3(dalloc(c, &c->hist, 2));
   TRY3(dalloc(c, &c->diag_now, 1));
   TRY3(dalloc(c, &c->first_bad, 1));
   TRY3(upload(c, c->tet, m.tet));
-  TRY3(upload(c, c->fnbr, m.fnbr));
-  TRY3(upload(c, c->geo, m.geo));
-  TRY3(upload(c, c->n2e_ptr, m.n2e_ptr));
-  TRY3(upload(c, c->n2e, m.n2e));
-  TRY3(upload(c, c->wf_ptr, m.wf_ptr));
-  TRY3(upload(c, c->wf_list, m.wf_list));
-  TRY3(upload(c, c->wface, m.wface));
-  TRY3(upload(c, c->warea, m.warea));
   TRY3(upload(c, c->is_wall, m.is_wall));
   TRY3(upload(c, c->mass, m.mass));
-  TRY3(upload(c, c->pvol, m.pvol));
   TRY3(upload(c, c->sell_ptr, m.sell_ptr));
   TRY3(upload(c, c->sell_col, m.sell_col));
+  TRY3(upload(c, c->lop_ptr, m.lop_ptr));
+  TRY3(upload(c, c->lop_col, m.lop_col));
+  TRY3(upload(c, c->wl_ptr, m.wl_ptr));
+  TRY3(upload(c, c->wl_face, m.wl_face));
+  TRY3(upload(c, c->wl_scale, m.wl_scale));
+  TRY3(upload(c, c->eopp, m.eopp));
   TRY3(upload(c, c->inc_ptr, m.inc_ptr));
   TRY3(upload(c, c->inc_e, m.inc_e));
   TRY3(upload(c, c->pair_ptr, m.pair_ptr));
@@ -748,6 +856,10 @@ int felbm3d_upload_mesh(felbm3d_ctx* c, int64_t n_nodes, const double* xyz, int6
     TRY3(upload(c, (double*)c->sell_val, m.sell_val));
     TRY3(upload(c, (double*)c->inc_w, m.inc_w));
     TRY3(upload(c, (double*)c->pair_v, m.pair_v));
+    TRY3(upload(c, (double*)c->lop_w, m.lop_w));
+    TRY3(upload(c, (double*)c->ew, m.ew));
+    std::vector<double> g64(m.geo.begin() + E, m.geo.end());
+    TRY3(upload(c, (double*)c->grad, g64));
     HIP_OK3(c, hipStreamSynchronize(c->stream));
   } else {
     std::vector<float> v32(m.sell_val.begin(), m.sell_val.end()), w32(m.inc_w.begin(), m.inc_w.end()),
@@ -755,6 +867,11 @@ int felbm3d_upload_mesh(felbm3d_ctx* c, int64_t n_nodes, const double* xyz, int6
     TRY3(upload(c, (float*)c->sell_val, v32));
     TRY3(upload(c, (float*)c->inc_w, w32));
     TRY3(upload(c, (float*)c->pair_v, p32));
+    std::vector<float> l32(m.lop_w.begin(), m.lop_w.end()), e32(m.ew.begin(), m.ew.end());
+    TRY3(upload(c, (float*)c->lop_w, l32));
+    TRY3(upload(c, (float*)c->ew, e32));
+    std::vector<float> g32(m.geo.begin() + E, m.geo.end());
+    TRY3(upload(c, (float*)c->grad, g32));
     HIP_OK3(c, hipStreamSynchronize(c->stream));
   }
   std::vector<double> zeros(N, 0.0);
@@ -769,11 +886,8 @@ int felbm3d_upload_mesh(felbm3d_ctx* c, int64_t n_nodes, const double* xyz, int6
   const double Nd = (double)N, Ed = (double)E, s = (double)rs, nnz = (double)m.nnz;
   const double pops = 38.0 * Nd * s, mat = nnz * (4.0 + s) + (double)(Np / 64 + 1) * 4.0;
   c->bytes[K3_MOMENTS] = 2 * pops + Nd * (8 + 4 * s + 8);
-  c->bytes[K3_GRAD] = Ed * (16 + 96 + 24 + 3 * s) + Nd * (8 + s);
-  c->bytes[K3_FFLUX] = Ed * (16 + 104 + 24 + 32);
-  c->bytes[K3_LAPC] = Nd * (4 + 8 + 8 + 8 + 8 + 8 + 4) + 4 * Ed * (4 + 8);
-  c->bytes[K3_GRADMU] = Ed * (16 + 96 + 24) + Nd * 8;
-  c->bytes[K3_LAPMU] = Ed * (16 + 16 + 96 + 24 + 8 + 24 + 3 * s + 13 * s) + Nd * (8 + 8 + 3 * s);
+  c->bytes[K3_LAPC] = (double)m.lop_col.size() * (4 + s) + Nd * (8 + 8 + 8 + 4) + (double)m.wl_scale.size() * (12 + 8);
+  c->bytes[K3_LAPMU] = Ed * (16 + 16 + 7 * s + 12 * s + 8 + 13 * s) + Nd * (8 + 8 + s + 3 * s);
   c->bytes[K3_RHS] = 2 * pops + (double)m.inc_e.size() * (4 + 4 * s) + (double)m.pair_col.size() * (4 + 9 * s) +
                      Ed * 13 * s;
   c->bytes[K3_SWEEP_FIRST] = 2 * pops + mat;

@@ -7,12 +7,12 @@
 //
 // Data layout (device):
 //   populations  real [38][Np]   g_0..g_18 then h_0..h_18, Np = N rounded to 64
-//   elements     tet / fnbr int32 [4][E] (fnbr: element across the face
-//                opposite local vertex l, -1 on a wall); geometry double
-//                [13][E] = (V, grad N_0, grad N_1, grad N_2, grad N_3)
-//   node->element gather list (CSR, element*4 + local vertex)
-//   wall faces containing each node (CSR of face indices; face nodes [3][W],
-//   areas [W])
+//   elements     tet int32 [4][E]; shape-function gradients [12][E] in the
+//                working precision (grad N_0 .. grad N_3)
+//   field operators: the patch Laplacian of C over the 2-ring (sliced ELL,
+//                weights / patch volume) with the wall faces of each patch
+//                (CSR); the element Laplacian of mu ([4][E] vertices across
+//                the faces, [7][E] weights)
 //   mass matrix  diag(m)^-1 M11 off-diagonal part, sliced ELL (slice 64);
 //                its diagonal is M11_ii / m_i = 2/5 for P1 tetrahedra
 //   right-hand side: incident-element weights [4][slots] and patch moments
@@ -108,34 +108,6 @@ __global__ void __launch_bounds__(BLOCK) k3_moments(real* __restrict__ pop, int 
   felbm::block_reduce_store<NRED3>(red, 2, partials, gridDim.x, blk);
 }
 
-// a2: element gradients of C (FP64) and p
-template <typename real>
-__global__ void __launch_bounds__(BLOCK) k3_elem_grad(int E, const int* __restrict__ tet, const double* __restrict__ geo,
-                                                     const double* __restrict__ Cn, const real* __restrict__ pn,
-                                                     double* __restrict__ gC, real* __restrict__ gp) {
-  const int e = xcd_block() * BLOCK + threadIdx.x;
-  if (e >= E) return;
-  double c[3] = {0, 0, 0};
-  real q[3] = {0, 0, 0};
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int n = tet[v * E + e];
-    const double Cv = Cn[n];
-    const real pv = pn[n];
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      const double g = geo[(1 + 3 * v + r) * E + e];
-      c[r] += Cv * g;
-      q[r] += pv * (real)g;
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    gC[r * E + e] = c[r];
-    gp[r * E + e] = q[r];
-  }
-}
-
 // Outward flux through a wall face from eq. bc2 (n into the fluid):
 // -int (phi_c/kappa)(C - C^2) dA with r = phi_c/kappa and C linear on the
 // triangle, exact: int lambda_i lambda_j = A (1 + delta_ij)/12 and
@@ -157,129 +129,107 @@ __device__ __forceinline__ double wall_flux3(const double (&C)[3], const double 
   return -area * (lin * (1.0 / 12.0) - cub * (1.0 / 60.0));
 }
 
-// a3: flux through each face of each element as seen from the opposite vertex
-// (|f| n_out = -3 V grad N_l; averaged gradients across interior faces, the
-// wetting flux on wall faces), then the node sum over the patch plus the wall
-// faces that contain the node, over the patch volume; mu (eqn:mp_mu).
-__global__ void __launch_bounds__(BLOCK) k3_face_flux(int E, const int* __restrict__ tet, const int* __restrict__ fnbr,
-                                                     const double* __restrict__ geo, const double* __restrict__ gC,
-                                                     const double* __restrict__ Cn, const double* __restrict__ bc,
-                                                     double* __restrict__ F) {
-  const int e = xcd_block() * BLOCK + threadIdx.x;
-  if (e >= E) return;
-  const double V = geo[e];
-  const double tx = gC[e], ty = gC[E + e], tz = gC[2 * E + e];
-#pragma unroll
-  for (int l = 0; l < 4; ++l) {
-    const double gx = geo[(1 + 3 * l) * E + e], gy = geo[(2 + 3 * l) * E + e], gz = geo[(3 + 3 * l) * E + e];
-    const int nb = fnbr[l * E + e];
-    double fl;
-    if (nb >= 0) {
-      fl = -1.5 * V * (gx * (tx + gC[nb]) + gy * (ty + gC[E + nb]) + gz * (tz + gC[2 * E + nb]));
-    } else {
-      double Cf[3], rf[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const int n = tet[((l + 1 + k) & 3) * E + e];
-        Cf[k] = Cn[n];
-        rf[k] = bc[n];
-      }
-      fl = wall_flux3(Cf, rf, 3.0 * V * sqrt(gx * gx + gy * gy + gz * gz));
-    }
-    F[l * E + e] = fl;
+// a3 as a precomputed operator.  The patch Laplacian of C (eqn:lapl_int_mp:
+// averaged element gradients across the interior outer faces of the patch,
+// the wetting flux of eq. bc2 over its wall faces) is linear in the nodal C of
+// the patch and of the vertices across its outer faces, apart from the wall
+// terms; with the weights divided by the patch volume V_k on the host,
+//   lap C_k = sum_j w_kj (C_j - C_k) + sum_{wall faces f of the patch} F_BC(f) / V_k
+// (difference form: sum_j w_kj = 0, so a constant field gives exactly 0).
+// Rows in sliced ELL (slice 64, entry q of lane l at base + 64 q + l, padding
+// pointing at the node itself with weight 0); the wall faces of each patch (those
+// opposite the node and those containing it) in a CSR list of node triples
+// [3][L] and area / V_k.  Values and arithmetic in FP64, weights in wreal.
+template <typename wreal>
+__global__ void __launch_bounds__(BLOCK) k3_lapC_mu_op(int N, const int* __restrict__ lop_ptr,
+                                                      const int* __restrict__ lop_col, const wreal* __restrict__ lop_w,
+                                                      const int* __restrict__ wl_ptr, const int* __restrict__ wl_face,
+                                                      const double* __restrict__ wl_scale, int L,
+                                                      const double* __restrict__ Cn, const double* __restrict__ bc,
+                                                      StepParams P, double* __restrict__ lapC, double* __restrict__ mu) {
+  const int i = xcd_block() * BLOCK + threadIdx.x;
+  if (i >= N) return;
+  const int slice = i >> 6, lane = i & 63;
+  const int base = lop_ptr[slice], width = (lop_ptr[slice + 1] - base) >> 6;
+  const double Ci = Cn[i];
+  double acc = 0.0;
+  for (int q = 0; q < width; ++q) {
+    const int idx = base + (q << 6) + lane;
+    acc += (double)lop_w[idx] * (Cn[lop_col[idx]] - Ci);
   }
-}
-
-__global__ void __launch_bounds__(BLOCK) k3_lapC_mu(int N, int E, const int* __restrict__ n2e_ptr,
-                                                   const int* __restrict__ n2e, const double* __restrict__ F,
-                                                   const double* __restrict__ pvol, const double* __restrict__ Cn,
-                                                   const double* __restrict__ bc, const int* __restrict__ wf_ptr,
-                                                   const int* __restrict__ wf_list, const int* __restrict__ wface,
-                                                   const double* __restrict__ warea, int W, StepParams P,
-                                                   double* __restrict__ lapC, double* __restrict__ mu) {
-  const int k = xcd_block() * BLOCK + threadIdx.x;
-  if (k >= N) return;
-  double flux = 0.0;
-  for (int q = n2e_ptr[k]; q < n2e_ptr[k + 1]; ++q) {
-    const int packed = n2e[q];
-    flux += F[(packed & 3) * E + (packed >> 2)];
-  }
-  for (int q = wf_ptr[k]; q < wf_ptr[k + 1]; ++q) {
-    const int f = wf_list[q];
+  for (int q = wl_ptr[i]; q < wl_ptr[i + 1]; ++q) {
     double Cf[3], rf[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const int n = wface[c * W + f];
+      const int n = wl_face[c * L + q];
       Cf[c] = Cn[n];
       rf[c] = bc[n];
     }
-    flux += wall_flux3(Cf, rf, warea[f]);
+    acc += wall_flux3(Cf, rf, wl_scale[q]);
   }
-  const double Ck = Cn[k], L = flux / pvol[k];
-  lapC[k] = L;
-  mu[k] = 2.0 * P.beta * Ck * (Ck - 1.0) * (2.0 * Ck - 1.0) - P.kappa * L;
+  lapC[i] = acc;
+  mu[i] = 2.0 * P.beta * Ci * (Ci - 1.0) * (2.0 * Ci - 1.0) - P.kappa * acc;
 }
 
-// a4: element gradient of mu and its element Laplacian, (1/V) sum over the
-// faces of |f| n . (mean of the two adjacent gradients), zero on wall faces:
-// -3/2 sum_l grad N_l . (g_T + g_T'(l))
-__global__ void __launch_bounds__(BLOCK) k3_elem_gradmu(int E, const int* __restrict__ tet,
-                                                       const double* __restrict__ geo, const double* __restrict__ mu,
-                                                       double* __restrict__ gmu) {
-  const int e = xcd_block() * BLOCK + threadIdx.x;
-  if (e >= E) return;
-  double c[3] = {0, 0, 0};
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const double m = mu[tet[v * E + e]];
-#pragma unroll
-    for (int r = 0; r < 3; ++r) c[r] += m * geo[(1 + 3 * v + r) * E + e];
-  }
-#pragma unroll
-  for (int r = 0; r < 3; ++r) gmu[r * E + e] = c[r];
-}
-
-// a4 + a5: element Laplacian of mu (FP64), fused with the element's force
+// a4 + a2 + a5: the element Laplacian of mu (Sec. II.D: -3/2 sum_l grad N_l .
+// (grad mu_T + grad mu_T'(l)) over the interior faces, zero on wall faces) as
+// a precomputed operator on mu at the element's vertices and at the four
+// vertices across its faces,
+//   lap mu_T = sum_{v=1..3} a_v (mu_v - mu_0) + sum_l b_l (mu_opp(l) - mu_0)
+// (a wall face contributes nothing: its opposite slot points at vertex 0 with
+// weight 0); then the element gradients of C and p and the element's force
 // parameters at the barycentric values (eq:G, eq:H): for the g set
 // A = (rho_l - rho_v) c_s^2 grad C_T and B = mu_bar grad C_T, for the h set
 // X = grad C_T - C_bar / (rho_bar c_s^2) (grad p_T - mu_bar grad C_T) and
 // d = M lap mu_T; both with u_bar.  Stored [13][E] as (u_bar, A, B, X, d).
-template <typename real>
-__global__ void __launch_bounds__(BLOCK) k3_elem_lapmu_force(int E, int Np, const int* __restrict__ tet,
-                                                            const int* __restrict__ fnbr,
-                                                            const double* __restrict__ geo,
-                                                            const double* __restrict__ gmu,
-                                                            const double* __restrict__ gC, const real* __restrict__ gp,
-                                                            const double* __restrict__ Cn, const double* __restrict__ mu,
-                                                            const real* __restrict__ un, StepParams P,
-                                                            double* __restrict__ lapmu, real* __restrict__ fpar) {
+// The shape-function gradients are read in the working precision ([12][E]):
+// every force parameter is rounded to it.
+template <typename real, typename wreal>
+__global__ void __launch_bounds__(BLOCK) k3_lapmu_force_op(int E, int Np, const int* __restrict__ tet,
+                                                          const int* __restrict__ eopp, const wreal* __restrict__ ew,
+                                                          const real* __restrict__ grad,
+                                                          const double* __restrict__ Cn, const double* __restrict__ mu,
+                                                          const real* __restrict__ pn, const real* __restrict__ un,
+                                                          StepParams P, double* __restrict__ lapmu,
+                                                          real* __restrict__ fpar) {
   const int e = xcd_block() * BLOCK + threadIdx.x;
   if (e >= E) return;
-  const double tx = gmu[e], ty = gmu[E + e], tz = gmu[2 * E + e];
-  double acc = 0.0;
-#pragma unroll
-  for (int l = 0; l < 4; ++l) {
-    const int nb = fnbr[l * E + e];
-    if (nb >= 0)
-      acc += geo[(1 + 3 * l) * E + e] * (tx + gmu[nb]) + geo[(2 + 3 * l) * E + e] * (ty + gmu[E + nb]) +
-             geo[(3 + 3 * l) * E + e] * (tz + gmu[2 * E + nb]);
-  }
-  const double lm = -1.5 * acc;
-  lapmu[e] = lm;
+  int v[4];
+  double Cv[4], mv[4];
+  real pv[4];
   double Cb = 0.0, mub = 0.0;
   real ubx = 0, uby = 0, ubz = 0;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const int v = tet[t * E + e];
-    Cb += Cn[v];
-    mub += mu[v];
-    ubx += un[v];
-    uby += un[Np + v];
-    ubz += un[2 * Np + v];
+    v[t] = tet[t * E + e];
+    Cv[t] = Cn[v[t]];
+    mv[t] = mu[v[t]];
+    pv[t] = pn[v[t]];
+    Cb += Cv[t];
+    mub += mv[t];
+    ubx += un[v[t]];
+    uby += un[Np + v[t]];
+    ubz += un[2 * Np + v[t]];
+  }
+  double lm = (double)ew[e] * (mv[1] - mv[0]) + (double)ew[E + e] * (mv[2] - mv[0]) +
+              (double)ew[2 * E + e] * (mv[3] - mv[0]);
+#pragma unroll
+  for (int l = 0; l < 4; ++l) lm += (double)ew[(3 + l) * E + e] * (mu[eopp[l * E + e]] - mv[0]);
+  lapmu[e] = lm;
+  double gCx = 0.0, gCy = 0.0, gCz = 0.0;
+  real gpx = 0, gpy = 0, gpz = 0;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const real gx = grad[(3 * t) * E + e], gy = grad[(3 * t + 1) * E + e], gz = grad[(3 * t + 2) * E + e];
+    gCx += Cv[t] * (double)gx;
+    gCy += Cv[t] * (double)gy;
+    gCz += Cv[t] * (double)gz;
+    gpx += pv[t] * gx;
+    gpy += pv[t] * gy;
+    gpz += pv[t] * gz;
   }
   Cb *= 0.25;
   mub *= 0.25;
-  const double gCx = gC[e], gCy = gC[E + e], gCz = gC[2 * E + e];
   const real drho_cs2 = (real)(CS2 * (P.rho_l - P.rho_v));
   const real rhob = (real)(Cb * P.rho_l + (1.0 - Cb) * P.rho_v);
   const real bx = (real)(mub * gCx), by = (real)(mub * gCy), bz = (real)(mub * gCz);
@@ -294,9 +244,9 @@ __global__ void __launch_bounds__(BLOCK) k3_elem_lapmu_force(int E, int Np, cons
   o[6 * E] = bx;
   o[7 * E] = by;
   o[8 * E] = bz;
-  o[9 * E] = (real)gCx - coef * (gp[e] - bx);
-  o[10 * E] = (real)gCy - coef * (gp[E + e] - by);
-  o[11 * E] = (real)gCz - coef * (gp[2 * E + e] - bz);
+  o[9 * E] = (real)gCx - coef * (gpx - bx);
+  o[10 * E] = (real)gCy - coef * (gpy - by);
+  o[11 * E] = (real)gCz - coef * (gpz - bz);
   o[12 * E] = (real)(P.mobility * lm);
 }
 
