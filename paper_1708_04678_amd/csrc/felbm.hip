@@ -145,7 +145,7 @@ struct felbm_ctx {
   bool use_rhs_lds = false;
   int32_t* rhs_off = nullptr;
   int2* rhs_ent = nullptr;
-  double* gaos = nullptr;  // element geometry records [E][8]
+  double* gaos = nullptr;  // element geometry records [E][4]
   // adjoint: element reverse adjacency, caller<->internal maps, reverse buffers, checkpoints
   int32_t *erev = nullptr, *d_node_perm = nullptr;
   void *lam = nullptr, *lhat = nullptr;
@@ -875,9 +875,11 @@ int build_rhs_tiles(felbm_ctx* c, const MeshPrep& m, const std::vector<int32_t>&
     }
     off[t + 1] = (int32_t)ent.size();
   }
-  std::vector<double> gaos(8 * (size_t)E, 0.0);
+  // element record {dN1/dx, dN1/dy, dN2/dx, dN2/dy}: grad N0 = -(grad N1 + grad N2)
+  // and A = 1 / (2 det[grad N1; grad N2]) follow in the kernel
+  std::vector<double> gaos(4 * (size_t)E, 0.0);
   for (int64_t e = 0; e < E; ++e)
-    for (int q = 0; q < 7; ++q) gaos[8 * e + q] = m.geo[q * E + e];
+    for (int q = 0; q < 4; ++q) gaos[4 * e + q] = m.geo[(3 + q) * E + e];
   TRY(dalloc(c, &c->rhs_off, off.size()));
   TRY(dalloc(c, &c->rhs_ent, ent.size()));
   TRY(dalloc(c, &c->gaos, gaos.size()));
@@ -891,7 +893,7 @@ int build_rhs_tiles(felbm_ctx* c, const MeshPrep& m, const std::vector<int32_t>&
   const double Nd = (double)N, Ed = (double)E;
   const double s = (double)c->rs, cons = c->prm.precision == FELBM_FP32 ? 8.0 : 0.0;
   c->kstat[K_RHS].bytes = 2 * 18 * Nd * s + Nd * (8 + 8 + 3 * s + 8 + cons) + (double)true_entries * 8 +
-                          Ed * (56 + 8) + (double)halo.size() * 4;
+                          Ed * (32 + 8) + (double)halo.size() * 4;
   return FELBM_OK;
 }
 

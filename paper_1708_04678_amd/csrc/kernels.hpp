@@ -828,7 +828,7 @@ constexpr unsigned rhs_lds_bytes() {
 struct RhsTile {
   const int* ent_off;   // [ntiles+1]
   const int2* ent;      // [entries]
-  const double* gaos;   // [E][8] FP64 element geometry {A, dN0/dx, dN0/dy, dN1/dx, dN1/dy, dN2/dx, dN2/dy, 0}
+  const double* gaos;   // [E][4] FP64 element geometry {dN1/dx, dN1/dy, dN2/dx, dN2/dy}
   const double* lapmu;  // [E]
 };
 
@@ -913,12 +913,13 @@ __global__ void __launch_bounds__(BLOCK) k_rhs_lds(int N, int Np, int E, TileArg
     // slots of the two other vertices, in the order (l + 1, l + 2) mod 3
     const int sa = l == 0 ? s1 : (l == 1 ? s2 : s0);
     const int sb = l == 0 ? s2 : (l == 1 ? s0 : s1);
-    // the element's geometry as one 64-byte record (a straddling element costs
-    // one cache line instead of seven)
-    const double2* g2 = reinterpret_cast<const double2*>(rt.gaos) + 4 * (size_t)e;
-    const double2 ga = g2[0], gb = g2[1], gc = g2[2], gd = g2[3];
-    const double Ad = ga.x;
-    const double gxd[3] = {ga.y, gb.y, gc.y}, gyd[3] = {gb.x, gc.x, gd.x};
+    // the element's geometry as one 32-byte record {grad N1, grad N2}; grad N0 =
+    // -(grad N1 + grad N2) and A = 1 / (2 det[grad N1; grad N2]) are recomputed
+    // (the same values at all three vertices of the element)
+    const double2* g2 = reinterpret_cast<const double2*>(rt.gaos) + 2 * (size_t)e;
+    const double2 ga = g2[0], gb = g2[1];
+    const double Ad = 0.5 / (ga.x * gb.y - ga.y * gb.x);
+    const double gxd[3] = {-(ga.x + gb.x), ga.x, gb.x}, gyd[3] = {-(ga.y + gb.y), ga.y, gb.y};
     real gxf[3], gyf[3];
 #pragma unroll
     for (int v = 0; v < 3; ++v) {
