@@ -20,9 +20,11 @@
  * caller's node / tetrahedron order, all validation on the host before any
  * device work, deterministic results (no atomics).  Global-gather kernels on
  * every mesh.  felbm_params is shared with felbm.h: precision FELBM_FP64 or
- * FELBM_FP32 (plain FP32 populations and arithmetic, FP64 chemical-potential
- * chain and reductions, without the FP64 composition transport of the 2-D
- * library), solver_sweeps, lambda_min / lambda_max (0/0 selects [1/5, 1]);
+ * FELBM_FP32 (FP32 populations and arithmetic; FP64 chemical-potential chain,
+ * reductions and composition: C = sum_a h_a + r with a per-node FP64
+ * remainder r, whose increment is the FP64 zeroth moment of the h right-hand
+ * side solved by the same sweeps with exactly mass-preserving column sums, as
+ * in felbm.h), solver_sweeps, lambda_min / lambda_max (0/0 selects [1/5, 1]);
  * kernels and force_scheme must be 0.
  */
 #ifndef FELBM3D_H

@@ -60,6 +60,7 @@ struct Prep3 {
   // and the element Laplacian of mu ([4][E] vertices across the faces, [7][E] weights)
   std::vector<int32_t> lop_ptr, lop_col, wl_ptr, wl_face, eopp;
   std::vector<double> lop_w, wl_scale, ew;
+  std::vector<double> dlt;  // diagonal of the FP64 composition sweeps (FP32 form)
 };
 
 struct FaceRec {
@@ -389,6 +390,14 @@ int prepare3(int64_t N, const double* xyz, int64_t E, const int32_t* tet, int64_
     rptr[i + 1] = (int32_t)rcol.size();
   }
   m.nnz = (int64_t)rcol.size();
+  // diagonal of the FP64 composition sweeps: with the float-rounded a_ij, sum_i m_i (A x)_i = sum_j m_j x_j
+  {
+    std::vector<double> colsum(N, 0.0);
+    for (int64_t i = 0; i < N; ++i)
+      for (int32_t q = rptr[i]; q < rptr[i + 1]; ++q) colsum[rcol[q]] += m.mass[i] * (double)(float)rval[q];
+    m.dlt.resize(N);
+    for (int64_t j = 0; j < N; ++j) m.dlt[j] = 1.0 - colsum[j] / m.mass[j];
+  }
   const int64_t nslices = m.Np / 64;
   m.sell_ptr.assign(nslices + 1, 0);
   for (int64_t s = 0; s < nslices; ++s) {
@@ -422,7 +431,7 @@ int prepare3(int64_t N, const double* xyz, int64_t E, const int32_t* tet, int64_
         for (int32_t q = m.n2e_ptr[i]; q < m.n2e_ptr[i + 1]; ++q) {
           const int64_t e = m.n2e[q] >> 2, l = m.n2e[q] & 3;
           const size_t idx = base + (size_t)(q - m.n2e_ptr[i]) * 64 + (size_t)(i - s * 64);
-          ie[idx] = (int32_t)e;
+          ie[idx] = (int32_t)(4 * e + l);
           iw[0][idx] = m.geo[e] / m.mass[i];
           for (int r = 0; r < 3; ++r) iw[1 + r][idx] = m.geo[e] * m.geo[(1 + 3 * l + r) * E + e] / m.mass[i];
         }
@@ -524,12 +533,16 @@ struct felbm3d_ctx {
   int64_t inc_slots = 0, pair_slots = 0;
   void *inc_w = nullptr, *pair_v = nullptr, *fpar = nullptr;
   double *bc = nullptr, *mass = nullptr;
+  // FP32 composition transport (null in FP64)
+  double *rC = nullptr, *jp = nullptr, *em = nullptr, *geo64 = nullptr, *fC = nullptr, *xCa = nullptr, *xCb = nullptr,
+         *dlt = nullptr;
   void* grad = nullptr;  // [12][E] shape-function gradients, working precision
   uint8_t* is_wall = nullptr;
   void *sell_val = nullptr, *pop = nullptr, *f = nullptr, *xa = nullptr, *xb = nullptr, *pn = nullptr, *un = nullptr;
   int32_t *lop_ptr = nullptr, *lop_col = nullptr, *wl_ptr = nullptr, *wl_face = nullptr, *eopp = nullptr;
   double* wl_scale = nullptr;
-  void *lop_w = nullptr, *ew = nullptr;
+  void* lop_w = nullptr;
+  double* ew = nullptr;
   int64_t n_wall_entries = 0;
   double *Cn = nullptr, *mu = nullptr, *lapC = nullptr, *lapmu = nullptr, *partials = nullptr;
   DiagRecord *hist = nullptr, *diag_now = nullptr;
@@ -640,33 +653,41 @@ std::vector<double> chebyshev_steps(int K, double lo, double hi) {
   return out;
 }
 
+// FP32 composition transport arguments (all null in FP64); em only in a step
+Cons3 cons3(felbm3d_ctx* c, bool step, double w = 0.0, const double* xCin = nullptr, double* xCout = nullptr) {
+  if (c->prm.precision != FELBM_FP32) return Cons3{};
+  return Cons3{c->rC, c->jp, step ? c->em : nullptr, c->geo64, c->fC, xCin, xCout, c->dlt, c->Cn, w};
+}
+
 template <typename real>
 int enqueue_fields(felbm3d_ctx* c, bool collide, DiagRecord* rec) {
   const int gN = grid_for(c->N), gE = grid_for(c->E);
-  const int N = (int)c->N, Np = (int)c->Np, E = (int)c->E, W = (int)c->W;
+  const int N = (int)c->N, Np = (int)c->Np, E = (int)c->E;
   real* pop = (real*)c->pop;
+  const Cons3 cs = cons3(c, collide);
   if (collide)
     TRY3(launch3(c, K3_MOMENTS, k3_moments<real, true>, gN, BLOCK, pop, N, Np, c->sp, c->Cn, (real*)c->pn, (real*)c->un,
-                 (const double*)c->mass, c->partials));
+                 (const double*)c->mass, c->partials, cs));
   else
     TRY3(launch3(c, K3_MOMENTS, k3_moments<real, false>, gN, BLOCK, pop, N, Np, c->sp, c->Cn, (real*)c->pn,
-                 (real*)c->un, (const double*)c->mass, c->partials));
+                 (real*)c->un, (const double*)c->mass, c->partials, cs));
   if (rec)
     TRY3(launch3(c, K3_REDUCE, felbm::k_reduce_final<>, 1, RBLOCK, (const double*)c->partials, gN, N, (int64_t)c->step,
                  rec, c->first_bad));
   TRY3(launch3(c, K3_LAPC, k3_lapC_mu_op<real>, gN, BLOCK, N, (const int*)c->lop_ptr, (const int*)c->lop_col,
                (const real*)c->lop_w, (const int*)c->wl_ptr, (const int*)c->wl_face, (const double*)c->wl_scale,
                (int)c->n_wall_entries, (const double*)c->Cn, (const double*)c->bc, c->sp, c->lapC, c->mu));
-  return launch3(c, K3_LAPMU, k3_lapmu_force_op<real, real>, gE, BLOCK, E, Np, (const int*)c->tet,
-                 (const int*)c->eopp, (const real*)c->ew, (const real*)c->grad, (const double*)c->Cn,
-                 (const double*)c->mu, (const real*)c->pn, (const real*)c->un, c->sp, c->lapmu, (real*)c->fpar);
+  return launch3(c, K3_LAPMU, k3_lapmu_force_op<real, double>, gE, BLOCK, E, Np, (const int*)c->tet,
+                 (const int*)c->eopp, (const double*)c->ew, (const real*)c->grad, (const double*)c->Cn,
+                 (const double*)c->mu, (const real*)c->pn, (const real*)c->un, c->sp, c->lapmu, (real*)c->fpar, cs);
 }
 
 template <typename real, int MODE>
-int sweep3(felbm3d_ctx* c, int kid, const real* xin, real* xout, real w) {
+int sweep3(felbm3d_ctx* c, int kid, const real* xin, real* xout, int j, const double* xCin, double* xCout) {
+  const double w = MODE == 4 ? 0.0 : c->cheb_w[j];
   return launch3(c, kid, k3_sweep<real, MODE>, grid_sets_for(c->N), BLOCK, (int)c->N, (int)c->Np, (const int*)c->sell_ptr,
                  (const int*)c->sell_col, (const real*)c->sell_val, (const real*)c->f, xin, xout, (real*)c->pop,
-                 (const uint8_t*)c->is_wall, w);
+                 (const uint8_t*)c->is_wall, (real)w, cons3(c, true, w, xCin, xCout));
 }
 
 template <typename real>
@@ -675,21 +696,24 @@ int enqueue_step(felbm3d_ctx* c) {
   TRY3(launch3(c, K3_RHS, k3_rhs<real>, grid_sets_for(c->N), BLOCK, (int)c->N, (int)c->Np, (int)c->E,
                (const int*)c->inc_ptr, (const int*)c->inc_e, (const real*)c->inc_w, (int)c->inc_slots,
                (const real*)c->fpar, (const int*)c->pair_ptr, (const int*)c->pair_col, (const real*)c->pair_v,
-               (int)c->pair_slots, (const real*)c->pop, (real*)c->f));
+               (int)c->pair_slots, (const real*)c->pop, (real*)c->f, (const double*)c->mass, cons3(c, true)));
   const int K = c->prm.solver_sweeps;
   real *xa = (real*)c->xa, *xb = (real*)c->xb;
+  double *ca = c->xCa, *cb = c->xCb;
   if (K == 0) {
-    TRY3((sweep3<real, 4>(c, K3_SWEEP_LAST, nullptr, nullptr, (real)0)));
+    TRY3((sweep3<real, 4>(c, K3_SWEEP_LAST, nullptr, nullptr, 0, nullptr, nullptr)));
   } else if (K == 1) {
-    TRY3((sweep3<real, 3>(c, K3_SWEEP_LAST, nullptr, nullptr, (real)c->cheb_w[0])));
+    TRY3((sweep3<real, 3>(c, K3_SWEEP_LAST, nullptr, nullptr, 0, nullptr, nullptr)));
   } else {
-    TRY3((sweep3<real, 0>(c, K3_SWEEP_FIRST, nullptr, xa, (real)c->cheb_w[0])));
+    TRY3((sweep3<real, 0>(c, K3_SWEEP_FIRST, nullptr, xa, 0, nullptr, ca)));
     real *xin = xa, *xout = xb;
+    double *cin = ca, *cout = cb;
     for (int j = 1; j < K - 1; ++j) {
-      TRY3((sweep3<real, 1>(c, K3_SWEEP_MID, xin, xout, (real)c->cheb_w[j])));
+      TRY3((sweep3<real, 1>(c, K3_SWEEP_MID, xin, xout, j, cin, cout)));
       std::swap(xin, xout);
+      std::swap(cin, cout);
     }
-    TRY3((sweep3<real, 2>(c, K3_SWEEP_LAST, xin, nullptr, (real)c->cheb_w[K - 1])));
+    TRY3((sweep3<real, 2>(c, K3_SWEEP_LAST, xin, nullptr, K - 1, cin, nullptr)));
   }
   c->step += 1;
   return FELBM_OK;
@@ -817,7 +841,17 @@ int felbm3d_upload_mesh(felbm3d_ctx* c, int64_t n_nodes, const double* xyz, int6
   TRY3(dalloc(c, &c->wl_face, m.wl_face.size()));
   TRY3(dalloc(c, &c->wl_scale, m.wl_scale.size()));
   TRY3(dalloc(c, &c->eopp, m.eopp.size()));
-  TRY3(dalloc_bytes(c, &c->ew, m.ew.size() * rs));
+  TRY3(dalloc(c, &c->ew, m.ew.size()));  // double in both precisions: conserves mass in the FP32 form
+  if (c->prm.precision == FELBM_FP32) {
+    TRY3(dalloc(c, &c->rC, N));
+    TRY3(dalloc(c, &c->jp, 9 * Np));
+    TRY3(dalloc(c, &c->em, 4 * E));
+    TRY3(dalloc(c, &c->geo64, 13 * E));
+    TRY3(dalloc(c, &c->fC, Np));
+    TRY3(dalloc(c, &c->xCa, Np));
+    TRY3(dalloc(c, &c->xCb, Np));
+    TRY3(dalloc(c, &c->dlt, N));
+  }
   TRY3(dalloc_bytes(c, &c->grad, 12 * E * rs));
   TRY3(dalloc_bytes(c, &c->pop, 38 * Np * rs));
   TRY3(dalloc_bytes(c, &c->f, 38 * Np * rs));
@@ -844,6 +878,7 @@ int felbm3d_upload_mesh(felbm3d_ctx* c, int64_t n_nodes, const double* xyz, int6
   TRY3(upload(c, c->wl_face, m.wl_face));
   TRY3(upload(c, c->wl_scale, m.wl_scale));
   TRY3(upload(c, c->eopp, m.eopp));
+  TRY3(upload(c, c->ew, m.ew));
   TRY3(upload(c, c->inc_ptr, m.inc_ptr));
   TRY3(upload(c, c->inc_e, m.inc_e));
   TRY3(upload(c, c->pair_ptr, m.pair_ptr));
@@ -857,7 +892,6 @@ int felbm3d_upload_mesh(felbm3d_ctx* c, int64_t n_nodes, const double* xyz, int6
     TRY3(upload(c, (double*)c->inc_w, m.inc_w));
     TRY3(upload(c, (double*)c->pair_v, m.pair_v));
     TRY3(upload(c, (double*)c->lop_w, m.lop_w));
-    TRY3(upload(c, (double*)c->ew, m.ew));
     std::vector<double> g64(m.geo.begin() + E, m.geo.end());
     TRY3(upload(c, (double*)c->grad, g64));
     HIP_OK3(c, hipStreamSynchronize(c->stream));
@@ -867,9 +901,10 @@ int felbm3d_upload_mesh(felbm3d_ctx* c, int64_t n_nodes, const double* xyz, int6
     TRY3(upload(c, (float*)c->sell_val, v32));
     TRY3(upload(c, (float*)c->inc_w, w32));
     TRY3(upload(c, (float*)c->pair_v, p32));
-    std::vector<float> l32(m.lop_w.begin(), m.lop_w.end()), e32(m.ew.begin(), m.ew.end());
+    std::vector<float> l32(m.lop_w.begin(), m.lop_w.end());
     TRY3(upload(c, (float*)c->lop_w, l32));
-    TRY3(upload(c, (float*)c->ew, e32));
+    TRY3(upload(c, c->geo64, m.geo));
+    TRY3(upload(c, c->dlt, m.dlt));
     std::vector<float> g32(m.geo.begin() + E, m.geo.end());
     TRY3(upload(c, (float*)c->grad, g32));
     HIP_OK3(c, hipStreamSynchronize(c->stream));
@@ -887,12 +922,15 @@ int felbm3d_upload_mesh(felbm3d_ctx* c, int64_t n_nodes, const double* xyz, int6
   const double pops = 38.0 * Nd * s, mat = nnz * (4.0 + s) + (double)(Np / 64 + 1) * 4.0;
   c->bytes[K3_MOMENTS] = 2 * pops + Nd * (8 + 4 * s + 8);
   c->bytes[K3_LAPC] = (double)m.lop_col.size() * (4 + s) + Nd * (8 + 8 + 8 + 4) + (double)m.wl_scale.size() * (12 + 8);
-  c->bytes[K3_LAPMU] = Ed * (16 + 16 + 7 * s + 12 * s + 8 + 13 * s) + Nd * (8 + 8 + s + 3 * s);
+  const double cons = c->prm.precision == FELBM_FP32 ? 1.0 : 0.0;
+  c->bytes[K3_MOMENTS] += cons * Nd * (8 + 72);
+  c->bytes[K3_LAPMU] = Ed * (16 + 16 + 7 * 8 + 12 * s + 8 + 13 * s) + Nd * (8 + 8 + s + 3 * s) +
+                       cons * (Ed * (96 + 32) + Nd * 72);
   c->bytes[K3_RHS] = 2 * pops + (double)m.inc_e.size() * (4 + 4 * s) + (double)m.pair_col.size() * (4 + 9 * s) +
-                     Ed * 13 * s;
-  c->bytes[K3_SWEEP_FIRST] = 2 * pops + mat;
-  c->bytes[K3_SWEEP_MID] = 3 * pops + mat;
-  c->bytes[K3_SWEEP_LAST] = 4 * pops + mat + Nd;
+                     Ed * 13 * s + cons * (Ed * 32 + Nd * 16);
+  c->bytes[K3_SWEEP_FIRST] = 2 * pops + mat + cons * Nd * 24;
+  c->bytes[K3_SWEEP_MID] = 3 * pops + mat + cons * Nd * 32;
+  c->bytes[K3_SWEEP_LAST] = 4 * pops + mat + Nd + cons * Nd * 40;
   c->has_mesh = true;
   return FELBM_OK;
 }
@@ -943,11 +981,11 @@ int felbm3d_init(felbm3d_ctx* c, const double* C, const double* u, const double*
     if (c->prm.precision == FELBM_FP64)
       hipLaunchKernelGGL(k3_init<double>, dim3(g), dim3(BLOCK), 0, c->stream, (int)N, (int)c->Np, c->sp,
                          (const double*)dC, (const double*)dU, (const double*)dP, (const uint8_t*)c->is_wall,
-                         (double*)c->pop);
+                         (double*)c->pop, (double*)nullptr);
     else
       hipLaunchKernelGGL(k3_init<float>, dim3(g), dim3(BLOCK), 0, c->stream, (int)N, (int)c->Np, c->sp,
                          (const double*)dC, (const double*)dU, (const double*)dP, (const uint8_t*)c->is_wall,
-                         (float*)c->pop);
+                         (float*)c->pop, c->rC);
     e = hipGetLastError();
   }
   const int32_t minus1 = -1;
@@ -1027,10 +1065,10 @@ int felbm3d_diagnostics(felbm3d_ctx* c, felbm_diag* out) {
   const int N = (int)c->N, Np = (int)c->Np;
   if (c->prm.precision == FELBM_FP64)
     TRY3(launch3(c, K3_MOMENTS, k3_moments<double, false>, gN, BLOCK, (double*)c->pop, N, Np, c->sp, c->Cn,
-                 (double*)c->pn, (double*)c->un, (const double*)c->mass, c->partials));
+                 (double*)c->pn, (double*)c->un, (const double*)c->mass, c->partials, cons3(c, false)));
   else
     TRY3(launch3(c, K3_MOMENTS, k3_moments<float, false>, gN, BLOCK, (float*)c->pop, N, Np, c->sp, c->Cn,
-                 (float*)c->pn, (float*)c->un, (const double*)c->mass, c->partials));
+                 (float*)c->pn, (float*)c->un, (const double*)c->mass, c->partials, cons3(c, false)));
   // the final pass writes its non-finite flag only where it is negative: a zeroed
   // scratch flag keeps the step's own first-bad-step record untouched
   int32_t* scratch = nullptr;

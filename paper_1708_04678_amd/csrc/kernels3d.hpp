@@ -54,17 +54,44 @@ __host__ __device__ constexpr int opp(int a) {
 
 constexpr int NRED3 = 6;  // same record as the 2-D reductions (band entries stay 0)
 
+// FP32 precision form: the composition is carried in FP64 beside the float
+// populations, C = sum_a h_a + r with a per-node FP64 remainder r.  Its
+// increment is the zeroth moment of the h right-hand side formed in FP64 from
+// the moment identities of the equilibrium (sum_a Phi_h = M lap mu,
+// sum_a e_a Phi_h = c_s^2 X + M lap mu u_bar) and from the first and second
+// moments J, Pi of the collided h; it is solved by the same Chebyshev steps in
+// FP64 with a diagonal that gives the stored float matrix exact mass-weighted
+// column sums, and the last sweep stores r = (C^n + X_C) - sum_a h_a^{n+1}.
+// Each element's moment terms are formed once (by one thread), so all of its
+// vertices see the same values and the mass balance holds to FP64 rounding.
+// Every pointer is null in FP64 (and em in the field read-back).
+struct Cons3 {
+  double* r;           // [N] remainder
+  double* jp;          // [9][Np] J (x, y, z), Pi (xx, yy, zz, xy, xz, yz) of the collided h
+  double* em;          // [4][E] the element's FP64 contribution to the zeroth moment at each
+                       // of its vertices l: V (dt/4 s0 + dt^2/2 grad N_l . s1), with
+                       // s0 = d - sum_v grad N_v . J_v, s1 = c_s^2 X + d u_bar - sum_v Pi_v grad N_v
+  const double* geo;   // [13][E] V and the shape-function gradients in FP64
+  double* fC;          // [Np] right-hand side / m
+  const double* xCin;  // [Np] iterate in
+  double* xCout;       // [Np] iterate out
+  const double* dlt;   // [N] diagonal of the FP64 sweeps
+  const double* Cn;    // [N] composition at the start of the step
+  double w;            // Chebyshev step of the current sweep
+};
+
 // a1 + a6: moments, relaxation time, equilibria and BGK collision; block partials of the reductions
 template <typename real, bool COLLIDE>
 __global__ void __launch_bounds__(BLOCK) k3_moments(real* __restrict__ pop, int N, int Np, StepParams P,
                                                    double* __restrict__ Cn, real* __restrict__ pn,
                                                    real* __restrict__ un, const double* __restrict__ mass,
-                                                   double* __restrict__ partials) {
+                                                   double* __restrict__ partials, Cons3 cs) {
+  constexpr bool CONS = sizeof(real) == 4;
   const int blk = xcd_block();
   const int i = blk * BLOCK + threadIdx.x;
   double red[NRED3] = {0, 0, 0, 0, 0, 0};
   if (i < N) {
-    double C = 0.0;
+    double C = CONS ? cs.r[i] : 0.0;
     real p = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
@@ -87,6 +114,7 @@ __global__ void __launch_bounds__(BLOCK) k3_moments(real* __restrict__ pop, int 
       const real tau = (real)(1.0 / (C * P.inv_tau_l + (1.0 - C) * P.inv_tau_v));
       const real om = (real)1 / (tau + (real)0.5);
       const real Cr = (real)C;
+      double J[3] = {0, 0, 0}, Pi[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
       for (int a = 0; a < Q; ++a) {
         const real eu = (real)ex(a) * ux + (real)ey(a) * uy + (real)ez(a) * uz;
@@ -94,8 +122,27 @@ __global__ void __launch_bounds__(BLOCK) k3_moments(real* __restrict__ pop, int 
         const real geq = (real)wq(a) * (p + rho * poly);
         const real heq = (real)wq(a) * Cr * ((real)1 + (real)3 * poly);
         const real g = pop[a * Np + i], h = pop[(Q + a) * Np + i];
+        const real hn = h - om * (h - heq);
         pop[a * Np + i] = g - om * (g - geq);
-        pop[(Q + a) * Np + i] = h - om * (h - heq);
+        pop[(Q + a) * Np + i] = hn;
+        if (CONS) {
+          const double hd = (double)hn;
+          if (ex(a)) J[0] += ex(a) * hd;
+          if (ey(a)) J[1] += ey(a) * hd;
+          if (ez(a)) J[2] += ez(a) * hd;
+          if (ex(a)) Pi[0] += hd;
+          if (ey(a)) Pi[1] += hd;
+          if (ez(a)) Pi[2] += hd;
+          if (ex(a) && ey(a)) Pi[3] += ex(a) * ey(a) * hd;
+          if (ex(a) && ez(a)) Pi[4] += ex(a) * ez(a) * hd;
+          if (ey(a) && ez(a)) Pi[5] += ey(a) * ez(a) * hd;
+        }
+      }
+      if (CONS) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) cs.jp[c * Np + i] = J[c];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) cs.jp[(3 + c) * Np + i] = Pi[c];
       }
     }
     const double uud = (double)uu;
@@ -191,7 +238,8 @@ __global__ void __launch_bounds__(BLOCK) k3_lapmu_force_op(int E, int Np, const 
                                                           const double* __restrict__ Cn, const double* __restrict__ mu,
                                                           const real* __restrict__ pn, const real* __restrict__ un,
                                                           StepParams P, double* __restrict__ lapmu,
-                                                          real* __restrict__ fpar) {
+                                                          real* __restrict__ fpar, Cons3 cs) {
+  constexpr bool CONS = sizeof(real) == 4;
   const int e = xcd_block() * BLOCK + threadIdx.x;
   if (e >= E) return;
   int v[4];
@@ -248,6 +296,51 @@ __global__ void __launch_bounds__(BLOCK) k3_lapmu_force_op(int E, int Np, const 
   o[10 * E] = (real)gCy - coef * (gpy - by);
   o[11 * E] = (real)gCz - coef * (gpz - bz);
   o[12 * E] = (real)(P.mobility * lm);
+  if (CONS && cs.em) {
+    // FP64 moment terms of this element (FP64 geometry, vertex order 0..3)
+    double gx[4], gy[4], gz[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      gx[t] = cs.geo[(1 + 3 * t) * E + e];
+      gy[t] = cs.geo[(2 + 3 * t) * E + e];
+      gz[t] = cs.geo[(3 + 3 * t) * E + e];
+    }
+    double GCx = 0.0, GCy = 0.0, GCz = 0.0, Gpx = 0.0, Gpy = 0.0, Gpz = 0.0, uxd = 0.0, uyd = 0.0, uzd = 0.0;
+    double divJ = 0.0, Dx = 0.0, Dy = 0.0, Dz = 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      GCx += Cv[t] * gx[t];
+      GCy += Cv[t] * gy[t];
+      GCz += Cv[t] * gz[t];
+      Gpx += (double)pv[t] * gx[t];
+      Gpy += (double)pv[t] * gy[t];
+      Gpz += (double)pv[t] * gz[t];
+      uxd += (double)un[v[t]];
+      uyd += (double)un[Np + v[t]];
+      uzd += (double)un[2 * Np + v[t]];
+      const double* q = cs.jp + v[t];
+      const double Jx = q[0], Jy = q[(size_t)Np], Jz = q[2 * (size_t)Np];
+      const double Pxx = q[3 * (size_t)Np], Pyy = q[4 * (size_t)Np], Pzz = q[5 * (size_t)Np];
+      const double Pxy = q[6 * (size_t)Np], Pxz = q[7 * (size_t)Np], Pyz = q[8 * (size_t)Np];
+      divJ += gx[t] * Jx + gy[t] * Jy + gz[t] * Jz;
+      Dx += Pxx * gx[t] + Pxy * gy[t] + Pxz * gz[t];
+      Dy += Pxy * gx[t] + Pyy * gy[t] + Pyz * gz[t];
+      Dz += Pxz * gx[t] + Pyz * gy[t] + Pzz * gz[t];
+    }
+    uxd *= 0.25;
+    uyd *= 0.25;
+    uzd *= 0.25;
+    const double rhod = Cb * P.rho_l + (1.0 - Cb) * P.rho_v;
+    const double cf = Cb / (rhod * CS2);
+    const double Ml = P.mobility * lm;
+    const double s0 = Ml - divJ;
+    const double s1x = CS2 * (GCx - cf * (Gpx - mub * GCx)) + Ml * uxd - Dx;
+    const double s1y = CS2 * (GCy - cf * (Gpy - mub * GCy)) + Ml * uyd - Dy;
+    const double s1z = CS2 * (GCz - cf * (Gpz - mub * GCz)) + Ml * uzd - Dz;
+    const double V = cs.geo[e], c1 = 0.25 * P.dt, c2 = 0.5 * P.dt * P.dt;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) cs.em[l * E + e] = V * (c1 * s0 + c2 * (gx[l] * s1x + gy[l] * s1y + gz[l] * s1z));
+  }
 }
 
 // a5 + a7: the Galerkin right-hand side (eq:galerkin_lbm) divided by m_i,
@@ -269,7 +362,9 @@ __global__ void __launch_bounds__(BLOCK) k3_rhs(int N, int Np, int E, const int*
                                                int inc_slots, const real* __restrict__ fpar,
                                                const int* __restrict__ pair_ptr, const int* __restrict__ pair_col,
                                                const real* __restrict__ pair_v, int pair_slots,
-                                               const real* __restrict__ pop, real* __restrict__ f) {
+                                               const real* __restrict__ pop, real* __restrict__ f,
+                                               const double* __restrict__ mass, Cons3 cs) {
+  constexpr bool CONS = sizeof(real) == 4;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int blk = xcd_block(), half = gridDim.x >> 1;
   const bool hset = blk >= half;
@@ -279,12 +374,14 @@ __global__ void __launch_bounds__(BLOCK) k3_rhs(int N, int Np, int E, const int*
   real b[Q];
 #pragma unroll
   for (int a = 0; a < Q; ++a) b[a] = (real)0;
+  double bC = 0.0;
   {
     const int base = inc_ptr[slice], width = (inc_ptr[slice + 1] - base) >> 6;
     for (int k = 0; k < width; ++k) {
       const int idx = base + (k << 6) + lane;
-      const int e = inc_e[idx];
-      if (e < 0) continue;
+      const int el = inc_e[idx];
+      if (el < 0) continue;
+      const int e = el >> 2;
       const real al = inc_w[idx], btx = inc_w[inc_slots + idx], bty = inc_w[2 * inc_slots + idx],
                  btz = inc_w[3 * inc_slots + idx];
       const real ux = fpar[e], uy = fpar[E + e], uz = fpar[2 * E + e];
@@ -303,6 +400,7 @@ __global__ void __launch_bounds__(BLOCK) k3_rhs(int N, int Np, int E, const int*
           b[a] += (al + exa * btx + eya * bty + eza * btz) * Phi;
         }
       } else {
+        if (CONS) bC += cs.em[(el & 3) * E + e];  // FP64 zeroth moment, divided by m_i below
         const real Xx = fpar[9 * E + e], Xy = fpar[10 * E + e], Xz = fpar[11 * E + e], d = fpar[12 * E + e];
         const real uX = ux * Xx + uy * Xy + uz * Xz;
 #pragma unroll
@@ -337,6 +435,7 @@ __global__ void __launch_bounds__(BLOCK) k3_rhs(int N, int Np, int E, const int*
   real* __restrict__ fo = f + (hset ? (size_t)Q * Np : 0);
 #pragma unroll
   for (int a = 0; a < Q; ++a) fo[a * Np + i] = b[a];
+  if (CONS && hset) cs.fC[i] = bC / mass[i];
 }
 
 // a8: Richardson sweeps with the reciprocal Chebyshev roots on [1/5, 1] (the
@@ -353,7 +452,9 @@ __global__ void __launch_bounds__(BLOCK) k3_sweep(int N, int Np, const int* __re
                                                  const int* __restrict__ sell_col, const real* __restrict__ sell_val,
                                                  const real* __restrict__ f, const real* __restrict__ xin,
                                                  real* __restrict__ xout, real* __restrict__ pop,
-                                                 const uint8_t* __restrict__ is_wall, real w) {
+                                                 const uint8_t* __restrict__ is_wall, real w, Cons3 cs) {
+  constexpr bool CONS = sizeof(real) == 4;
+  constexpr bool FIRST = MODE == 0 || MODE == 3;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int b = xcd_block(), half = gridDim.x >> 1;
   const bool hset = b >= half;
@@ -364,9 +465,14 @@ __global__ void __launch_bounds__(BLOCK) k3_sweep(int N, int Np, const int* __re
   const real* __restrict__ fs = f + off;
   const real* __restrict__ x = (MODE == 0 || MODE == 3) ? fs : xin + off;
   real r[Q];
+  // the FP64 composition sweep rides with the h set
+  const bool comp = CONS && hset;
+  const double* __restrict__ xC = FIRST ? cs.fC : cs.xCin;
+  double rc = 0.0;
   if (MODE != 4) {
 #pragma unroll
     for (int a = 0; a < Q; ++a) r[a] = (real)0.4 * x[a * Np + i];
+    double accC = comp ? cs.dlt[i] * xC[i] : 0.0;
     const int base = sell_ptr[slice], width = (sell_ptr[slice + 1] - base) >> 6;
     for (int k = 0; k < width; ++k) {
       const int idx = base + (k << 6) + lane;
@@ -374,20 +480,27 @@ __global__ void __launch_bounds__(BLOCK) k3_sweep(int N, int Np, const int* __re
       const real aij = sell_val[idx];
 #pragma unroll
       for (int a = 0; a < Q; ++a) r[a] += aij * x[a * Np + j];
+      if (comp) accC += (double)aij * xC[j];
     }
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
       const real xi = x[a * Np + i];
-      const real fi = (MODE == 0 || MODE == 3) ? xi : fs[a * Np + i];
+      const real fi = FIRST ? xi : fs[a * Np + i];
       r[a] = xi + w * (fi - r[a]);
+    }
+    if (comp) {
+      const double xci = xC[i];
+      rc = xci + cs.w * ((FIRST ? xci : cs.fC[i]) - accC);
     }
   } else {
 #pragma unroll
     for (int a = 0; a < Q; ++a) r[a] = fs[a * Np + i];
+    if (comp) rc = cs.fC[i];
   }
   if (MODE == 0 || MODE == 1) {
 #pragma unroll
     for (int a = 0; a < Q; ++a) xout[off + a * Np + i] = r[a];
+    if (comp) cs.xCout[i] = rc;
     return;
   }
   real* __restrict__ ps = pop + off;
@@ -406,13 +519,20 @@ __global__ void __launch_bounds__(BLOCK) k3_sweep(int N, int Np, const int* __re
   }
 #pragma unroll
   for (int a = 0; a < Q; ++a) ps[a * Np + i] = r[a];
+  if (comp) {
+    double sh = 0.0;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) sh += (double)r[a];
+    cs.r[i] = (cs.Cn[i] + rc) - sh;
+  }
 }
 
 // init: psi_bar^0 = psi_eq(C, u, p), then the wall operator
 template <typename real>
 __global__ void __launch_bounds__(BLOCK) k3_init(int N, int Np, StepParams P, const double* __restrict__ C,
                                                 const double* __restrict__ U, const double* __restrict__ Pr,
-                                                const uint8_t* __restrict__ is_wall, real* __restrict__ pop) {
+                                                const uint8_t* __restrict__ is_wall, real* __restrict__ pop,
+                                                double* __restrict__ rC) {
   const int i = blockIdx.x * BLOCK + threadIdx.x;
   if (i >= N) return;
   const double c = C[i], ux = U[3 * i], uy = U[3 * i + 1], uz = U[3 * i + 2], p = Pr[i];
@@ -437,6 +557,12 @@ __global__ void __launch_bounds__(BLOCK) k3_init(int N, int Np, StepParams P, co
   }
 #pragma unroll
   for (int a = 0; a < NPOP; ++a) pop[a * Np + i] = (real)s[a];
+  if (rC) {  // FP32: the remainder makes C exactly the given composition
+    double sh = 0.0;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) sh += (double)(real)s[Q + a];
+    rC[i] = c - sh;
+  }
 }
 
 }  // namespace felbm3d
