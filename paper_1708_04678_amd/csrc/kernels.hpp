@@ -816,10 +816,13 @@ __device__ __forceinline__ void st_stream(T v, T* p) {
 // element's vertices 0, 1, 2 (9 bits each).  Element data (geometry as one
 // FP64 record, lap mu) is read from global memory, the geometry rounded to the
 // working precision where the arithmetic is; the element gradients of C and
-// p come from the staged vertex values.  FP32 only: the FP64 zeroth h-moment uses
+// p come from the staged vertex values.  Every element sum runs over the
+// vertices in the order 0, 1, 2, so the three vertices of an element form the
+// same streaming derivative; only the test-function weight is the gathering
+// vertex's own.  FP32 only: the FP64 zeroth h-moment uses
 // div J = sum_a s_a, div Pi = sum_a e_a s_a with
-// s_a = sum_v (e_a . grad N_v) h_hat_{a,v}, in a vertex order that does not
-// depend on which vertex gathers, as in k_rhs.
+// s_a = sum_v (e_a . grad N_v) h_hat_{a,v}, as in k_rhs.  The FP32 form is held
+// to 128 VGPRs, so that four workgroups per CU (the LDS limit) are resident.
 // ----------------------------------------------------------------------------
 template <typename real>
 constexpr unsigned rhs_lds_bytes() {
@@ -833,7 +836,7 @@ struct RhsTile {
 };
 
 template <typename real>
-__global__ void __launch_bounds__(BLOCK) k_rhs_lds(int N, int Np, int E, TileArgs ta, RhsTile rt,
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(real) == 4 ? 4 : 1))) k_rhs_lds(int N, int Np, int E, TileArgs ta, RhsTile rt,
                                                   const double* __restrict__ Cn, const real* __restrict__ pn,
                                                   const real* __restrict__ uxn,
                                                   const real* __restrict__ uyn, const double* __restrict__ mu,
@@ -910,9 +913,6 @@ __global__ void __launch_bounds__(BLOCK) k_rhs_lds(int N, int Np, int E, TileArg
     if (en.x < 0) continue;
     const int e = en.x >> 2, l = en.x & 3;
     const int s0 = en.y & 511, s1 = (en.y >> 9) & 511, s2 = (en.y >> 18) & 511;
-    // slots of the two other vertices, in the order (l + 1, l + 2) mod 3
-    const int sa = l == 0 ? s1 : (l == 1 ? s2 : s0);
-    const int sb = l == 0 ? s2 : (l == 1 ? s0 : s1);
     // the element's geometry as one 32-byte record {grad N1, grad N2}; grad N0 =
     // -(grad N1 + grad N2) and A = 1 / (2 det[grad N1; grad N2]) are recomputed
     // (the same values at all three vertices of the element)
@@ -927,13 +927,9 @@ __global__ void __launch_bounds__(BLOCK) k_rhs_lds(int N, int Np, int E, TileArg
       gyf[v] = (real)gyd[v];
     }
     const real A = (real)Ad;
-    // own vertex l and the two others (l + 1, l + 2) mod 3
+    // the gathering vertex's shape-function gradient (test function of the row)
     const real gxl = l == 0 ? gxf[0] : (l == 1 ? gxf[1] : gxf[2]);
     const real gyl = l == 0 ? gyf[0] : (l == 1 ? gyf[1] : gyf[2]);
-    const real gla = l == 0 ? gxf[1] : (l == 1 ? gxf[2] : gxf[0]);
-    const real hla = l == 0 ? gyf[1] : (l == 1 ? gyf[2] : gyf[0]);
-    const real glb = l == 0 ? gxf[2] : (l == 1 ? gxf[0] : gxf[1]);
-    const real hlb = l == 0 ? gyf[2] : (l == 1 ? gyf[0] : gyf[1]);
     // barycentric values of the P1 fields and the element gradients
     const double Cb = (Cs[s0] + Cs[s1] + Cs[s2]) * (1.0 / 3.0);  // barycentric values
     const double mub = (mus[s0] + mus[s1] + mus[s2]) * (1.0 / 3.0);
@@ -955,6 +951,26 @@ __global__ void __launch_bounds__(BLOCK) k_rhs_lds(int N, int Np, int E, TileArg
     const real d = (real)(P.mobility * lm);
     const real uA = ubx * ax + uby * ay, uB = ubx * bx + uby * by, uX = ubx * Xx + uby * Xy;
     const real uu = ubx * ubx + uby * uby;
+    // FP32 only: the parts of the FP64 composition moment that do not depend on
+    // h, formed before the direction loop so that only six doubles stay live
+    // through it: bC += cw0 (M lap mu - div J) + cwl . (s1 - div Pi), with
+    // s1 = c_s^2 X + M lap mu u and cw0 = A dt / 3, cwl = A dt^2 / 2 grad N_l
+    double cw0 = 0.0, cwx = 0.0, cwy = 0.0, Ml = 0.0, s1x = 0.0, s1y = 0.0;
+    if (CONS) {
+      const double uxd = ((double)ux0 + (double)ux1 + (double)ux2) * (1.0 / 3.0);
+      const double uyd = ((double)uy0 + (double)uy1 + (double)uy2) * (1.0 / 3.0);
+      const double cf = Cb / (rhobd * CS2);
+      const double Xdx = gCx - cf * ((double)gpx - mub * gCx), Xdy = gCy - cf * ((double)gpy - mub * gCy);
+      Ml = P.mobility * lm;
+      s1x = CS2 * Xdx + Ml * uxd;
+      s1y = CS2 * Xdy + Ml * uyd;
+      const double gxl_d = l == 0 ? gxd[0] : (l == 1 ? gxd[1] : gxd[2]);
+      const double gyl_d = l == 0 ? gyd[0] : (l == 1 ? gyd[1] : gyd[2]);
+      const double c2d = Ad * (0.5 * P.dt * P.dt);
+      cw0 = Ad * (P.dt * (1.0 / 3.0));
+      cwx = c2d * gxl_d;
+      cwy = c2d * gyl_d;
+    }
     double divJ = 0.0, dPx = 0.0, dPy = 0.0;
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
@@ -963,39 +979,26 @@ __global__ void __launch_bounds__(BLOCK) k_rhs_lds(int N, int Np, int E, TileArg
       const real G = (real)wq(a) * ((real)1 + (real)3 * eu + (real)4.5 * eu * eu - (real)1.5 * uu);
       const real Phig = (exa * ax + eya * ay - uA) * (G - (real)wq(a)) + (exa * bx + eya * by - uB) * G;
       const real Phih = (exa * Xx + eya * Xy - uX + d) * G;
-      const real enl = exa * gxl + eya * gyl;
-      const real ena = exa * gla + eya * hla, enb = exa * glb + eya * hlb;
-      const real ha = ps[(Q + a) * S + sa], hb = ps[(Q + a) * S + sb], hl = ps[(Q + a) * S + lane];
-      const real sg = ps[a * S + lane] * enl + ps[a * S + sa] * ena + ps[a * S + sb] * enb;
-      const real sh = hl * enl + ha * ena + hb * enb;
+      // the element's streaming derivative e_a . grad psi_a over its vertices in
+      // the order 0, 1, 2, the same at each of the three gathering vertices
+      const real en0 = exa * gxf[0] + eya * gyf[0], en1 = exa * gxf[1] + eya * gyf[1];
+      const real en2 = exa * gxf[2] + eya * gyf[2], enl = exa * gxl + eya * gyl;
+      const real h0 = ps[(Q + a) * S + s0], h1 = ps[(Q + a) * S + s1], h2 = ps[(Q + a) * S + s2];
+      const real sg = ps[a * S + s0] * en0 + ps[a * S + s1] * en1 + ps[a * S + s2] * en2;
+      const real sh = h0 * en0 + h1 * en1 + h2 * en2;
       const real wgt = A * (c1 + c2 * enl);
       b[a] += wgt * (Phig - sg);
       b[Q + a] += wgt * (Phih - sh);
       if (CONS && a != 0) {
-        // FP64, vertex order 0, 1, 2 whichever vertex gathers (vertex l holds hl,
-        // vertex l + 1 holds ha, vertex l + 2 holds hb)
-        const double h0v = l == 0 ? hl : (l == 1 ? hb : ha);
-        const double h1v = l == 1 ? hl : (l == 2 ? hb : ha);
-        const double h2v = l == 2 ? hl : (l == 0 ? hb : ha);
-        const double sa_d = (ex(a) * gxd[0] + ey(a) * gyd[0]) * h0v + (ex(a) * gxd[1] + ey(a) * gyd[1]) * h1v +
-                            (ex(a) * gxd[2] + ey(a) * gyd[2]) * h2v;
+        const double sa_d = (ex(a) * gxd[0] + ey(a) * gyd[0]) * (double)h0 +
+                            (ex(a) * gxd[1] + ey(a) * gyd[1]) * (double)h1 +
+                            (ex(a) * gxd[2] + ey(a) * gyd[2]) * (double)h2;
         divJ += sa_d;
         if (ex(a)) dPx += ex(a) * sa_d;
         if (ey(a)) dPy += ey(a) * sa_d;
       }
     }
-    if (CONS) {
-      const double uxd = ((double)ux0 + (double)ux1 + (double)ux2) * (1.0 / 3.0);
-      const double uyd = ((double)uy0 + (double)uy1 + (double)uy2) * (1.0 / 3.0);
-      const double cf = Cb / (rhobd * CS2);
-      const double Xdx = gCx - cf * ((double)gpx - mub * gCx), Xdy = gCy - cf * ((double)gpy - mub * gCy);
-      const double Ml = P.mobility * lm;
-      const double s0m = Ml - divJ;
-      const double s1x = CS2 * Xdx + Ml * uxd - dPx, s1y = CS2 * Xdy + Ml * uyd - dPy;
-      const double gxl_d = l == 0 ? gxd[0] : (l == 1 ? gxd[1] : gxd[2]);
-      const double gyl_d = l == 0 ? gyd[0] : (l == 1 ? gyd[1] : gyd[2]);
-      bC += Ad * (P.dt * (1.0 / 3.0) * s0m + 0.5 * P.dt * P.dt * (gxl_d * s1x + gyl_d * s1y));
-    }
+    if (CONS) bC += cw0 * (Ml - divJ) + cwx * (s1x - dPx) + cwy * (s1y - dPy);
   }
   const real inv_m = (real)(1.0 / mi);
 #pragma unroll
