@@ -854,9 +854,9 @@ int felbm3d_upload_mesh(felbm3d_ctx* c, int64_t n_nodes, const double* xyz, int6
   }
   TRY3(dalloc_bytes(c, &c->grad, 12 * E * rs));
   TRY3(dalloc_bytes(c, &c->pop, 38 * Np * rs));
-  TRY3(dalloc_bytes(c, &c->f, 38 * Np * rs));
-  TRY3(dalloc_bytes(c, &c->xa, 38 * Np * rs));
-  TRY3(dalloc_bytes(c, &c->xb, 38 * Np * rs));
+  TRY3(dalloc_bytes(c, &c->f, 2 * QS * Np * rs));  // solve vectors: [2][5][Np][4]
+  TRY3(dalloc_bytes(c, &c->xa, 2 * QS * Np * rs));
+  TRY3(dalloc_bytes(c, &c->xb, 2 * QS * Np * rs));
   TRY3(dalloc_bytes(c, &c->pn, Np * rs));
   TRY3(dalloc_bytes(c, &c->un, 3 * Np * rs));
   TRY3(dalloc(c, &c->Cn, N));
@@ -912,9 +912,9 @@ int felbm3d_upload_mesh(felbm3d_ctx* c, int64_t n_nodes, const double* xyz, int6
   std::vector<double> zeros(N, 0.0);
   TRY3(upload(c, c->bc, zeros));
   HIP_OK3(c, hipMemsetAsync(c->pop, 0, 38 * Np * rs, c->stream));
-  HIP_OK3(c, hipMemsetAsync(c->f, 0, 38 * Np * rs, c->stream));
-  HIP_OK3(c, hipMemsetAsync(c->xa, 0, 38 * Np * rs, c->stream));
-  HIP_OK3(c, hipMemsetAsync(c->xb, 0, 38 * Np * rs, c->stream));
+  HIP_OK3(c, hipMemsetAsync(c->f, 0, 2 * QS * Np * rs, c->stream));
+  HIP_OK3(c, hipMemsetAsync(c->xa, 0, 2 * QS * Np * rs, c->stream));
+  HIP_OK3(c, hipMemsetAsync(c->xb, 0, 2 * QS * Np * rs, c->stream));
   HIP_OK3(c, hipMemsetAsync(c->un, 0, 3 * Np * rs, c->stream));
   HIP_OK3(c, hipStreamSynchronize(c->stream));
   // algorithmic bytes per launch (perfect reuse of gathered data)

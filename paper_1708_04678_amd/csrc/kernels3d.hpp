@@ -17,6 +17,9 @@
 //                its diagonal is M11_ii / m_i = 2/5 for P1 tetrahedra
 //   right-hand side: incident-element weights [4][slots] and patch moments
 //                [9][slots] in sliced ELL; element force parameters [13][E]
+//   solve vectors (the right-hand side f and the sweep iterates): per
+//                population set [5][Np][4], populations 4q..4q+3 of node j
+//                at [q][j], slot 19 unused (0), g set then h set
 #pragma once
 
 #include "common.hpp"
@@ -50,6 +53,50 @@ __host__ __device__ constexpr int ez(int a) {
 __host__ __device__ constexpr double wq(int a) { return a == 0 ? 1.0 / 3.0 : (a < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
 __host__ __device__ constexpr int opp(int a) {
   return a == 0 ? 0 : (a < 7 ? ((a & 1) ? a + 1 : a - 1) : (((a - 7) & 1) ? a - 1 : a + 1));
+}
+
+// The solve vectors hold each population set as five groups of four
+// populations per node, so that the 19 values of a gathered neighbour arrive
+// in five 16-byte (FP64: 32-byte) loads instead of nineteen 4-byte ones.
+constexpr int QS = 20;  // slots per node and set in the solve vectors
+template <typename real>
+struct Quad4;
+template <>
+struct Quad4<float> {
+  using type = float4;
+};
+template <>
+struct Quad4<double> {
+  using type = double4;
+};
+// v[0..19] <- the set at node j (v[19] is the unused slot)
+template <typename real>
+__device__ __forceinline__ void load_set(const real* __restrict__ base, int j, int Np, real* v) {
+  using V4 = typename Quad4<real>::type;
+  const V4* b4 = reinterpret_cast<const V4*>(base);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    const V4 t = b4[(size_t)q * Np + j];
+    v[4 * q] = t.x;
+    v[4 * q + 1] = t.y;
+    v[4 * q + 2] = t.z;
+    v[4 * q + 3] = t.w;
+  }
+}
+// the set at node i <- v[0..18]; the unused slot is written as 0
+template <typename real>
+__device__ __forceinline__ void store_set(real* __restrict__ base, int i, int Np, const real* v) {
+  using V4 = typename Quad4<real>::type;
+  V4* b4 = reinterpret_cast<V4*>(base);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    V4 t;
+    t.x = v[4 * q];
+    t.y = v[4 * q + 1];
+    t.z = v[4 * q + 2];
+    t.w = q < 4 ? v[4 * q + 3] : (real)0;
+    b4[(size_t)q * Np + i] = t;
+  }
 }
 
 constexpr int NRED3 = 6;  // same record as the 2-D reductions (band entries stay 0)
@@ -432,9 +479,7 @@ __global__ void __launch_bounds__(BLOCK) k3_rhs(int N, int Np, int E, const int*
       }
     }
   }
-  real* __restrict__ fo = f + (hset ? (size_t)Q * Np : 0);
-#pragma unroll
-  for (int a = 0; a < Q; ++a) fo[a * Np + i] = b[a];
+  store_set(f + (hset ? (size_t)QS * Np : 0), i, Np, b);
   if (CONS && hset) cs.fC[i] = bC / mass[i];
 }
 
@@ -461,49 +506,55 @@ __global__ void __launch_bounds__(BLOCK) k3_sweep(int N, int Np, const int* __re
   const int slice = (b - (hset ? half : 0)) * 4 + wave;
   const int i = (slice << 6) + lane;
   if (i >= N) return;
-  const size_t off = hset ? (size_t)Q * Np : 0;
+  const size_t off = hset ? (size_t)QS * Np : 0;  // solve vectors
   const real* __restrict__ fs = f + off;
   const real* __restrict__ x = (MODE == 0 || MODE == 3) ? fs : xin + off;
-  real r[Q];
+  real r[QS], v[QS];
   // the FP64 composition sweep rides with the h set
   const bool comp = CONS && hset;
   const double* __restrict__ xC = FIRST ? cs.fC : cs.xCin;
   double rc = 0.0;
   if (MODE != 4) {
+    load_set(x, i, Np, v);
 #pragma unroll
-    for (int a = 0; a < Q; ++a) r[a] = (real)0.4 * x[a * Np + i];
+    for (int a = 0; a < Q; ++a) r[a] = (real)0.4 * v[a];
     double accC = comp ? cs.dlt[i] * xC[i] : 0.0;
     const int base = sell_ptr[slice], width = (sell_ptr[slice + 1] - base) >> 6;
     for (int k = 0; k < width; ++k) {
       const int idx = base + (k << 6) + lane;
       const int j = sell_col[idx];
       const real aij = sell_val[idx];
+      load_set(x, j, Np, v);
 #pragma unroll
-      for (int a = 0; a < Q; ++a) r[a] += aij * x[a * Np + j];
+      for (int a = 0; a < Q; ++a) r[a] += aij * v[a];
       if (comp) accC += (double)aij * xC[j];
     }
+    // x_i and f_i again (the first read is in cache), so that they hold no
+    // registers through the gather
+    load_set(x, i, Np, v);
+    if (FIRST) {
 #pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      const real xi = x[a * Np + i];
-      const real fi = FIRST ? xi : fs[a * Np + i];
-      r[a] = xi + w * (fi - r[a]);
+      for (int a = 0; a < Q; ++a) r[a] = v[a] + w * (v[a] - r[a]);
+    } else {
+      real fv[QS];
+      load_set(fs, i, Np, fv);
+#pragma unroll
+      for (int a = 0; a < Q; ++a) r[a] = v[a] + w * (fv[a] - r[a]);
     }
     if (comp) {
       const double xci = xC[i];
       rc = xci + cs.w * ((FIRST ? xci : cs.fC[i]) - accC);
     }
   } else {
-#pragma unroll
-    for (int a = 0; a < Q; ++a) r[a] = fs[a * Np + i];
+    load_set(fs, i, Np, r);
     if (comp) rc = cs.fC[i];
   }
   if (MODE == 0 || MODE == 1) {
-#pragma unroll
-    for (int a = 0; a < Q; ++a) xout[off + a * Np + i] = r[a];
+    store_set(xout + off, i, Np, r);
     if (comp) cs.xCout[i] = rc;
     return;
   }
-  real* __restrict__ ps = pop + off;
+  real* __restrict__ ps = pop + (hset ? (size_t)Q * Np : 0);
 #pragma unroll
   for (int a = 0; a < Q; ++a) r[a] += ps[a * Np + i];
   if (is_wall[i]) {
