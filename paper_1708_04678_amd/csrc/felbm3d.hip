@@ -853,7 +853,7 @@ int felbm3d_upload_mesh(felbm3d_ctx* c, int64_t n_nodes, const double* xyz, int6
     TRY3(dalloc(c, &c->dlt, N));
   }
   TRY3(dalloc_bytes(c, &c->grad, 12 * E * rs));
-  TRY3(dalloc_bytes(c, &c->pop, 38 * Np * rs));
+  TRY3(dalloc_bytes(c, &c->pop, 2 * QS * Np * rs));  // [2][5][Np][4]
   TRY3(dalloc_bytes(c, &c->f, 2 * QS * Np * rs));  // solve vectors: [2][5][Np][4]
   TRY3(dalloc_bytes(c, &c->xa, 2 * QS * Np * rs));
   TRY3(dalloc_bytes(c, &c->xb, 2 * QS * Np * rs));
@@ -911,7 +911,7 @@ int felbm3d_upload_mesh(felbm3d_ctx* c, int64_t n_nodes, const double* xyz, int6
   }
   std::vector<double> zeros(N, 0.0);
   TRY3(upload(c, c->bc, zeros));
-  HIP_OK3(c, hipMemsetAsync(c->pop, 0, 38 * Np * rs, c->stream));
+  HIP_OK3(c, hipMemsetAsync(c->pop, 0, 2 * QS * Np * rs, c->stream));
   HIP_OK3(c, hipMemsetAsync(c->f, 0, 2 * QS * Np * rs, c->stream));
   HIP_OK3(c, hipMemsetAsync(c->xa, 0, 2 * QS * Np * rs, c->stream));
   HIP_OK3(c, hipMemsetAsync(c->xb, 0, 2 * QS * Np * rs, c->stream));
@@ -1051,9 +1051,15 @@ int felbm3d_read_populations(felbm3d_ctx* c, double* out) {
   if (!c->has_state) return fail(c, FELBM_ESTATE, "read_populations: not initialised");
   if (!out) return fail(c, FELBM_EINVAL, "read_populations: null output");
   std::vector<double> host;
-  TRY3(copy_out(c, c->pop, true, 38 * c->Np, host));
-  for (int64_t a = 0; a < 38; ++a)
-    std::copy(host.begin() + a * c->Np, host.begin() + a * c->Np + c->N, out + a * c->N);
+  TRY3(copy_out(c, c->pop, true, 2 * QS * c->Np, host));
+  // device [set][a / 4][Np][a % 4] -> caller [set * 19 + a][N]
+  const int64_t Np = c->Np, N = c->N;
+  for (int64_t set = 0; set < 2; ++set)
+    for (int64_t a = 0; a < Q; ++a) {
+      const double* src = host.data() + set * QS * Np + (a >> 2) * 4 * Np + (a & 3);
+      double* dst = out + (set * Q + a) * N;
+      for (int64_t j = 0; j < N; ++j) dst[j] = src[4 * j];
+    }
   return FELBM_OK;
 }
 

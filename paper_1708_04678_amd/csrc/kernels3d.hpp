@@ -6,7 +6,8 @@
 // order.
 //
 // Data layout (device):
-//   populations  real [38][Np]   g_0..g_18 then h_0..h_18, Np = N rounded to 64
+//   populations  per set [5][Np][4] (populations 4q..4q+3 of node j at [q][j],
+//                slot 19 unused), the g set then the h set, Np = N rounded to 64
 //   elements     tet int32 [4][E]; shape-function gradients [12][E] in the
 //                working precision (grad N_0 .. grad N_3)
 //   field operators: the patch Laplacian of C over the 2-ring (sliced ELL,
@@ -17,9 +18,8 @@
 //                its diagonal is M11_ii / m_i = 2/5 for P1 tetrahedra
 //   right-hand side: incident-element weights [4][slots] and patch moments
 //                [9][slots] in sliced ELL; element force parameters [13][E]
-//   solve vectors (the right-hand side f and the sweep iterates): per
-//                population set [5][Np][4], populations 4q..4q+3 of node j
-//                at [q][j], slot 19 unused (0), g set then h set
+//   solve vectors (the right-hand side f and the sweep iterates): the same
+//                layout as the populations
 #pragma once
 
 #include "common.hpp"
@@ -55,10 +55,11 @@ __host__ __device__ constexpr int opp(int a) {
   return a == 0 ? 0 : (a < 7 ? ((a & 1) ? a + 1 : a - 1) : (((a - 7) & 1) ? a - 1 : a + 1));
 }
 
-// The solve vectors hold each population set as five groups of four
-// populations per node, so that the 19 values of a gathered neighbour arrive
-// in five 16-byte (FP64: 32-byte) loads instead of nineteen 4-byte ones.
-constexpr int QS = 20;  // slots per node and set in the solve vectors
+// The populations and the solve vectors hold each population set as five
+// groups of four populations per node, so that the 19 values of a gathered
+// neighbour arrive in five 16-byte (FP64: 32-byte) loads instead of nineteen
+// 4-byte ones.
+constexpr int QS = 20;  // slots per node and set
 template <typename real>
 struct Quad4;
 template <>
@@ -140,14 +141,19 @@ __global__ void __launch_bounds__(BLOCK) k3_moments(real* __restrict__ pop, int 
   if (i < N) {
     double C = CONS ? cs.r[i] : 0.0;
     real p = 0, jx = 0, jy = 0, jz = 0;
+    {
+      real gv[QS], hv[QS];
+      load_set(pop, i, Np, gv);
+      load_set(pop + (size_t)QS * Np, i, Np, hv);
 #pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      const real g = pop[a * Np + i];
-      C += (double)pop[(Q + a) * Np + i];
-      p += g;
+      for (int a = 0; a < Q; ++a) {
+        const real g = gv[a];
+        C += (double)hv[a];
+        p += g;
       if (ex(a)) jx += ex(a) > 0 ? g : -g;
       if (ey(a)) jy += ey(a) > 0 ? g : -g;
-      if (ez(a)) jz += ez(a) > 0 ? g : -g;
+        if (ez(a)) jz += ez(a) > 0 ? g : -g;
+      }
     }
     const real rho = (real)(C * P.rho_l + (1.0 - C) * P.rho_v);
     const real ux = (real)3 * jx / rho, uy = (real)3 * jy / rho, uz = (real)3 * jz / rho;
@@ -162,28 +168,42 @@ __global__ void __launch_bounds__(BLOCK) k3_moments(real* __restrict__ pop, int 
       const real om = (real)1 / (tau + (real)0.5);
       const real Cr = (real)C;
       double J[3] = {0, 0, 0}, Pi[6] = {0, 0, 0, 0, 0, 0};
+      using V4 = typename Quad4<real>::type;
+      V4* pg = reinterpret_cast<V4*>(pop);
+      V4* ph = reinterpret_cast<V4*>(pop + (size_t)QS * Np);
+      // one group of four populations at a time (read again: the first read is in cache)
 #pragma unroll
-      for (int a = 0; a < Q; ++a) {
-        const real eu = (real)ex(a) * ux + (real)ey(a) * uy + (real)ez(a) * uz;
-        const real poly = eu + (real)1.5 * eu * eu - (real)0.5 * uu;
-        const real geq = (real)wq(a) * (p + rho * poly);
-        const real heq = (real)wq(a) * Cr * ((real)1 + (real)3 * poly);
-        const real g = pop[a * Np + i], h = pop[(Q + a) * Np + i];
-        const real hn = h - om * (h - heq);
-        pop[a * Np + i] = g - om * (g - geq);
-        pop[(Q + a) * Np + i] = hn;
-        if (CONS) {
-          const double hd = (double)hn;
-          if (ex(a)) J[0] += ex(a) * hd;
-          if (ey(a)) J[1] += ey(a) * hd;
-          if (ez(a)) J[2] += ez(a) * hd;
-          if (ex(a)) Pi[0] += hd;
-          if (ey(a)) Pi[1] += hd;
-          if (ez(a)) Pi[2] += hd;
-          if (ex(a) && ey(a)) Pi[3] += ex(a) * ey(a) * hd;
-          if (ex(a) && ez(a)) Pi[4] += ex(a) * ez(a) * hd;
-          if (ey(a) && ez(a)) Pi[5] += ey(a) * ez(a) * hd;
+      for (int q = 0; q < 5; ++q) {
+        const V4 g4 = pg[(size_t)q * Np + i], h4 = ph[(size_t)q * Np + i];
+        const real gq[4] = {g4.x, g4.y, g4.z, g4.w}, hq[4] = {h4.x, h4.y, h4.z, h4.w};
+        real go[4] = {0, 0, 0, 0}, ho[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int a = 4 * q + c;
+          if (a >= Q) continue;
+          const real eu = (real)ex(a) * ux + (real)ey(a) * uy + (real)ez(a) * uz;
+          const real poly = eu + (real)1.5 * eu * eu - (real)0.5 * uu;
+          const real geq = (real)wq(a) * (p + rho * poly);
+          const real heq = (real)wq(a) * Cr * ((real)1 + (real)3 * poly);
+          const real g = gq[c], h = hq[c];
+          const real hn = h - om * (h - heq);
+          go[c] = g - om * (g - geq);
+          ho[c] = hn;
+          if (CONS) {
+            const double hd = (double)hn;
+            if (ex(a)) J[0] += ex(a) * hd;
+            if (ey(a)) J[1] += ey(a) * hd;
+            if (ez(a)) J[2] += ez(a) * hd;
+            if (ex(a)) Pi[0] += hd;
+            if (ey(a)) Pi[1] += hd;
+            if (ez(a)) Pi[2] += hd;
+            if (ex(a) && ey(a)) Pi[3] += ex(a) * ey(a) * hd;
+            if (ex(a) && ez(a)) Pi[4] += ex(a) * ez(a) * hd;
+            if (ey(a) && ez(a)) Pi[5] += ey(a) * ez(a) * hd;
+          }
         }
+        pg[(size_t)q * Np + i] = V4{go[0], go[1], go[2], go[3]};
+        ph[(size_t)q * Np + i] = V4{ho[0], ho[1], ho[2], ho[3]};
       }
       if (CONS) {
 #pragma unroll
@@ -460,7 +480,7 @@ __global__ void __launch_bounds__(BLOCK) k3_rhs(int N, int Np, int E, const int*
       }
     }
   }
-  const real* __restrict__ ps = pop + (hset ? (size_t)Q * Np : 0);
+  const real* __restrict__ ps = pop + (hset ? (size_t)QS * Np : 0);
   {
     const int base = pair_ptr[slice], width = (pair_ptr[slice + 1] - base) >> 6;
     for (int k = 0; k < width; ++k) {
@@ -470,12 +490,14 @@ __global__ void __launch_bounds__(BLOCK) k3_rhs(int N, int Np, int E, const int*
       const real Sxx = pair_v[3 * pair_slots + idx], Syy = pair_v[4 * pair_slots + idx],
                  Szz = pair_v[5 * pair_slots + idx], Sxy = pair_v[6 * pair_slots + idx],
                  Sxz = pair_v[7 * pair_slots + idx], Syz = pair_v[8 * pair_slots + idx];
+      real v[QS];
+      load_set(ps, j, Np, v);
 #pragma unroll
       for (int a = 0; a < Q; ++a) {
         const real exa = (real)ex(a), eya = (real)ey(a), eza = (real)ez(a);
         const real c = exa * Gx + eya * Gy + eza * Gz + exa * exa * Sxx + eya * eya * Syy + eza * eza * Szz +
                        exa * eya * Sxy + exa * eza * Sxz + eya * eza * Syz;
-        b[a] -= c * ps[a * Np + j];
+        b[a] -= c * v[a];
       }
     }
   }
@@ -506,7 +528,7 @@ __global__ void __launch_bounds__(BLOCK) k3_sweep(int N, int Np, const int* __re
   const int slice = (b - (hset ? half : 0)) * 4 + wave;
   const int i = (slice << 6) + lane;
   if (i >= N) return;
-  const size_t off = hset ? (size_t)QS * Np : 0;  // solve vectors
+  const size_t off = hset ? (size_t)QS * Np : 0;  // the set in the populations and solve vectors
   const real* __restrict__ fs = f + off;
   const real* __restrict__ x = (MODE == 0 || MODE == 3) ? fs : xin + off;
   real r[QS], v[QS];
@@ -554,9 +576,10 @@ __global__ void __launch_bounds__(BLOCK) k3_sweep(int N, int Np, const int* __re
     if (comp) cs.xCout[i] = rc;
     return;
   }
-  real* __restrict__ ps = pop + (hset ? (size_t)Q * Np : 0);
+  real* __restrict__ ps = pop + off;
+  load_set(ps, i, Np, v);
 #pragma unroll
-  for (int a = 0; a < Q; ++a) r[a] += ps[a * Np + i];
+  for (int a = 0; a < Q; ++a) r[a] += v[a];
   if (is_wall[i]) {
 #pragma unroll
     for (int a = 1; a < Q; ++a) {
@@ -568,8 +591,7 @@ __global__ void __launch_bounds__(BLOCK) k3_sweep(int N, int Np, const int* __re
       }
     }
   }
-#pragma unroll
-  for (int a = 0; a < Q; ++a) ps[a * Np + i] = r[a];
+  store_set(ps, i, Np, r);
   if (comp) {
     double sh = 0.0;
 #pragma unroll
@@ -606,8 +628,14 @@ __global__ void __launch_bounds__(BLOCK) k3_init(int N, int Np, StepParams P, co
       }
     }
   }
+  real gv[Q], hv[Q];
 #pragma unroll
-  for (int a = 0; a < NPOP; ++a) pop[a * Np + i] = (real)s[a];
+  for (int a = 0; a < Q; ++a) {
+    gv[a] = (real)s[a];
+    hv[a] = (real)s[Q + a];
+  }
+  store_set(pop, i, Np, gv);
+  store_set(pop + (size_t)QS * Np, i, Np, hv);
   if (rC) {  // FP32: the remainder makes C exactly the given composition
     double sh = 0.0;
 #pragma unroll
