@@ -536,7 +536,7 @@ struct felbm3d_ctx {
   // FP32 composition transport (null in FP64)
   double *rC = nullptr, *jp = nullptr, *em = nullptr, *geo64 = nullptr, *fC = nullptr, *xCa = nullptr, *xCb = nullptr,
          *dlt = nullptr;
-  void* grad = nullptr;  // [12][E] shape-function gradients, working precision
+  double* grad = nullptr;  // [9][E] grad N_1 .. grad N_3 (FP64 steps)
   uint8_t* is_wall = nullptr;
   void *sell_val = nullptr, *pop = nullptr, *f = nullptr, *xa = nullptr, *xb = nullptr, *pn = nullptr, *un = nullptr;
   int32_t *lop_ptr = nullptr, *lop_col = nullptr, *wl_ptr = nullptr, *wl_face = nullptr, *eopp = nullptr;
@@ -678,7 +678,7 @@ int enqueue_fields(felbm3d_ctx* c, bool collide, DiagRecord* rec) {
                (const real*)c->lop_w, (const int*)c->wl_ptr, (const int*)c->wl_face, (const double*)c->wl_scale,
                (int)c->n_wall_entries, (const double*)c->Cn, (const double*)c->bc, c->sp, c->lapC, c->mu));
   return launch3(c, K3_LAPMU, k3_lapmu_force_op<real, double>, gE, BLOCK, E, Np, (const int*)c->tet,
-                 (const int*)c->eopp, (const double*)c->ew, (const real*)c->grad, (const double*)c->Cn,
+                 (const int*)c->eopp, (const double*)c->ew, (const double*)c->grad, (const double*)c->Cn,
                  (const double*)c->mu, (const real*)c->pn, (const real*)c->un, c->sp, c->lapmu, (real*)c->fpar, cs);
 }
 
@@ -846,13 +846,13 @@ int felbm3d_upload_mesh(felbm3d_ctx* c, int64_t n_nodes, const double* xyz, int6
     TRY3(dalloc(c, &c->rC, N));
     TRY3(dalloc(c, &c->jp, 9 * Np));
     TRY3(dalloc(c, &c->em, 4 * E));
-    TRY3(dalloc(c, &c->geo64, 13 * E));
+    TRY3(dalloc(c, &c->geo64, 10 * E));  // V, grad N_1 .. grad N_3
     TRY3(dalloc(c, &c->fC, Np));
     TRY3(dalloc(c, &c->xCa, Np));
     TRY3(dalloc(c, &c->xCb, Np));
     TRY3(dalloc(c, &c->dlt, N));
   }
-  TRY3(dalloc_bytes(c, &c->grad, 12 * E * rs));
+  if (c->prm.precision == FELBM_FP64) TRY3(dalloc(c, &c->grad, 9 * E));  // grad N_1 .. grad N_3
   TRY3(dalloc_bytes(c, &c->pop, 2 * QS * Np * rs));  // [2][5][Np][4]
   TRY3(dalloc_bytes(c, &c->f, 2 * QS * Np * rs));  // solve vectors: [2][5][Np][4]
   TRY3(dalloc_bytes(c, &c->xa, 2 * QS * Np * rs));
@@ -892,7 +892,7 @@ int felbm3d_upload_mesh(felbm3d_ctx* c, int64_t n_nodes, const double* xyz, int6
     TRY3(upload(c, (double*)c->inc_w, m.inc_w));
     TRY3(upload(c, (double*)c->pair_v, m.pair_v));
     TRY3(upload(c, (double*)c->lop_w, m.lop_w));
-    std::vector<double> g64(m.geo.begin() + E, m.geo.end());
+    std::vector<double> g64(m.geo.begin() + 4 * E, m.geo.end());
     TRY3(upload(c, (double*)c->grad, g64));
     HIP_OK3(c, hipStreamSynchronize(c->stream));
   } else {
@@ -903,10 +903,11 @@ int felbm3d_upload_mesh(felbm3d_ctx* c, int64_t n_nodes, const double* xyz, int6
     TRY3(upload(c, (float*)c->pair_v, p32));
     std::vector<float> l32(m.lop_w.begin(), m.lop_w.end());
     TRY3(upload(c, (float*)c->lop_w, l32));
-    TRY3(upload(c, c->geo64, m.geo));
+    std::vector<double> geo(10 * E);  // V, then the rows of grad N_1 .. grad N_3
+    std::copy(m.geo.begin(), m.geo.begin() + E, geo.begin());
+    std::copy(m.geo.begin() + 4 * E, m.geo.end(), geo.begin() + E);
+    TRY3(upload(c, c->geo64, geo));
     TRY3(upload(c, c->dlt, m.dlt));
-    std::vector<float> g32(m.geo.begin() + E, m.geo.end());
-    TRY3(upload(c, (float*)c->grad, g32));
     HIP_OK3(c, hipStreamSynchronize(c->stream));
   }
   std::vector<double> zeros(N, 0.0);

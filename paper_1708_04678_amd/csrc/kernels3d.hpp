@@ -8,8 +8,10 @@
 // Data layout (device):
 //   populations  per set [5][Np][4] (populations 4q..4q+3 of node j at [q][j],
 //                slot 19 unused), the g set then the h set, Np = N rounded to 64
-//   elements     tet int32 [4][E]; shape-function gradients [12][E] in the
-//                working precision (grad N_0 .. grad N_3)
+//   elements     tet int32 [4][E]; shape-function gradients grad N_1 .. grad N_3
+//                ([9][E], grad N_0 = -(grad N_1 + grad N_2 + grad N_3) formed
+//                in the kernel): FP64 steps as such, FP32 steps from the FP64
+//                geometry record [10][E] = (V, grad N_1 .. grad N_3)
 //   field operators: the patch Laplacian of C over the 2-ring (sliced ELL,
 //                weights / patch volume) with the wall faces of each patch
 //                (CSR); the element Laplacian of mu ([4][E] vertices across
@@ -119,7 +121,7 @@ struct Cons3 {
   double* em;          // [4][E] the element's FP64 contribution to the zeroth moment at each
                        // of its vertices l: V (dt/4 s0 + dt^2/2 grad N_l . s1), with
                        // s0 = d - sum_v grad N_v . J_v, s1 = c_s^2 X + d u_bar - sum_v Pi_v grad N_v
-  const double* geo;   // [13][E] V and the shape-function gradients in FP64
+  const double* geo;   // [10][E] V and grad N_1 .. grad N_3 in FP64
   double* fC;          // [Np] right-hand side / m
   const double* xCin;  // [Np] iterate in
   double* xCout;       // [Np] iterate out
@@ -296,12 +298,14 @@ __global__ void __launch_bounds__(BLOCK) k3_lapC_mu_op(int N, const int* __restr
 // A = (rho_l - rho_v) c_s^2 grad C_T and B = mu_bar grad C_T, for the h set
 // X = grad C_T - C_bar / (rho_bar c_s^2) (grad p_T - mu_bar grad C_T) and
 // d = M lap mu_T; both with u_bar.  Stored [13][E] as (u_bar, A, B, X, d).
-// The shape-function gradients are read in the working precision ([12][E]):
-// every force parameter is rounded to it.
+// The shape-function gradients grad N_1 .. grad N_3 are read in FP64 (FP32
+// steps: from the geometry record) and grad N_0 = -(grad N_1 + grad N_2 +
+// grad N_3) formed in the order of the mesh preparation; every force
+// parameter is rounded to the working precision.
 template <typename real, typename wreal>
 __global__ void __launch_bounds__(BLOCK) k3_lapmu_force_op(int E, int Np, const int* __restrict__ tet,
                                                           const int* __restrict__ eopp, const wreal* __restrict__ ew,
-                                                          const real* __restrict__ grad,
+                                                          const double* __restrict__ grad,
                                                           const double* __restrict__ Cn, const double* __restrict__ mu,
                                                           const real* __restrict__ pn, const real* __restrict__ un,
                                                           StepParams P, double* __restrict__ lapmu,
@@ -331,11 +335,23 @@ __global__ void __launch_bounds__(BLOCK) k3_lapmu_force_op(int E, int Np, const 
 #pragma unroll
   for (int l = 0; l < 4; ++l) lm += (double)ew[(3 + l) * E + e] * (mu[eopp[l * E + e]] - mv[0]);
   lapmu[e] = lm;
+  // FP64 shape-function gradients (rows of vertex 1..3), grad N_0 from their sum
+  const double* __restrict__ g = CONS ? cs.geo + E : grad;
+  double gxd[4], gyd[4], gzd[4];
+#pragma unroll
+  for (int t = 1; t < 4; ++t) {
+    gxd[t] = g[(3 * t - 3) * E + e];
+    gyd[t] = g[(3 * t - 2) * E + e];
+    gzd[t] = g[(3 * t - 1) * E + e];
+  }
+  gxd[0] = -(gxd[1] + gxd[2] + gxd[3]);
+  gyd[0] = -(gyd[1] + gyd[2] + gyd[3]);
+  gzd[0] = -(gzd[1] + gzd[2] + gzd[3]);
   double gCx = 0.0, gCy = 0.0, gCz = 0.0;
   real gpx = 0, gpy = 0, gpz = 0;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const real gx = grad[(3 * t) * E + e], gy = grad[(3 * t + 1) * E + e], gz = grad[(3 * t + 2) * E + e];
+    const real gx = (real)gxd[t], gy = (real)gyd[t], gz = (real)gzd[t];
     gCx += Cv[t] * (double)gx;
     gCy += Cv[t] * (double)gy;
     gCz += Cv[t] * (double)gz;
@@ -365,13 +381,7 @@ __global__ void __launch_bounds__(BLOCK) k3_lapmu_force_op(int E, int Np, const 
   o[12 * E] = (real)(P.mobility * lm);
   if (CONS && cs.em) {
     // FP64 moment terms of this element (FP64 geometry, vertex order 0..3)
-    double gx[4], gy[4], gz[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      gx[t] = cs.geo[(1 + 3 * t) * E + e];
-      gy[t] = cs.geo[(2 + 3 * t) * E + e];
-      gz[t] = cs.geo[(3 + 3 * t) * E + e];
-    }
+    const double *gx = gxd, *gy = gyd, *gz = gzd;
     double GCx = 0.0, GCy = 0.0, GCz = 0.0, Gpx = 0.0, Gpy = 0.0, Gpz = 0.0, uxd = 0.0, uyd = 0.0, uzd = 0.0;
     double divJ = 0.0, Dx = 0.0, Dy = 0.0, Dz = 0.0;
 #pragma unroll
