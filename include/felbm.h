@@ -184,6 +184,14 @@ int felbm_upload_mesh(felbm_ctx* ctx, int64_t n_nodes, const double* xy, int64_t
  * nonzero with kappa = 0), ESTATE (no mesh). */
 int felbm_set_wetting(felbm_ctx* ctx, const double* omega_c);
 
+/* The same with omega_c_dev [n_nodes] in device memory (caller node order,
+ * double), for callers whose data already lives on the GPU (an autograd
+ * graph).  The values are checked on the device first, so a rejected call
+ * leaves the wetting field as it was; the bound stream is synchronised
+ * before returning, after which omega_c_dev may be reused.  Same errors as
+ * felbm_set_wetting, plus EDEVICE. */
+int felbm_set_wetting_device(felbm_ctx* ctx, const double* omega_c_dev);
+
 /* Initialise the populations to the equilibria (eqn::g_eq, eqn::f_eq) of
  * C [n_nodes], u [n_nodes][2] (NULL = 0) and p [n_nodes] (NULL = 0), then
  * apply the wall operator.  Resets the step counter.
@@ -202,6 +210,13 @@ int felbm_step_async(felbm_ctx* ctx, int64_t n_steps);
 /* Copy a field derived from the current state to out (caller-owned double,
  * N or E values as listed above).  Errors: EINVAL, ESTATE. */
 int felbm_read(felbm_ctx* ctx, int32_t field, double* out);
+
+/* A nodal field (FELBM_FIELD_C .. FELBM_FIELD_LAPC) written to out_dev
+ * [n_nodes] in device memory (caller-owned, caller node order, double), with
+ * the same values as felbm_read.  Queued on the bound stream without
+ * waiting: work the caller queues after it on that stream sees the values.
+ * Errors: EINVAL (null, element field), ESTATE, EDEVICE. */
+int felbm_read_device(felbm_ctx* ctx, int32_t field, double* out_dev);
 
 /* Copy the current populations to out [18][n_nodes] (g_0..g_8, h_0..h_8) as
  * double.  In FELBM_FP32 the composition is sum_a h_a plus an FP64 remainder

@@ -18,10 +18,12 @@ class WettingToComposition(torch.autograd.Function):
     def forward(ctx, omega: torch.Tensor, sim: Context, C0: np.ndarray, n_steps: int, every: int):
         stream = torch.cuda.current_stream(omega.device)
         sim.bind_stream(stream.cuda_stream)
-        sim.set_wetting(omega.detach().to("cpu", torch.float64).numpy())
+        om = omega.detach().to(torch.float64).contiguous()
+        sim.set_wetting_device(om.data_ptr())
         sim.init(C0)
         sim.forward_ckpt(n_steps, every)
-        C = torch.from_numpy(sim.read("C")).to(omega.device)
+        C = torch.empty(sim.n_nodes, dtype=torch.float64, device=omega.device)
+        sim.read_device("C", C.data_ptr())
         ctx.sim = sim
         ctx.run = sim.adjoint_run()
         return C

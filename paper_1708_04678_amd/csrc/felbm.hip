@@ -167,6 +167,7 @@ struct felbm_ctx {
   DiagRecord* hist = nullptr;  // ring of per-step reductions
   DiagRecord* diag_now = nullptr;
   int32_t* first_bad = nullptr;
+  int32_t* wet_flags = nullptr;  // [2] checks of felbm_set_wetting_device
   int64_t hist_cap = 16384;
   std::vector<double> host_omega;
   // internal orderings (see mesh_prep.hpp)
@@ -1194,6 +1195,7 @@ int felbm_upload_mesh(felbm_ctx* c, int64_t n_nodes, const double* xy, int64_t n
     TRY(upload(c, c->erev, erev));
     TRY(dalloc(c, &c->d_node_perm, N));
     TRY(upload(c, c->d_node_perm, m.node_perm));
+    TRY(dalloc(c, &c->wet_flags, 2));
     HIP_OK(c, hipStreamSynchronize(c->stream));
   }
   set_kernel_bytes(c);
@@ -1233,6 +1235,32 @@ int felbm_set_wetting(felbm_ctx* c, const double* omega_c) {
   }
   invalidate_adjoint(c);
   TRY(upload(c, c->bc, bc));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  return FELBM_OK;
+}
+
+int felbm_set_wetting_device(felbm_ctx* c, const double* omega_dev) {
+  if (!c) return FELBM_EINVAL;
+  if (!c->has_mesh) return fail(c, FELBM_ESTATE, "set_wetting_device: no mesh");
+  if (!omega_dev) return fail(c, FELBM_EINVAL, "set_wetting_device: null omega_c");
+  const double kappa = c->sp.kappa, beta = c->sp.beta;
+  const int N = (int)c->N, g1 = (N + BLOCK - 1) / BLOCK;
+  // validate first, so that a rejected call leaves the wetting field as it was
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->stream, c->wet_flags, 2, 0);
+  hipLaunchKernelGGL(k_wetting_check, dim3(g1), dim3(BLOCK), 0, c->stream, N, (const int*)c->d_node_perm,
+                     (const uint8_t*)c->is_wall, omega_dev, c->wet_flags);
+  HIP_OK(c, hipGetLastError());
+  int32_t flags[2] = {0, 0};
+  HIP_OK(c, hipMemcpyAsync(flags, c->wet_flags, sizeof flags, hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  if (flags[0]) return fail(c, FELBM_EINVAL, "set_wetting_device: non-finite value");
+  if (flags[1] && kappa <= 0.0)
+    return fail(c, FELBM_EINVAL, "set_wetting_device: a nonzero wetting potential needs kappa > 0");
+  invalidate_adjoint(c);
+  const double sq = flags[1] ? std::sqrt(2.0 * kappa * beta) : 0.0;
+  hipLaunchKernelGGL(k_wetting_bc, dim3(g1), dim3(BLOCK), 0, c->stream, N, (const int*)c->d_node_perm,
+                     (const uint8_t*)c->is_wall, omega_dev, sq, flags[1] ? kappa : 1.0, c->bc);
+  HIP_OK(c, hipGetLastError());
   HIP_OK(c, hipStreamSynchronize(c->stream));
   return FELBM_OK;
 }
@@ -1333,6 +1361,35 @@ int felbm_read(felbm_ctx* c, int32_t field, double* out) {
   for (int64_t k = 0; k < n; ++k) out[perm[k]] = host[k];
   if (field == FELBM_FIELD_RHO)
     for (int64_t i = 0; i < N; ++i) out[i] = out[i] * c->prm.rho_l + (1.0 - out[i]) * c->prm.rho_v;
+  return FELBM_OK;
+}
+
+int felbm_read_device(felbm_ctx* c, int32_t field, double* out_dev) {
+  if (!c) return FELBM_EINVAL;
+  if (!c->has_state) return fail(c, FELBM_ESTATE, "read_device: not initialised");
+  if (!out_dev) return fail(c, FELBM_EINVAL, "read_device: null output");
+  if (field < FELBM_FIELD_C || field > FELBM_FIELD_LAPC)
+    return fail(c, FELBM_EINVAL, "read_device: not a nodal field (element fields: felbm_read)");
+  TRY(enqueue_fields_any(c, false, false, nullptr, read_field_mode(c)));
+  const int N = (int)c->N, g1 = (N + BLOCK - 1) / BLOCK;
+  const double* src = nullptr;
+  double* tmp = nullptr;
+  switch (field) {
+    case FELBM_FIELD_C:
+    case FELBM_FIELD_RHO: src = c->Cn; break;
+    case FELBM_FIELD_MU: src = c->mu; break;
+    case FELBM_FIELD_LAPC: src = c->lapC; break;
+    default: {
+      const void* s = field == FELBM_FIELD_P ? c->pn : (field == FELBM_FIELD_UX ? c->uxn : c->uyn);
+      HIP_OK(c, hipMallocAsync((void**)&tmp, (size_t)N * 8, c->stream));
+      TRY(to_double(c, s, tmp, N));
+      src = tmp;
+    }
+  }
+  hipLaunchKernelGGL(k_field_to_caller, dim3(g1), dim3(BLOCK), 0, c->stream, N, (const int*)c->d_node_perm, src,
+                     out_dev, field == FELBM_FIELD_RHO ? 1 : 0, c->prm.rho_l, c->prm.rho_v);
+  HIP_OK(c, hipGetLastError());
+  if (tmp) HIP_OK(c, hipFreeAsync(tmp, c->stream));
   return FELBM_OK;
 }
 

@@ -1307,6 +1307,42 @@ __global__ void __launch_bounds__(BLOCK) k_init(int N, int Np, StepParams P, con
   if (Conserve<real>::on) rC[i] = c - sh;
 }
 
+// Wetting potential handed over in device memory (caller node order): flags[0]
+// is set if any value is non-finite, flags[1] if a wall node has a nonzero one.
+// Every thread that sets a flag stores the same value.
+__global__ void __launch_bounds__(BLOCK) k_wetting_check(int N, const int* __restrict__ node_perm,
+                                                        const uint8_t* __restrict__ is_wall,
+                                                        const double* __restrict__ omega, int32_t* __restrict__ flags) {
+  const int k = blockIdx.x * BLOCK + threadIdx.x;
+  if (k >= N) return;
+  const double v = omega[node_perm[k]];
+  if (!isfinite(v)) flags[0] = 1;
+  if (is_wall[k] && v != 0.0) flags[1] = 1;
+}
+
+// phi_c / kappa = Omega_c sqrt(2 kappa beta) / kappa at wall nodes (eq. bc2),
+// 0 elsewhere, in internal order; the same operations as the host path
+__global__ void __launch_bounds__(BLOCK) k_wetting_bc(int N, const int* __restrict__ node_perm,
+                                                     const uint8_t* __restrict__ is_wall,
+                                                     const double* __restrict__ omega, double sq, double kappa,
+                                                     double* __restrict__ bc) {
+  const int k = blockIdx.x * BLOCK + threadIdx.x;
+  if (k >= N) return;
+  const double v = omega[node_perm[k]];
+  bc[k] = (is_wall[k] && v != 0.0) ? __ddiv_rn(__dmul_rn(v, sq), kappa) : 0.0;
+}
+
+// a nodal field from internal to caller order; rho = C rho_l + (1 - C) rho_v
+// when to_rho is set (unfused, as on the host)
+__global__ void __launch_bounds__(BLOCK) k_field_to_caller(int N, const int* __restrict__ node_perm,
+                                                          const double* __restrict__ src, double* __restrict__ dst,
+                                                          int to_rho, double rho_l, double rho_v) {
+  const int k = blockIdx.x * BLOCK + threadIdx.x;
+  if (k >= N) return;
+  const double v = src[k];
+  dst[node_perm[k]] = to_rho ? __dadd_rn(__dmul_rn(v, rho_l), __dmul_rn(__dsub_rn(1.0, v), rho_v)) : v;
+}
+
 __global__ void k_fill_i32(int32_t* __restrict__ p, int n, int32_t v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;

@@ -54,10 +54,12 @@ _SIGNATURES = {
     "felbm_last_error": ([_P], ct.c_char_p),
     "felbm_upload_mesh": ([_P, ct.c_int64, _D, ct.c_int64, _I, ct.c_int64, _I, ct.c_double], ct.c_int),
     "felbm_set_wetting": ([_P, _D], ct.c_int),
+    "felbm_set_wetting_device": ([_P, _P], ct.c_int),
     "felbm_init": ([_P, _D, _D, _D], ct.c_int),
     "felbm_step": ([_P, ct.c_int64], ct.c_int),
     "felbm_step_async": ([_P, ct.c_int64], ct.c_int),
     "felbm_read": ([_P, ct.c_int32, _D], ct.c_int),
+    "felbm_read_device": ([_P, ct.c_int32, _P], ct.c_int),
     "felbm_read_populations": ([_P, _D], ct.c_int),
     "felbm_step_debug": ([_P, _D, _D, _D], ct.c_int),
     "felbm_set_band": ([_P, ct.c_double, ct.c_double, ct.c_double, ct.c_double], ct.c_int),
@@ -189,6 +191,10 @@ class Context:
         om = _f64(omega_c, (self.n_nodes,))
         self._check(self._lib.felbm_set_wetting(self._h, _dptr(om)))
 
+    def set_wetting_device(self, omega_dev_ptr):
+        """Device pointer (int) to N doubles, caller node order."""
+        self._check(self._lib.felbm_set_wetting_device(self._h, ct.c_void_p(omega_dev_ptr)))
+
     def init(self, C, u=None, p=None):
         C = _f64(C, (self.n_nodes,))
         u = None if u is None else _f64(u, (self.n_nodes, 2))
@@ -215,6 +221,11 @@ class Context:
         out = np.empty(self.n_tris if fid == FIELDS["LAPMU"] else self.n_nodes)
         self._check(self._lib.felbm_read(self._h, fid, _dptr(out)))
         return out
+
+    def read_device(self, field, out_dev_ptr):
+        """A nodal field into a device buffer of N doubles (caller order), queued on the bound stream."""
+        fid = FIELDS[field] if isinstance(field, str) else int(field)
+        self._check(self._lib.felbm_read_device(self._h, fid, ct.c_void_p(out_dev_ptr)))
 
     def read_populations(self):
         out = np.empty((18, self.n_nodes))
