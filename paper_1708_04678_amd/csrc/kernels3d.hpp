@@ -102,6 +102,47 @@ __device__ __forceinline__ void store_set(real* __restrict__ base, int i, int Np
   }
 }
 
+// the same for vectors touched once per launch (the right-hand side read by a
+// sweep at its own node, the new iterate): nontemporal accesses.  Used by the
+// FP32 sweeps only: they ran 2 % faster with them, the FP64 sweeps 1 % slower.
+template <typename real>
+struct NatV4;
+template <>
+struct NatV4<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct NatV4<double> {
+  typedef double type __attribute__((ext_vector_type(4)));
+};
+template <typename real>
+__device__ __forceinline__ void load_set_nt(const real* __restrict__ base, int j, int Np, real* v) {
+  using V = typename NatV4<real>::type;
+  const V* b4 = reinterpret_cast<const V*>(base);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    const V t = __builtin_nontemporal_load(b4 + (size_t)q * Np + j);
+    v[4 * q] = t.x;
+    v[4 * q + 1] = t.y;
+    v[4 * q + 2] = t.z;
+    v[4 * q + 3] = t.w;
+  }
+}
+template <typename real>
+__device__ __forceinline__ void store_set_nt(real* __restrict__ base, int i, int Np, const real* v) {
+  using V = typename NatV4<real>::type;
+  V* b4 = reinterpret_cast<V*>(base);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    V t;
+    t.x = v[4 * q];
+    t.y = v[4 * q + 1];
+    t.z = v[4 * q + 2];
+    t.w = q < 4 ? v[4 * q + 3] : (real)0;
+    __builtin_nontemporal_store(t, b4 + (size_t)q * Np + i);
+  }
+}
+
 constexpr int NRED3 = 6;  // same record as the 2-D reductions (band entries stay 0)
 
 // FP32 precision form: the composition is carried in FP64 beside the float
@@ -569,7 +610,8 @@ __global__ void __launch_bounds__(BLOCK) k3_sweep(int N, int Np, const int* __re
       for (int a = 0; a < Q; ++a) r[a] = v[a] + w * (v[a] - r[a]);
     } else {
       real fv[QS];
-      load_set(fs, i, Np, fv);
+      if constexpr (CONS) load_set_nt(fs, i, Np, fv);
+      else load_set(fs, i, Np, fv);
 #pragma unroll
       for (int a = 0; a < Q; ++a) r[a] = v[a] + w * (fv[a] - r[a]);
     }
@@ -582,7 +624,8 @@ __global__ void __launch_bounds__(BLOCK) k3_sweep(int N, int Np, const int* __re
     if (comp) rc = cs.fC[i];
   }
   if (MODE == 0 || MODE == 1) {
-    store_set(xout + off, i, Np, r);
+    if constexpr (CONS) store_set_nt(xout + off, i, Np, r);
+    else store_set(xout + off, i, Np, r);
     if (comp) cs.xCout[i] = rc;
     return;
   }
