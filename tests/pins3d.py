@@ -323,3 +323,39 @@ def force_moments_error() -> float:
     f0 = o.fields(g0, h0)
     e3 = abs(f0["Phi_g"] @ fo3.E - fo3.CS2 * f0["mu"][tet].mean(1)[:, None] * f0["gradC"]).max()
     return float(max(e1, e2, e3))
+
+
+def first_step_composition_error_3d(h: float, rho_l: float = 3.0, rho_v: float = 1.0, p0: float = 2e-3) -> float:
+    """Composition change over the first step from rest (u = 0, populations
+    at equilibrium) with mobility M = 0, as in 2-D.  The continuum equations of
+    Sec. II give dC/dt = -div(C u) and, with rho du/dt = -grad p + mu grad C at
+    rest, d2C/dt2 = div[(C / rho)(grad p - mu grad C)]; so over one step
+    dC = dt^2/2 d/dx[(C / rho)(p' - mu C')] + O(dt^3), which the h-scheme
+    carries only through the C/(rho c_s^2)(grad p - mu grad C) term of eq:H.
+    Layers C = 0.5 + 0.3 cos(k x), p = p0 sin(k x) along the periodic x axis of
+    an unjittered box (3 cells in y, walls at z = 0 and z = 6h with a neutral
+    wall); mu from the closed form 2 beta C (C - 1)(2C - 1) - kappa C''
+    (kappa = 1.5 sigma xi, beta = 12 sigma / xi).  Returns the max error at the
+    nodes two or more layers from the walls, relative to the max exact change."""
+    L = 32.0
+    nx, ny, nz = int(round(L / h)), 3, 6
+    mesh = tet_box_mesh(L, ny * h, nz * h, nx, ny, nz, seed=[5], jitter=0.0)
+    phys = make_physics(sigma=0.01, m_rho=rho_l / rho_v, m_nu=1, dt=0.1, mobility=0.0, rho_l=rho_l)
+    o = fo3.Oracle3D(mesh, phys, np.zeros(mesh.n_nodes))
+    k = 2 * np.pi / L
+    x, z = mesh.xyz[:, 0], mesh.xyz[:, 2]
+    g, hh = o.init_state(0.5 + 0.3 * np.cos(k * x), p=p0 * np.sin(k * x))
+    g1, h1 = o.step(g, hh)
+    dC = h1.sum(1) - hh.sum(1)
+    kap, bet = 1.5 * phys.sigma * phys.xi, 12.0 * phys.sigma / phys.xi
+
+    def flux(xx):
+        C = 0.5 + 0.3 * np.cos(k * xx)
+        Cp, Cpp = -0.3 * k * np.sin(k * xx), -0.3 * k * k * np.cos(k * xx)
+        mu = 2 * bet * C * (C - 1) * (2 * C - 1) - kap * Cpp
+        return (C / (C * rho_l + (1 - C) * rho_v)) * (p0 * k * np.cos(k * xx) - mu * Cp)
+
+    eps = 1e-5
+    exact = 0.5 * phys.dt ** 2 * (flux(x + eps) - flux(x - eps)) / (2 * eps)
+    inner = (z > 1.5 * h) & (z < (nz - 1.5) * h)
+    return float(abs(dC[inner] - exact[inner]).max() / abs(exact[inner]).max())

@@ -55,6 +55,34 @@ def forces_no_mobility(prm, C, rho, u, mu, gradC, gradp, gradrho, lapmu):
     return _pf(prm, C, rho, u, mu, gradC, gradp, gradrho, 0 * lapmu)
 
 
+def _h_force(eq_h_term):
+    """point_forces with the X vector of eq:H replaced by eq_h_term(C, rho, mu, gradC, gradp)."""
+    def forces(prm, C, rho, u, mu, gradC, gradp, gradrho, lapmu):
+        Pg, _ = _pf(prm, C, rho, u, mu, gradC, gradp, gradrho, lapmu)
+        Gu = fo3.gamma(u)
+        X = eq_h_term(C, rho, mu, gradC, gradp)
+        return Pg, (fo3.edot(X) - np.sum(u * X, axis=1)[:, None]) * Gu + prm.mobility * lapmu[:, None] * Gu
+    return forces
+
+
+eqH_term_deleted = _h_force(lambda C, rho, mu, gC, gp: gC)
+eqH_mu_sign = _h_force(lambda C, rho, mu, gC, gp: gC - (C / (rho * fo3.CS2))[:, None] * (gp + mu[:, None] * gC))
+eqH_rho_one = _h_force(lambda C, rho, mu, gC, gp: gC - (C / fo3.CS2)[:, None] * (gp - mu[:, None] * gC))
+
+
+def gamma_quadratic_doubled(u):
+    eu = fo3.edot(u)
+    uu = np.sum(u * u, axis=1)[:, None]
+    return fo3.W * (1.0 + eu / fo3.CS2 + (eu * eu - fo3.CS2 * uu) / (fo3.CS2 * fo3.CS2))
+
+
+def g_eq_quadratic_doubled(C, p, rho, u):
+    g, h = _eq(C, p, rho, u)
+    eu = fo3.edot(u)
+    uu = np.sum(u * u, axis=1)[:, None]
+    return g + fo3.W * rho[:, None] * fo3.CS2 * (eu * eu - fo3.CS2 * uu) / (2.0 * fo3.CS2 * fo3.CS2), h
+
+
 _W = fo3.W.copy()
 
 MUTATIONS = [
@@ -67,6 +95,14 @@ MUTATIONS = [
      lambda: pins3d.wall_linear_laplacian_error() > 1e-6),
     ("printed M10 sign", "rhs", rhs_printed_sign, lambda: pins3d.static_balance_drift() > 1e-8),
     ("dropped mobility term", "point_forces", forces_no_mobility, lambda: pins3d.force_moments_error() > 1e-8),
+    ("eq:H pressure/mu term deleted", "point_forces", eqH_term_deleted,
+     lambda: pins3d.first_step_composition_error_3d(0.5) > 0.05),
+    ("eq:H mu grad C sign", "point_forces", eqH_mu_sign, lambda: pins3d.first_step_composition_error_3d(0.5) > 0.05),
+    ("eq:H rho -> 1", "point_forces", eqH_rho_one, lambda: pins3d.first_step_composition_error_3d(0.5) > 0.05),
+    ("Gamma quadratic coefficient doubled", "gamma", gamma_quadratic_doubled,
+     lambda: pins3d.lattice_identities_error() > 1e-4),
+    ("g_eq quadratic coefficient doubled", "equilibria", g_eq_quadratic_doubled,
+     lambda: pins3d.lattice_identities_error() > 1e-4),
 ]
 
 

@@ -61,3 +61,11 @@ def test_laplace_pressure_jump_3d():
     assert abs(cont - 1.0) < 0.01                  # the continuum integral is 2 sigma / R here
     assert abs((4.0 * q2 - q1) / 3.0 - 1.0) < 0.05  # Richardson-extrapolated discrete value
     assert (1.0 - q1) / (1.0 - q2) > 2.5            # converging at about second order
+
+
+def test_first_step_composition_flux_of_eq_H_3d():
+    # from rest with M = 0 the composition changes by dt^2/2 div[(C/rho)(grad p - mu grad C)],
+    # which the h-scheme carries only through the C/(rho c_s^2)(grad p - mu grad C) term of eq:H
+    e1, e2 = pins3d.first_step_composition_error_3d(1.0), pins3d.first_step_composition_error_3d(0.5)
+    assert e2 < 0.01
+    assert e1 / e2 > 3.0  # second order in h
