@@ -83,6 +83,27 @@ def g_eq_quadratic_doubled(C, p, rho, u):
     return g + fo3.W * rho[:, None] * fo3.CS2 * (eu * eu - fo3.CS2 * uu) / (2.0 * fo3.CS2 * fo3.CS2), h
 
 
+_moments, _collide = fo3.moments, fo3.collide
+
+
+def tau_arithmetic(C, prm):
+    return C * prm.tau_l + (1.0 - C) * prm.tau_v
+
+
+def velocity_without_density(g, h, prm):
+    C, p, rho, u = _moments(g, h, prm)
+    return C, p, rho, u * rho[:, None]
+
+
+def collide_without_half(psi, psi_eq, tau):
+    return psi - (psi - psi_eq) / tau[:, None]
+
+
+def _mixture_off():
+    r = pins3d.mixture_viscosity_ratio()
+    return not 1.0 < r < 1.2
+
+
 _W = fo3.W.copy()
 
 MUTATIONS = [
@@ -103,6 +124,9 @@ MUTATIONS = [
      lambda: pins3d.lattice_identities_error() > 1e-4),
     ("g_eq quadratic coefficient doubled", "equilibria", g_eq_quadratic_doubled,
      lambda: pins3d.lattice_identities_error() > 1e-4),
+    ("arithmetic relaxation-time mixing", "relaxation_time", tau_arithmetic, _mixture_off),
+    ("velocity moment without 1/rho", "moments", velocity_without_density, _mixture_off),
+    ("collision rate 1/tau", "collide", collide_without_half, lambda: pins3d.shear_wave_viscosity_ratio() < 0.98),
 ]
 
 

@@ -69,3 +69,11 @@ def test_first_step_composition_flux_of_eq_H_3d():
     e1, e2 = pins3d.first_step_composition_error_3d(1.0), pins3d.first_step_composition_error_3d(0.5)
     assert e2 < 0.01
     assert e1 / e2 > 3.0  # second order in h
+
+
+def test_mixture_viscosity_3d():
+    # a uniform mixture C = 1/2 shears with nu = c_s^2 tau dt at the relaxation time of
+    # Sec. II.A (harmonic in C) and at density (rho_l + rho_v)/2
+    r1, r2 = pins3d.mixture_viscosity_ratio(H=12), pins3d.mixture_viscosity_ratio(H=24, n_steps=600)
+    assert r1 > r2 > 1.0                      # converging from above (1.10, 1.05; 1.02 at H = 48)
+    assert abs(2.0 * r2 - r1 - 1.0) < 0.02    # first-order extrapolation to 1
