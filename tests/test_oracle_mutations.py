@@ -212,6 +212,18 @@ def init_without_half_force(self, C, u=None, p=None):
     return fo.wall_operator(self.geo, g), fo.wall_operator(self.geo, h)
 
 
+_moments, _tau = fo.moments, fo.relaxation_time
+
+
+def velocity_without_density(g, h, prm):
+    C, p, rho, u = _moments(g, h, prm)
+    return C, p, rho, u * rho[:, None]
+
+
+def tau_arithmetic(C, prm):
+    return C * prm.tau_l + (1.0 - C) * prm.tau_v
+
+
 MUTATIONS = [
     ("printed M10 sign", "rhs", rhs_printed_sign, lambda: pins.static_balance_drift() > 1e-8),
     ("dropped D term", "rhs", rhs_no_D, lambda: pins.advection_error() > 0.05),
@@ -253,6 +265,10 @@ MUTATIONS = [
      lambda: pins.collision_step_moment_error() > 1e-8),
     ("collision-step initial state without -dt/2 F", "Oracle.init_state", init_without_half_force,
      lambda: pins.first_step_composition_error(0.25, force_scheme="nodal_collide") > 0.5),
+    ("velocity moment without 1/rho", "moments", velocity_without_density,
+     lambda: pins.collision_conservation_error() > 1e-8),
+    ("arithmetic relaxation-time mixing", "relaxation_time", tau_arithmetic,
+     lambda: pins.relaxation_time_cases() > 1e-8),
 ]
 
 
