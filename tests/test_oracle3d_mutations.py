@@ -51,6 +51,25 @@ def rhs_printed_sign(mat, dt, psi_hat, Phi):
     return out + np.stack([-dt * (mat.M10 @ Phi[:, a]) + dt * dt * (mat.Ka[a] @ Phi[:, a]) for a in range(fo3.Q)], 1)
 
 
+def rhs_no_D(mat, dt, psi_hat, Phi):
+    return np.stack([-dt * (mat.Ca[a] @ psi_hat[:, a]) + dt * (mat.M10 @ Phi[:, a]) + dt * dt * (mat.Ka[a] @ Phi[:, a])
+                     for a in range(fo3.Q)], 1)
+
+
+def rhs_K_sign(mat, dt, psi_hat, Phi):
+    return np.stack([-dt * (mat.Ca[a] @ psi_hat[:, a]) - dt * dt * (mat.Da[a] @ psi_hat[:, a])
+                     + dt * (mat.M10 @ Phi[:, a]) - dt * dt * (mat.Ka[a] @ Phi[:, a]) for a in range(fo3.Q)], 1)
+
+
+def rhs_C_transposed(mat, dt, psi_hat, Phi):
+    return np.stack([-dt * (mat.Ca[a].T @ psi_hat[:, a]) - dt * dt * (mat.Da[a] @ psi_hat[:, a])
+                     + dt * (mat.M10 @ Phi[:, a]) + dt * dt * (mat.Ka[a] @ Phi[:, a]) for a in range(fo3.Q)], 1)
+
+
+def wall_flux_flipped(Cf, rf, area):
+    return -_wall(Cf, rf, area)
+
+
 def forces_no_mobility(prm, C, rho, u, mu, gradC, gradp, gradrho, lapmu):
     return _pf(prm, C, rho, u, mu, gradC, gradp, gradrho, 0 * lapmu)
 
@@ -127,6 +146,10 @@ MUTATIONS = [
     ("arithmetic relaxation-time mixing", "relaxation_time", tau_arithmetic, _mixture_off),
     ("velocity moment without 1/rho", "moments", velocity_without_density, _mixture_off),
     ("collision rate 1/tau", "collide", collide_without_half, lambda: pins3d.shear_wave_viscosity_ratio() < 0.98),
+    ("dropped dt^2 D term", "rhs", rhs_no_D, lambda: pins3d.static_balance_drift() > 1e-8),
+    ("K sign", "rhs", rhs_K_sign, lambda: pins3d.static_balance_drift() > 1e-8),
+    ("C transposed", "rhs", rhs_C_transposed, lambda: pins3d.static_balance_drift() > 1e-8),
+    ("wetting flux sign", "wall_flux", wall_flux_flipped, lambda: pins3d.wall_linear_laplacian_error() > 1e-6),
 ]
 
 
