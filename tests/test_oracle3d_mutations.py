@@ -118,6 +118,22 @@ def collide_without_half(psi, psi_eq, tau):
     return psi - (psi - psi_eq) / tau[:, None]
 
 
+_diagnostics = fo3.Oracle3D.diagnostics
+
+
+def diagnostics_ke_doubled(self, g, h):
+    d = _diagnostics(self, g, h)
+    d["mean_ke"] *= 2.0
+    return d
+
+
+def diagnostics_ke_without_rho(self, g, h):
+    d = _diagnostics(self, g, h)
+    C, p, rho, u = fo3.moments(g, h, self.prm)
+    d["mean_ke"] = float(0.5 * np.sum(u * u) / self.geo.N)
+    return d
+
+
 def _mixture_off():
     r = pins3d.mixture_viscosity_ratio()
     return not 1.0 < r < 1.2
@@ -150,12 +166,16 @@ MUTATIONS = [
     ("K sign", "rhs", rhs_K_sign, lambda: pins3d.static_balance_drift() > 1e-8),
     ("C transposed", "rhs", rhs_C_transposed, lambda: pins3d.static_balance_drift() > 1e-8),
     ("wetting flux sign", "wall_flux", wall_flux_flipped, lambda: pins3d.wall_linear_laplacian_error() > 1e-6),
+    ("<T> doubled", "Oracle3D.diagnostics", diagnostics_ke_doubled, lambda: pins3d.diagnostics_error_3d() > 1e-6),
+    ("<T> without rho", "Oracle3D.diagnostics", diagnostics_ke_without_rho,
+     lambda: pins3d.diagnostics_error_3d() > 1e-6),
 ]
 
 
 @pytest.mark.parametrize("name,attr,fn,caught", MUTATIONS, ids=[m[0] for m in MUTATIONS])
 def test_pin_catches_planted_mistake_3d(monkeypatch, name, attr, fn, caught):
-    monkeypatch.setattr(fo3, attr, fn)
+    owner, _, leaf = attr.rpartition(".")
+    monkeypatch.setattr(getattr(fo3, owner) if owner else fo3, leaf, fn)
     assert caught(), f"no pin caught the planted mistake: {name}"
 
 

@@ -77,3 +77,8 @@ def test_mixture_viscosity_3d():
     r1, r2 = pins3d.mixture_viscosity_ratio(H=12), pins3d.mixture_viscosity_ratio(H=24, n_steps=600)
     assert r1 > r2 > 1.0                      # converging from above (1.10, 1.05; 1.02 at H = 48)
     assert abs(2.0 * r2 - r1 - 1.0) < 0.02    # first-order extrapolation to 1
+
+
+def test_diagnostics_hand_count_3d():
+    # mass, <T> and max |u> of a state whose velocities and density are set node by node
+    assert pins3d.diagnostics_error_3d() < 1e-12
